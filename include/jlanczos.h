@@ -1,0 +1,159 @@
+/*
+ * jlanczos.h -- C ABI of the MI355X (gfx950) thick-restart Lanczos solver for
+ * Hermitian J-symmetric eigenproblems (TRLAN-JSYM, Ishikawa & Sogabe,
+ * arXiv:2001.07428).
+ *
+ * Problem (Sec. 1): A in C^{n x n} Hermitian with J A J^-1 = A^T, J real,
+ * J^T = -J = J^-1 (eq. symmetry).  With the canonical J = [[0, -I], [I, 0]]
+ * (n even, J acts as [a; b] -> [-b; a]) A has the block form
+ * A = [[A11, A12], [A12^H, A11^T]], A11^H = A11, A12^T = -A12 (eq. blockform).
+ * Every eigenvalue is doubly degenerate; the partner of an eigenvector x is
+ * y = J x^* (eq. pairev).  The solver runs the Lanczos iteration inside one of
+ * the two J-split Krylov subspaces (Algorithms 1 and 2) and returns the nev
+ * lowest (or largest) distinct pair eigenvalues with one eigenvector each.
+ *
+ * Conventions for every entry point
+ *  - Return value: JL_OK (0) on success, a negative jl_status on error, a
+ *    positive jl_status for a result that is valid but qualified.  On error
+ *    the message is available from jl_last_error(ctx).
+ *  - Complex numbers are interleaved (re, im).  JL_C64 = two floats,
+ *    JL_C128 = two doubles.  The operator dtype also selects the solver
+ *    precision: JL_C64 stores and applies the operator and the Lanczos basis
+ *    in FP32 complex, while the reorthogonalisation inner products, norms,
+ *    residual checks and the Ritz eigenproblem are FP64; JL_C128 is FP64
+ *    throughout.
+ *  - Vectors are [top; bottom] with halves of length n/2 (Sec. 1, the block
+ *    form); for the stencil each half is site-major (x0 slowest, x3
+ *    fastest) with the internal index fastest.  Blocks of vectors are
+ *    column-major with a leading dimension in elements.
+ *  - "device" pointers are HIP device memory on the context's device;
+ *    "host" pointers are ordinary host memory.  The library never takes
+ *    ownership of caller buffers; operator data are borrowed for the
+ *    lifetime of the operator, other buffers for the duration of the call.
+ *  - All GPU work is ordered on the context's stream.  Calls that return
+ *    host results (jl_solve) synchronise that stream before returning.
+ *  - The library allocates no device memory: the solver's scratch space is
+ *    the caller's workspace (size from jl_workspace_bytes).
+ */
+#ifndef JLANCZOS_H
+#define JLANCZOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t jl_status;
+enum {
+  JL_OK = 0,
+  JL_EINVAL = -1,          /* invalid argument (message says which)        */
+  JL_EHIP = -2,            /* a HIP runtime call failed                    */
+  JL_ENOMEM = -3,          /* workspace smaller than jl_workspace_bytes    */
+  JL_EUNSUPPORTED = -4,    /* valid request this build does not implement  */
+  JL_NOT_CONVERGED = 1,    /* max_cycles reached; first stats.icnv valid   */
+  JL_BREAKDOWN = 2         /* invariant subspace reached before nev pairs  */
+};
+
+typedef enum { JL_C64 = 1, JL_C128 = 2 } jl_dtype;
+typedef enum { JL_LOWEST = 0, JL_LARGEST = 1 } jl_which;
+
+typedef struct jl_ctx_s* jl_ctx;
+typedef struct jl_op_s* jl_op;
+
+/* Context on HIP device `device`, ordering all work on `hip_stream`
+ * (a hipStream_t, borrowed; NULL = the device's null stream). */
+jl_status jl_ctx_create(jl_ctx* out, int32_t device, void* hip_stream);
+jl_status jl_ctx_destroy(jl_ctx ctx);
+/* Last error message of `ctx` (or of the calling thread when ctx is NULL). */
+const char* jl_last_error(jl_ctx ctx);
+const char* jl_status_string(jl_status s);
+
+/* Dense operator from the blocks of eq. (blockform).  A11 and A12 are device
+ * pointers to h x h row-major complex matrices (h = n/2) with row stride
+ * `ld` elements; A11 must be Hermitian and A12 antisymmetric (not checked).
+ * Errors: JL_EINVAL for odd or non-positive n, ld < h, NULL pointers. */
+jl_status jl_op_create_dense(jl_ctx ctx, int64_t n, const void* A11, const void* A12,
+                             int64_t ld, jl_dtype dtype, jl_op* out);
+
+/* Matrix-free 4D periodic J-stencil on an L[0] x L[1] x L[2] x L[3] lattice
+ * with internal dimension d (n = 2 * V * d, V = prod L):
+ *   A11 = diag I - sum_mu (U_mu T_mu + (U_mu T_mu)^H),
+ *   A12 = a12_scale sum_mu (B_mu T_mu - (B_mu T_mu)^T),
+ * (T_mu a)(x) = a(x + mu_hat) periodic.  U: device [4][V][d][d] row-major
+ * complex links (unitarity not required); B: device [4][d][d] (b_per_site =
+ * 0) or [4][V][d][d] (b_per_site = 1).  The result is Hermitian J-symmetric
+ * by construction.  Errors: JL_EINVAL for L[i] < 2 or NULL pointers;
+ * JL_EUNSUPPORTED for d != 4. */
+jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double diag,
+                               double a12_scale, const void* U, const void* B,
+                               int32_t b_per_site, jl_dtype dtype, jl_op* out);
+jl_status jl_op_destroy(jl_op op);
+/* Dimension n of the operator. */
+jl_status jl_op_dim(jl_op op, int64_t* n);
+
+/* y(:, r) = A x(:, r) for r < nrhs; x, y device, column-major with leading
+ * dimension n (element type = operator dtype, accumulation in that
+ * precision).  x and y must not overlap. */
+jl_status jl_op_apply(jl_op op, const void* x, void* y, int32_t nrhs);
+
+typedef struct {
+  int32_t nev;          /* number of desired pairs (1 <= nev <= mwin)          */
+  int32_t m;            /* maximum Krylov dimension (mwin < m <= n/2)          */
+  int32_t mwin;         /* restart window: k = min(icnv + mwin, m - 1)         */
+  int32_t which;        /* jl_which                                            */
+  double tol;           /* absolute residual tolerance ||A x - lambda x|| < tol */
+  int32_t max_cycles;   /* outer-iteration cap (<= 0: 10000)                   */
+  int32_t max_passes;   /* reorthogonalisation passes per step cap (<= 0: 16)  */
+  int32_t timing;       /* nonzero: time each kernel class with HIP events     */
+  int32_t trace_cap;    /* record alpha_j, beta_j of the first trace_cap steps */
+  double* trace_ab;     /* host [2 * trace_cap]: alpha then beta (may be NULL) */
+} jl_params;
+
+typedef struct {
+  int32_t cycles;       /* outer iterations N_conv                              */
+  int32_t n_mv;         /* Lanczos matvecs N_MV (residual checks excluded)      */
+  int32_t n_resid;      /* operator applies spent on true-residual checks       */
+  int32_t gs_passes;    /* reorthogonalisation passes over all steps            */
+  int32_t icnv;         /* converged pairs at return                            */
+  int32_t status;       /* same as the return value of jl_solve                 */
+  /* Per kernel class (only with params.timing): accumulated GPU time [s],
+   * launch count and algorithmic bytes (or flops for the GEMM). */
+  double t_total;       /* wall time of jl_solve [s] (always set)               */
+  double t_matvec, t_dots, t_update, t_gemm, t_ritz, t_resid;
+  int64_t n_matvec_launch, n_dots_launch, n_update_launch, n_gemm_launch;
+  double bytes_matvec, bytes_dots, bytes_update, flops_gemm;
+} jl_stats;
+
+/* Workspace bytes jl_solve needs for `op` and `p`. */
+jl_status jl_workspace_bytes(jl_op op, const jl_params* p, size_t* bytes);
+
+/* Thick-restart J-Lanczos (Algorithm 1 with Algorithm 2 as its inner step).
+ *  v1      device start vector (n, op dtype) or NULL for the all-ones vector
+ *          the paper uses; it is normalised internally.
+ *  ws      device workspace of ws_bytes >= jl_workspace_bytes.
+ *  evals   host [nev]: pair eigenvalues in the desired order.
+ *  X       device n x nev (leading dimension ldx >= n), op dtype: one unit
+ *          eigenvector per pair; the partners are J X^* (jl_pair_vectors).
+ *  res     host [nev]: true residual norms ||A x_i - lambda_i x_i|| (FP64).
+ *  stats   host, may be NULL.
+ * Returns JL_OK when all nev pairs converged, JL_NOT_CONVERGED after
+ * max_cycles (the first stats.icnv entries are converged), JL_BREAKDOWN when
+ * the Krylov space became invariant before nev pairs converged (converged
+ * entries first).  Errors: JL_EINVAL for parameters outside the ranges
+ * above, JL_ENOMEM for a short workspace, JL_EHIP for runtime failures. */
+jl_status jl_solve(jl_op op, const jl_params* p, const void* v1, void* ws, size_t ws_bytes,
+                   double* evals, void* X, int64_t ldx, double* res, jl_stats* stats);
+
+/* Partner vectors Y = J X^* = [-conj(X_bottom); conj(X_top)] (eq. pairev) for
+ * k columns; X, Y device, leading dimensions ldx, ldy >= n; may alias only if
+ * X == Y and ldx == ldy. */
+jl_status jl_pair_vectors(jl_ctx ctx, int64_t n, int32_t k, jl_dtype dtype, const void* X,
+                          int64_t ldx, void* Y, int64_t ldy);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JLANCZOS_H */

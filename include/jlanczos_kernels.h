@@ -1,0 +1,54 @@
+/*
+ * jlanczos_kernels.h -- the individual steps of the J-restricted Lanczos
+ * iteration as C-ABI calls, for callers that assemble their own iteration and
+ * for step-by-step parity checks.  Conventions (status codes, dtypes, vector
+ * layout, streams, device/host pointers, no device allocation) are those of
+ * jlanczos.h.  Scratch space comes from the caller; its size from the
+ * matching *_workspace_bytes call.
+ */
+#ifndef JLANCZOS_KERNELS_H
+#define JLANCZOS_KERNELS_H
+
+#include "jlanczos.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One pass of the J-restricted Gram-Schmidt of Alg. 2 in block form:
+ *   c_v = V^H u,  c_w = W^H u  (W = J V^*, never stored),
+ *   u  <- u - V c_v - W c_w,
+ * against the ncol columns of V (device, n x ncol, leading dimension ldv,
+ * dtype).  u (device, n) is updated in place.  coef (device, FP64 [4*ncol+2])
+ * receives per column (Re c_v, Im c_v, Re c_w, Im c_w), then ||u||^2 before
+ * the pass at [4*ncol] and ||u||^2 after it at [4*ncol+1].  Inner products
+ * and norms are accumulated in FP64.  ncol may be 0 (norm only).
+ * Errors: JL_EINVAL (odd n, ncol < 0 or > 2047, ldv < n, NULL), JL_ENOMEM. */
+jl_status jl_reorth_pass_workspace_bytes(int64_t n, int32_t ncol, size_t* bytes);
+jl_status jl_reorth_pass(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t ncol, const void* V,
+                         int64_t ldv, void* u, double* coef, void* ws, size_t ws_bytes);
+
+/* Rayleigh-Ritz step of Alg. 1: T = Z diag(lam) Z^T for a real symmetric
+ * m x m FP64 matrix T (device, column-major, leading dimension m), with the
+ * eigenpairs sorted ascending (which = JL_LOWEST) or descending
+ * (JL_LARGEST).  lam (device, m) and Z (device, m x m column-major) are FP64.
+ * Errors: JL_EINVAL (m < 1, NULL), JL_ENOMEM. */
+jl_status jl_ritz_workspace_bytes(int32_t m, size_t* bytes);
+jl_status jl_ritz(jl_ctx ctx, int32_t m, const double* T, int32_t which, double* lam, double* Z,
+                  void* ws, size_t ws_bytes);
+
+/* Thick-restart basis update of Alg. 1 (V_m := V_m Z_m, first k columns):
+ * Y = V Z with V (device, n x m complex, leading dimension ldv, dtype), Z
+ * (device, m x k real column-major, leading dimension ldz, FP32 for JL_C64,
+ * FP64 for JL_C128) and Y (device, n x k, leading dimension ldy).  Y must not
+ * overlap V.  ldv and ldy must be even (16-byte aligned columns).
+ * Errors: JL_EINVAL. */
+jl_status jl_basis_update(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t m, int32_t k,
+                          const void* V, int64_t ldv, const void* Z, int64_t ldz, void* Y,
+                          int64_t ldy);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JLANCZOS_KERNELS_H */

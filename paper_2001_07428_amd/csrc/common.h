@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace jl {
+
+// Interleaved complex of storage type S.
+template <typename S> struct cplx_t;
+template <> struct cplx_t<float> { using type = float2; };
+template <> struct cplx_t<double> { using type = double2; };
+template <typename S> using cplx = typename cplx_t<S>::type;
+
+// 16-byte vector of storage type S (two FP32 complex or one FP64 complex).
+template <typename S> struct vec16_t;
+template <> struct vec16_t<float> { using type = float4; };
+template <> struct vec16_t<double> { using type = double2; };
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- launchers
+// Every launcher enqueues on `st` and returns the launch error (if any).
+
+// Stencil operator data (d = 4).  U: [4][V][4][4], B: [4][4][4] or [4][V][4][4].
+template <typename S> struct StencilArgs {
+  const cplx<S>* U;
+  const cplx<S>* B;
+  int32_t L[4];
+  int64_t V;
+  int b_per_site;
+  double diag;
+  double scale;
+};
+
+// y = A x for nrhs columns (ld = n), compute type = S.
+template <typename S>
+hipError_t launch_stencil_apply(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
+                                int nrhs, hipStream_t st);
+// Per-block partial sums of ||A x_c - lam_c x_c||^2 (FP64 compute) for ncols
+// columns x_c = X + cols[c]*ldx (cols, lam on the device); partial layout
+// [blk][c]; *nblk = blocks per column.
+template <typename S>
+hipError_t launch_stencil_resid(const StencilArgs<S>& a, const cplx<S>* X, int64_t ldx,
+                                const int* cols, const double* lam, int ncols, double* partial,
+                                int* nblk, hipStream_t st);
+int stencil_resid_blocks(int64_t V);
+
+// Dense operator: A11, A12 row-major h x h with row stride ld.
+template <typename S> struct DenseArgs {
+  const cplx<S>* A11;
+  const cplx<S>* A12;
+  int64_t h;
+  int64_t ld;
+};
+template <typename S>
+hipError_t launch_dense_apply(const DenseArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ldv,
+                              int nrhs, hipStream_t st);
+template <typename S>
+hipError_t launch_dense_resid(const DenseArgs<S>& a, const cplx<S>* X, int64_t ldx,
+                              const int* cols, const double* lam, int ncols, double* partial,
+                              int* nblk, hipStream_t st);
+int dense_resid_blocks(int64_t h);
+
+// ------------------------------------------------------- reorthogonalisation
+// Basis V: ncol columns of length n = 2h, column stride ldv.
+// dots: partial[blk][4*ncol + 1] = per block (Re, Im of v_i^H u, Re, Im of
+// w_i^H u) for each column, then ||u||^2.
+int reorth_dots_blocks(int64_t h);     // partial rows written by dots
+int reorth_update_blocks(int64_t h);   // partial entries written by update
+constexpr int kReorthMaxCols = 2048;   // largest basis dots supports
+template <typename S>
+hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, const cplx<S>* u, int64_t h,
+                              double* partial, int nblk, hipStream_t st);
+// update: u -= V c_v + W c_w (W = J V^*), coef = [4*ncol] FP64 (Re cv, Im cv,
+// Re cw, Im cw per column); partial[blk] = ||u_new||^2 per block.
+template <typename S>
+hipError_t launch_reorth_update(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
+                                const double* coef, double* partial, int nblk, hipStream_t st);
+// out[c] = sum_b partial[b * stride + c] for c < ncols (deterministic order).
+hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int ncols, double* out,
+                              hipStream_t st);
+// u *= scale (n complex).
+template <typename S>
+hipError_t launch_scale(cplx<S>* u, int64_t n, double scale, hipStream_t st);
+// fill with a constant real value (n complex).
+template <typename S>
+hipError_t launch_fill(cplx<S>* u, int64_t n, double value, hipStream_t st);
+// Y = J X^* for k columns.
+template <typename S>
+hipError_t launch_pair(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t ldy, int64_t h, int k,
+                       hipStream_t st);
+// copy k columns of length n between column-major blocks.
+template <typename S>
+hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t ldy, int64_t n,
+                            int k, hipStream_t st);
+
+// ------------------------------------------------------------ restart GEMM
+// C (M x N, ldc) = A (M x K, lda) * B (K x N, ldb), real, column-major.
+template <typename S>
+hipError_t launch_gemm_nn(const S* A, int64_t lda, const S* B, int64_t ldb, S* C, int64_t ldc,
+                          int64_t M, int N, int K, hipStream_t st);
+
+// ------------------------------------------------------- Ritz eigenproblem
+// Symmetric eigen-decomposition of an m x m FP64 matrix by parallel cyclic
+// Jacobi (one launch per round).  mp = m rounded up to even.
+struct EigWork {
+  double* A[2];   // (mp x mp) ping-pong; eigenvalues end on the diagonal
+  double* Z;      // (mp x mp) eigenvectors (columns), updated in place
+  double* off;    // [1] off-diagonal sum of squares
+};
+size_t eig_work_doubles(int m);
+int eig_small_max();   // largest mp handled by launch_eig_small
+// A[0] = T (m x m col-major, ldt) padded; Z = I.
+hipError_t launch_eig_init(const double* T, int ldt, int m, EigWork w, hipStream_t st);
+// Round r of a sweep: reads A[cur], writes A[1-cur], updates Z.
+hipError_t launch_eig_round(int m, EigWork w, int cur, int r, hipStream_t st);
+// off[0] = sum of squares of the off-diagonal entries of A[cur].
+hipError_t launch_eig_offnorm(int m, EigWork w, int cur, hipStream_t st);
+// Small problems: all sweeps in one workgroup; lam[m], Z (m x m, ldz).
+hipError_t launch_eig_small(const double* T, int ldt, int m, double* lam, double* Z, int ldz,
+                            int max_sweeps, hipStream_t st);
+// Sort: perm[r] = index of the r-th desired Ritz value (ascending unless
+// descending), with lam_i = lam[i * lstride]; then lam_s[r], Zs[:, r] (FP64,
+// m rows), Zc[:, r] (storage type, r < kcols), zlast[r] = Zs[m-1, r].
+template <typename S>
+hipError_t launch_ritz_sort(int m, const double* lam, int64_t lstride, const double* Z, int ldz,
+                            int descending, int kcols, int* perm, double* lam_s, double* Zs, S* Zc,
+                            double* zlast, hipStream_t st);
+
+}  // namespace jl

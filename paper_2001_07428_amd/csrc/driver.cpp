@@ -1,0 +1,723 @@
+// Host driver and C ABI of the J-symmetric thick-restart Lanczos solver.
+//
+// The control flow is Algorithm 1 (outer thick-restart loop) with Algorithm 2
+// (the J-restricted Lanczos steps) as its inner loop; every vector operation
+// is a kernel on the context's stream and the host only handles the m x m
+// projected matrix bookkeeping and a few scalars per step:
+//   - alpha_j and the norm b0 after the alpha step (read after the first
+//     inner-product pass), and the norm b1 after each reorthogonalisation
+//     pass (the sqrt(2) test of Alg. 2 is taken on the host);
+//   - once per cycle the sorted Ritz values, the last row of Z and the true
+//     residuals of the candidates.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+using namespace jl;
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+enum OpKind { OP_DENSE = 1, OP_STENCIL = 2 };
+
+}  // namespace
+
+struct jl_op_s {
+  jl_ctx ctx = nullptr;
+  OpKind kind = OP_DENSE;
+  jl_dtype dtype = JL_C128;
+  int64_t n = 0;
+  StencilArgs<float> sf{};
+  StencilArgs<double> sd{};
+  DenseArgs<float> df{};
+  DenseArgs<double> dd{};
+};
+
+namespace jl {
+
+jl_status set_err(jl_ctx ctx, jl_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  g_thread_err = buf;
+  return code;
+}
+
+size_t ritz_scratch_doubles(int m) {
+  return eig_work_doubles(m) + (size_t)m + (size_t)m * m + (size_t)m;   // eig, lam, Z, perm
+}
+
+template <typename S>
+hipError_t ritz_device(int m, const double* Tdev, double fro2, int descending, int kcols,
+                       double* scratch, double* lam_s, double* Zs, S* Zc, double* zlast,
+                       double* hs, hipStream_t st) {
+  double* eigw = scratch;
+  double* lam_raw = eigw + eig_work_doubles(m);
+  double* Z_raw = lam_raw + m;
+  int* perm = reinterpret_cast<int*>(Z_raw + (size_t)m * m);
+  const double* lam_ptr;
+  int64_t lstride;
+  const double* Zptr;
+  int ldz;
+  const int mp = m + (m & 1);
+  hipError_t e;
+  if (mp <= eig_small_max()) {
+    if ((e = launch_eig_small(Tdev, m, m, lam_raw, Z_raw, m, 60, st)) != hipSuccess) return e;
+    lam_ptr = lam_raw;
+    lstride = 1;
+    Zptr = Z_raw;
+    ldz = m;
+  } else {
+    EigWork w;
+    w.A[0] = eigw;
+    w.A[1] = eigw + (size_t)mp * mp;
+    w.Z = eigw + 2 * (size_t)mp * mp;
+    w.off = eigw + 3 * (size_t)mp * mp;
+    if ((e = launch_eig_init(Tdev, m, m, w, st)) != hipSuccess) return e;
+    int c = 0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      for (int r = 0; r < mp - 1; ++r) {
+        if ((e = launch_eig_round(m, w, c, r, st)) != hipSuccess) return e;
+        c ^= 1;
+      }
+      if ((e = launch_eig_offnorm(m, w, c, st)) != hipSuccess) return e;
+      if ((e = hipMemcpyAsync(hs, w.off, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+      if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+      if (hs[0] <= 1e-30 * fro2) break;
+    }
+    lam_ptr = w.A[c];
+    lstride = mp + 1;
+    Zptr = w.Z;
+    ldz = mp;
+  }
+  return launch_ritz_sort<S>(m, lam_ptr, lstride, Zptr, ldz, descending, kcols, perm, lam_s, Zs, Zc,
+                             zlast, st);
+}
+
+template hipError_t ritz_device<float>(int, const double*, double, int, int, double*, double*,
+                                       double*, float*, double*, double*, hipStream_t);
+template hipError_t ritz_device<double>(int, const double*, double, int, int, double*, double*,
+                                        double*, double*, double*, double*, hipStream_t);
+
+}  // namespace jl
+
+namespace {
+
+// Operator dispatch over storage type.
+template <typename S> struct OpView;
+template <> struct OpView<float> {
+  static const StencilArgs<float>& st(const jl_op_s* o) { return o->sf; }
+  static const DenseArgs<float>& de(const jl_op_s* o) { return o->df; }
+};
+template <> struct OpView<double> {
+  static const StencilArgs<double>& st(const jl_op_s* o) { return o->sd; }
+  static const DenseArgs<double>& de(const jl_op_s* o) { return o->dd; }
+};
+
+template <typename S>
+hipError_t op_apply(const jl_op_s* op, const cplx<S>* x, cplx<S>* y, int64_t ld, int nrhs,
+                    hipStream_t st) {
+  if (op->kind == OP_STENCIL) return launch_stencil_apply<S>(OpView<S>::st(op), x, y, ld, nrhs, st);
+  return launch_dense_apply<S>(OpView<S>::de(op), x, y, ld, nrhs, st);
+}
+
+template <typename S>
+hipError_t op_resid(const jl_op_s* op, const cplx<S>* X, int64_t ldx, const int* cols,
+                    const double* lam, int ncols, double* partial, int* nblk, hipStream_t st) {
+  if (op->kind == OP_STENCIL)
+    return launch_stencil_resid<S>(OpView<S>::st(op), X, ldx, cols, lam, ncols, partial, nblk, st);
+  return launch_dense_resid<S>(OpView<S>::de(op), X, ldx, cols, lam, ncols, partial, nblk, st);
+}
+
+int op_resid_blocks(const jl_op_s* op) {
+  return op->kind == OP_STENCIL ? stencil_resid_blocks(op->n / 8) : dense_resid_blocks(op->n / 2);
+}
+
+// Algorithmic bytes of one operator apply (storage element size es).
+double op_bytes(const jl_op_s* op, int es) {
+  if (op->kind == OP_STENCIL) {
+    const double V = (double)(op->n / 8);
+    const int bps = op->dtype == JL_C64 ? op->sf.b_per_site : op->sd.b_per_site;
+    return V * es * (16.0 + 64.0 + (bps ? 64.0 : 0.0));
+  }
+  const double h = (double)(op->n / 2);
+  return es * (h * (double)op->n + 2.0 * (double)op->n);
+}
+
+// ----------------------------------------------------------- workspace layout
+struct Layout {
+  size_t V[2], dots_part, upd_part, coef, scal, Tdev, ritz, lam_s, Zs, Zc, zlast, res_part,
+      res_out, res_lam, res_cols, total;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(const jl_op_s* op, const jl_params* p) {
+  const int es = op->dtype == JL_C64 ? 8 : 16;   // bytes per complex element
+  const int64_t n = op->n, h = n / 2;
+  const int m = p->m;
+  const int kmax = std::min(p->nev + p->mwin, m - 1);
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.V[0] = take((size_t)n * (m + 1) * es);
+  L.V[1] = take((size_t)n * (m + 1) * es);
+  L.dots_part = take(sizeof(double) * (size_t)reorth_dots_blocks(h) * (4 * (size_t)(m + 1) + 1));
+  L.upd_part = take(sizeof(double) * (size_t)std::max(reorth_update_blocks(h), 1));
+  L.coef = take(sizeof(double) * (4 * (size_t)(m + 1) + 1));
+  L.scal = take(sizeof(double) * 64);
+  L.Tdev = take(sizeof(double) * (size_t)m * m);
+  L.ritz = take(sizeof(double) * ritz_scratch_doubles(m));
+  L.lam_s = take(sizeof(double) * m);
+  L.Zs = take(sizeof(double) * (size_t)m * m);
+  L.Zc = take((size_t)(es / 2) * (size_t)m * kmax);
+  L.zlast = take(sizeof(double) * m);
+  L.res_part = take(sizeof(double) * (size_t)op_resid_blocks(op) * p->nev);
+  L.res_out = take(sizeof(double) * p->nev);
+  L.res_lam = take(sizeof(double) * p->nev);
+  L.res_cols = take(sizeof(int) * p->nev);
+  L.total = off;
+  return L;
+}
+
+jl_status check_params(jl_ctx ctx, const jl_op_s* op, const jl_params* p) {
+  if (!p) return set_err(ctx, JL_EINVAL, "params is NULL");
+  const int64_t n = op->n;
+  if (p->nev < 1) return set_err(ctx, JL_EINVAL, "nev must be >= 1 (got %d)", p->nev);
+  if (p->mwin < p->nev)
+    return set_err(ctx, JL_EINVAL, "mwin (%d) must be >= nev (%d)", p->mwin, p->nev);
+  if (p->m <= p->mwin) return set_err(ctx, JL_EINVAL, "m (%d) must exceed mwin (%d)", p->m, p->mwin);
+  if ((int64_t)p->m > n / 2)
+    return set_err(ctx, JL_EINVAL, "m (%d) exceeds n/2 (%lld): the J-half Krylov space is exhausted",
+                   p->m, (long long)(n / 2));
+  if (p->m + 1 > kReorthMaxCols)
+    return set_err(ctx, JL_EINVAL, "m (%d) exceeds the supported maximum %d", p->m,
+                   kReorthMaxCols - 1);
+  if (!(p->tol > 0.0)) return set_err(ctx, JL_EINVAL, "tol must be positive");
+  if (p->which != JL_LOWEST && p->which != JL_LARGEST)
+    return set_err(ctx, JL_EINVAL, "which must be JL_LOWEST or JL_LARGEST");
+  if (p->trace_cap < 0 || (p->trace_cap > 0 && !p->trace_ab))
+    return set_err(ctx, JL_EINVAL, "trace_cap > 0 needs trace_ab");
+  return JL_OK;
+}
+
+// Accumulates GPU time of kernel classes from HIP event pairs; pairs are
+// resolved at the driver's synchronisation points.
+struct Timer {
+  enum { MATVEC, DOTS, UPDATE, GEMM, RITZ, RESID, NCLS };
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double t[NCLS] = {};
+  int cur = -1;
+  hipEvent_t cur_start = nullptr;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void start(int cls) {
+    if (!on) return;
+    cur = cls;
+    cur_start = get();
+    if (cur_start) hipEventRecord(cur_start, st);
+  }
+  void stop() {
+    if (!on || !cur_start) return;
+    hipEvent_t e = get();
+    if (!e) return;
+    hipEventRecord(e, st);
+    pending.push_back({cur, {cur_start, e}});
+    cur_start = nullptr;
+  }
+  // Call only after the stream has been synchronised.
+  void resolve() {
+    for (auto& pr : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pr.second.first, pr.second.second) == hipSuccess)
+        t[pr.first] += 1e-3 * ms;
+      pool.push_back(pr.second.first);
+      pool.push_back(pr.second.second);
+    }
+    pending.clear();
+  }
+  ~Timer() {
+    for (auto e : pool) hipEventDestroy(e);
+    for (auto& pr : pending) {
+      hipEventDestroy(pr.second.first);
+      hipEventDestroy(pr.second.second);
+    }
+  }
+};
+
+// Pinned host staging for the few values read back each step.
+struct Pinned {
+  double* p = nullptr;
+  ~Pinned() {
+    if (p) hipHostFree(p);
+  }
+};
+
+template <typename S>
+jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws, size_t ws_bytes,
+                     double* evals, void* Xout, int64_t ldx, double* res_out, jl_stats* stats) {
+  jl_ctx ctx = op->ctx;
+  hipStream_t st = ctx->stream;
+  const auto t_begin = std::chrono::steady_clock::now();
+  jl_stats S_{};
+  const int64_t n = op->n, h = n / 2;
+  const int m = prm->m, nev = prm->nev, mwin = prm->mwin;
+  const int kmax = std::min(nev + mwin, m - 1);
+  const int max_cycles = prm->max_cycles > 0 ? prm->max_cycles : 10000;
+  const int max_passes = prm->max_passes > 0 ? prm->max_passes : 16;
+  const int es = (int)sizeof(cplx<S>);
+  const double uround = sizeof(S) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
+  const double bd_factor = 64.0;
+
+  const Layout L = make_layout(op, prm);
+  if (!ws || ws_bytes < L.total)
+    return set_err(ctx, JL_ENOMEM, "workspace of %zu bytes is smaller than the %zu required",
+                   ws_bytes, L.total);
+  if (!evals || !Xout || !res_out) return set_err(ctx, JL_EINVAL, "evals, X and res are required");
+  if (ldx < n) return set_err(ctx, JL_EINVAL, "ldx (%lld) < n (%lld)", (long long)ldx, (long long)n);
+
+  char* base = static_cast<char*>(ws);
+  cplx<S>* Vb[2] = {reinterpret_cast<cplx<S>*>(base + L.V[0]),
+                    reinterpret_cast<cplx<S>*>(base + L.V[1])};
+  double* dots_part = reinterpret_cast<double*>(base + L.dots_part);
+  double* upd_part = reinterpret_cast<double*>(base + L.upd_part);
+  double* coef = reinterpret_cast<double*>(base + L.coef);
+  double* scal = reinterpret_cast<double*>(base + L.scal);
+  double* Tdev = reinterpret_cast<double*>(base + L.Tdev);
+  double* ritz_scr = reinterpret_cast<double*>(base + L.ritz);
+  double* lam_s = reinterpret_cast<double*>(base + L.lam_s);
+  double* Zs = reinterpret_cast<double*>(base + L.Zs);
+  S* Zc = reinterpret_cast<S*>(base + L.Zc);
+  double* zlast = reinterpret_cast<double*>(base + L.zlast);
+  double* res_part = reinterpret_cast<double*>(base + L.res_part);
+  double* res_dev = reinterpret_cast<double*>(base + L.res_out);
+  double* res_lam = reinterpret_cast<double*>(base + L.res_lam);
+  int* res_cols = reinterpret_cast<int*>(base + L.res_cols);
+
+  const int ndots = reorth_dots_blocks(h);
+  const int nupd = reorth_update_blocks(h);
+  const int64_t ldv = n;
+
+  Pinned pin;
+  const size_t pin_doubles = 16 + 3 * (size_t)m + 3 * (size_t)nev;
+  JL_HIP(ctx, hipHostMalloc((void**)&pin.p, sizeof(double) * pin_doubles, hipHostMallocDefault));
+  double* hs = pin.p;                    // [16] scalars
+  double* h_lam = pin.p + 16;            // [m]
+  double* h_zl = h_lam + m;              // [m]
+  double* h_res = h_zl + m;              // [nev]
+  double* h_rlam = h_res + nev;          // [nev]
+  int* h_rcols = reinterpret_cast<int*>(h_rlam + nev);   // [nev] ints (fits in nev doubles)
+
+  Timer tm;
+  tm.on = prm->timing != 0;
+  tm.st = st;
+
+  // ---- start vector (Alg. 1: v_1 = ones / ||ones||, or the caller's)
+  int cur = 0;
+  if (!v1) {
+    JL_HIP(ctx, launch_fill<S>(Vb[cur], n, 1.0 / std::sqrt((double)n), st));
+  } else {
+    JL_HIP(ctx, hipMemcpyAsync(Vb[cur], v1, (size_t)n * es, hipMemcpyDeviceToDevice, st));
+    JL_HIP(ctx, launch_reorth_dots<S>(Vb[cur], ldv, 0, Vb[cur], h, dots_part, ndots, st));
+    JL_HIP(ctx, launch_reduce_cols(dots_part, ndots, 1, 1, scal, st));
+    JL_HIP(ctx, hipMemcpyAsync(hs, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    JL_HIP(ctx, hipStreamSynchronize(st));
+    if (!(hs[0] > 0.0) || !std::isfinite(hs[0]))
+      return set_err(ctx, JL_EINVAL, "start vector has zero or non-finite norm");
+    JL_HIP(ctx, launch_scale<S>(Vb[cur], n, 1.0 / std::sqrt(hs[0]), st));
+  }
+
+  // Tbar: (m+1) x m, column-major on the host (row i, column j at i + j*(m+1)).
+  std::vector<double> T((size_t)(m + 1) * m, 0.0);
+  auto Tat = [&](int i, int j) -> double& { return T[(size_t)i + (size_t)j * (m + 1)]; };
+  double maxT = 0.0;
+  std::vector<double> Tm((size_t)m * m);
+  std::vector<double> lam_sorted(m), svec(m);
+  std::vector<char> conv(nev);
+  std::vector<double> resv(nev);
+  int k = 0;
+  int trace_n = 0;
+  const double sqrt2 = std::sqrt(2.0);
+  jl_status status = JL_NOT_CONVERGED;
+  int icnv = 0;
+  std::vector<int> out_order;
+
+  for (int cycle = 0; cycle < max_cycles; ++cycle) {
+    S_.cycles++;
+    cplx<S>* V = Vb[cur];
+    cplx<S>* Vn = Vb[1 - cur];
+    int meff = m;
+    bool broke = false;
+    // ================= Algorithm 2: Lanczos steps j = k .. m-1
+    for (int j = k; j < m; ++j) {
+      cplx<S>* vj = V + (int64_t)j * ldv;
+      cplx<S>* u = V + (int64_t)(j + 1) * ldv;
+      tm.start(Timer::MATVEC);
+      JL_HIP(ctx, op_apply<S>(op, vj, u, ldv, 1, st));
+      tm.stop();
+      S_.n_mv++;
+      S_.n_matvec_launch++;
+      S_.bytes_matvec += op_bytes(op, es);
+      const int ncol = j + 1;
+      const int stride = 4 * ncol + 1;
+      // first pass inner products against [V_j, W_j] (includes t_jj = v_j^H u)
+      tm.start(Timer::DOTS);
+      JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st));
+      tm.stop();
+      JL_HIP(ctx, launch_reduce_cols(dots_part, ndots, stride, stride, coef, st));
+      S_.n_dots_launch++;
+      S_.bytes_dots += (double)(ncol + 1) * n * es;
+      JL_HIP(ctx, hipMemcpyAsync(hs, coef + 4 * j, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      JL_HIP(ctx, hipMemcpyAsync(hs + 2, coef + 4 * ncol, sizeof(double), hipMemcpyDeviceToHost, st));
+      JL_HIP(ctx, hipStreamSynchronize(st));
+      tm.resolve();
+      const double tr = hs[0], ti = hs[1], unorm2 = hs[2];
+      const double alpha = tr;
+      Tat(j, j) = alpha;
+      maxT = std::max(maxT, std::fabs(alpha));
+      // b0 = ||u - t_jj v_j||
+      double b0 = std::sqrt(std::max(unorm2 - (tr * tr + ti * ti), 0.0));
+      const double btol = bd_factor * uround * std::max(maxT, 1e-300);
+      double b1 = 0.0;
+      int passes = 0;
+      for (;;) {
+        tm.start(Timer::UPDATE);
+        JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st));
+        tm.stop();
+        JL_HIP(ctx, launch_reduce_cols(upd_part, nupd, 1, 1, scal, st));
+        S_.n_update_launch++;
+        S_.bytes_update += (double)(ncol + 2) * n * es;
+        JL_HIP(ctx, hipMemcpyAsync(hs, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+        JL_HIP(ctx, hipStreamSynchronize(st));
+        tm.resolve();
+        b1 = std::sqrt(hs[0]);
+        passes++;
+        S_.gs_passes++;
+        if (b1 * sqrt2 > b0 || b1 <= btol || passes >= max_passes) break;
+        b0 = b1;
+        tm.start(Timer::DOTS);
+        JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st));
+        tm.stop();
+        JL_HIP(ctx, launch_reduce_cols(dots_part, ndots, stride, stride, coef, st));
+        S_.n_dots_launch++;
+        S_.bytes_dots += (double)(ncol + 1) * n * es;
+      }
+      if (trace_n < prm->trace_cap) {
+        prm->trace_ab[trace_n] = alpha;
+        prm->trace_ab[prm->trace_cap + trace_n] = b1;
+        trace_n++;
+      }
+      if (!std::isfinite(b1) || !std::isfinite(alpha))
+        return set_err(ctx, JL_EHIP, "non-finite Lanczos coefficient at step %d", j);
+      if (b1 <= btol) {   // invariant subspace: the cycle ends at dimension j+1
+        Tat(j + 1, j) = 0.0;
+        meff = j + 1;
+        broke = true;
+        break;
+      }
+      JL_HIP(ctx, launch_scale<S>(u, n, 1.0 / b1, st));
+      Tat(j + 1, j) = b1;
+      maxT = std::max(maxT, b1);
+    }
+    if (meff < nev) {
+      status = JL_BREAKDOWN;
+      icnv = 0;
+      out_order.clear();
+      for (int i = 0; i < nev; ++i) {
+        evals[i] = NAN;
+        res_out[i] = INFINITY;
+      }
+      break;
+    }
+    // ================= Rayleigh-Ritz: T_m = Z Lambda Z^T, sort (Alg. 1)
+    for (int jj = 0; jj < meff; ++jj)
+      for (int ii = 0; ii < meff; ++ii) {
+        const double v = ii >= jj ? Tat(ii, jj) : Tat(jj, ii);
+        Tm[(size_t)ii + (size_t)jj * meff] = v;
+      }
+    double fro2 = 0.0;
+    for (int i = 0; i < meff * meff; ++i) fro2 += Tm[i] * Tm[i];
+    tm.start(Timer::RITZ);
+    JL_HIP(ctx, hipMemcpyAsync(Tdev, Tm.data(), sizeof(double) * (size_t)meff * meff,
+                               hipMemcpyHostToDevice, st));
+    const int kcols = std::min(kmax, meff);
+    JL_HIP(ctx, ritz_device<S>(meff, Tdev, fro2, prm->which == JL_LARGEST, kcols, ritz_scr, lam_s,
+                               Zs, Zc, zlast, hs, st));
+    JL_HIP(ctx, hipMemcpyAsync(h_lam, lam_s, sizeof(double) * meff, hipMemcpyDeviceToHost, st));
+    JL_HIP(ctx, hipMemcpyAsync(h_zl, zlast, sizeof(double) * meff, hipMemcpyDeviceToHost, st));
+    tm.stop();
+    // ================= V_k := V_m Z[:, 0:kcols] (real GEMM on the interleaved basis)
+    tm.start(Timer::GEMM);
+    JL_HIP(ctx, launch_gemm_nn<S>(reinterpret_cast<const S*>(V), 2 * ldv, Zc, meff,
+                                  reinterpret_cast<S*>(Vn), 2 * ldv, 2 * n, kcols, meff, st));
+    tm.stop();
+    S_.n_gemm_launch++;
+    S_.flops_gemm += 2.0 * (double)(2 * n) * kcols * meff;
+    JL_HIP(ctx, hipStreamSynchronize(st));
+    tm.resolve();
+    const double beta_m = Tat(meff, meff - 1);
+    for (int i = 0; i < meff; ++i) {
+      lam_sorted[i] = h_lam[i];
+      svec[i] = beta_m * h_zl[i];   // t_{m+1,i} = t_{m+1,m} z_{m,i}
+    }
+    // ================= convergence check on the true residuals (Alg. 1)
+    int ncand = 0;
+    for (int i = 0; i < nev; ++i) {
+      conv[i] = 0;
+      resv[i] = INFINITY;
+      if (std::fabs(svec[i]) < prm->tol) {
+        h_rcols[ncand] = i;
+        h_rlam[ncand] = lam_sorted[i];
+        ncand++;
+      }
+    }
+    if (ncand > 0) {
+      tm.start(Timer::RESID);
+      JL_HIP(ctx, hipMemcpyAsync(res_cols, h_rcols, sizeof(int) * ncand, hipMemcpyHostToDevice, st));
+      JL_HIP(ctx, hipMemcpyAsync(res_lam, h_rlam, sizeof(double) * ncand, hipMemcpyHostToDevice, st));
+      int nrb = 0;
+      JL_HIP(ctx, op_resid<S>(op, Vn, ldv, res_cols, res_lam, ncand, res_part, &nrb, st));
+      JL_HIP(ctx, launch_reduce_cols(res_part, nrb, ncand, ncand, res_dev, st));
+      JL_HIP(ctx, hipMemcpyAsync(h_res, res_dev, sizeof(double) * ncand, hipMemcpyDeviceToHost, st));
+      tm.stop();
+      JL_HIP(ctx, hipStreamSynchronize(st));
+      tm.resolve();
+      S_.n_resid += ncand;
+      for (int c = 0; c < ncand; ++c) {
+        const int i = h_rcols[c];
+        resv[i] = std::sqrt(h_res[c]);
+        conv[i] = resv[i] < prm->tol;
+      }
+    }
+    icnv = 0;
+    out_order.clear();
+    for (int i = 0; i < nev; ++i)
+      if (conv[i]) out_order.push_back(i), icnv++;
+    for (int i = 0; i < nev; ++i)
+      if (!conv[i]) out_order.push_back(i);
+    const bool last = (cycle + 1 == max_cycles);
+    if (icnv == nev || broke || last) {
+      status = icnv == nev ? JL_OK : (broke ? JL_BREAKDOWN : JL_NOT_CONVERGED);
+      cur = 1 - cur;   // the Ritz vectors live in Vn
+      break;
+    }
+    // ================= shrink to k + 1 (eq. dynamicwin) and continue
+    k = std::min(icnv + mwin, m - 1);
+    std::fill(T.begin(), T.end(), 0.0);
+    maxT = 0.0;
+    for (int i = 0; i < k; ++i) {
+      Tat(i, i) = lam_sorted[i];
+      const double si = (i < nev && conv[i]) ? 0.0 : svec[i];   // decouple converged
+      Tat(k, i) = si;
+      maxT = std::max(maxT, std::max(std::fabs(lam_sorted[i]), std::fabs(si)));
+    }
+    JL_HIP(ctx, launch_copy_cols<S>(V + (int64_t)meff * ldv, ldv, Vn + (int64_t)k * ldv, ldv, n, 1,
+                                    st));
+    cur = 1 - cur;
+  }
+
+  // ---- outputs: converged pairs first, desired order otherwise
+  if (!out_order.empty()) {
+    cplx<S>* Vf = Vb[cur];
+    cplx<S>* X = static_cast<cplx<S>*>(Xout);
+    for (int c = 0; c < nev; ++c) {
+      const int i = out_order[c];
+      evals[c] = lam_sorted[i];
+      res_out[c] = resv[i];
+      JL_HIP(ctx, launch_copy_cols<S>(Vf + (int64_t)i * ldv, ldv, X + (int64_t)c * ldx, ldx, n, 1,
+                                      st));
+    }
+  }
+  JL_HIP(ctx, hipStreamSynchronize(st));
+  tm.resolve();
+  S_.icnv = icnv;
+  S_.status = status;
+  S_.t_matvec = tm.t[Timer::MATVEC];
+  S_.t_dots = tm.t[Timer::DOTS];
+  S_.t_update = tm.t[Timer::UPDATE];
+  S_.t_gemm = tm.t[Timer::GEMM];
+  S_.t_ritz = tm.t[Timer::RITZ];
+  S_.t_resid = tm.t[Timer::RESID];
+  S_.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count();
+  if (stats) *stats = S_;
+  return status;
+}
+
+}  // namespace
+
+// =============================================================== C ABI
+extern "C" {
+
+const char* jl_status_string(jl_status s) {
+  switch (s) {
+    case JL_OK: return "ok";
+    case JL_EINVAL: return "invalid argument";
+    case JL_EHIP: return "HIP runtime error";
+    case JL_ENOMEM: return "workspace too small";
+    case JL_EUNSUPPORTED: return "unsupported";
+    case JL_NOT_CONVERGED: return "not converged";
+    case JL_BREAKDOWN: return "breakdown (invariant subspace)";
+    default: return "unknown status";
+  }
+}
+
+const char* jl_last_error(jl_ctx ctx) { return ctx ? ctx->err.c_str() : g_thread_err.c_str(); }
+
+jl_status jl_ctx_create(jl_ctx* out, int32_t device, void* hip_stream) {
+  if (!out) return set_err(nullptr, JL_EINVAL, "out is NULL");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess)
+    return set_err(nullptr, JL_EHIP, "hipGetDeviceCount failed: %s", hipGetErrorString(e));
+  if (device < 0 || device >= ndev)
+    return set_err(nullptr, JL_EINVAL, "device %d out of range (%d devices)", device, ndev);
+  jl_ctx c = new jl_ctx_s();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return JL_OK;
+}
+
+jl_status jl_ctx_destroy(jl_ctx ctx) {
+  delete ctx;
+  return JL_OK;
+}
+
+jl_status jl_op_create_dense(jl_ctx ctx, int64_t n, const void* A11, const void* A12, int64_t ld,
+                             jl_dtype dtype, jl_op* out) {
+  if (!ctx || !out) return set_err(ctx, JL_EINVAL, "ctx and out are required");
+  if (n <= 0 || n % 2) return set_err(ctx, JL_EINVAL, "n must be positive and even (got %lld)", (long long)n);
+  if (ld < n / 2) return set_err(ctx, JL_EINVAL, "ld (%lld) < n/2", (long long)ld);
+  if (!A11 || !A12) return set_err(ctx, JL_EINVAL, "A11 and A12 are required");
+  if (dtype != JL_C64 && dtype != JL_C128) return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
+  jl_op o = new jl_op_s();
+  o->ctx = ctx;
+  o->kind = OP_DENSE;
+  o->dtype = dtype;
+  o->n = n;
+  o->df = DenseArgs<float>{static_cast<const float2*>(A11), static_cast<const float2*>(A12), n / 2, ld};
+  o->dd = DenseArgs<double>{static_cast<const double2*>(A11), static_cast<const double2*>(A12), n / 2, ld};
+  *out = o;
+  return JL_OK;
+}
+
+jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double diag,
+                               double a12_scale, const void* U, const void* B, int32_t b_per_site,
+                               jl_dtype dtype, jl_op* out) {
+  if (!ctx || !out || !L) return set_err(ctx, JL_EINVAL, "ctx, L and out are required");
+  if (d != 4) return set_err(ctx, JL_EUNSUPPORTED, "only internal dimension d = 4 is implemented (got %d)", d);
+  for (int i = 0; i < 4; ++i)
+    if (L[i] < 2) return set_err(ctx, JL_EINVAL, "L[%d] = %d must be >= 2", i, L[i]);
+  if (!U || !B) return set_err(ctx, JL_EINVAL, "U and B are required");
+  if (dtype != JL_C64 && dtype != JL_C128) return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
+  const int64_t V = (int64_t)L[0] * L[1] * L[2] * L[3];
+  jl_op o = new jl_op_s();
+  o->ctx = ctx;
+  o->kind = OP_STENCIL;
+  o->dtype = dtype;
+  o->n = 2 * V * 4;
+  StencilArgs<float> sf{};
+  StencilArgs<double> sd{};
+  for (int i = 0; i < 4; ++i) sf.L[i] = sd.L[i] = L[i];
+  sf.V = sd.V = V;
+  sf.b_per_site = sd.b_per_site = b_per_site ? 1 : 0;
+  sf.diag = sd.diag = diag;
+  sf.scale = sd.scale = a12_scale;
+  sf.U = static_cast<const float2*>(U);
+  sf.B = static_cast<const float2*>(B);
+  sd.U = static_cast<const double2*>(U);
+  sd.B = static_cast<const double2*>(B);
+  o->sf = sf;
+  o->sd = sd;
+  *out = o;
+  return JL_OK;
+}
+
+jl_status jl_op_destroy(jl_op op) {
+  delete op;
+  return JL_OK;
+}
+
+jl_status jl_op_dim(jl_op op, int64_t* n) {
+  if (!op || !n) return set_err(op ? op->ctx : nullptr, JL_EINVAL, "op and n are required");
+  *n = op->n;
+  return JL_OK;
+}
+
+jl_status jl_op_apply(jl_op op, const void* x, void* y, int32_t nrhs) {
+  if (!op) return set_err(nullptr, JL_EINVAL, "op is NULL");
+  jl_ctx ctx = op->ctx;
+  if (!x || !y || nrhs < 0) return set_err(ctx, JL_EINVAL, "x, y required and nrhs >= 0");
+  if (nrhs == 0) return JL_OK;
+  DeviceGuard g(ctx->device);
+  if (op->dtype == JL_C64)
+    JL_HIP(ctx, op_apply<float>(op, static_cast<const float2*>(x), static_cast<float2*>(y), op->n, nrhs, ctx->stream));
+  else
+    JL_HIP(ctx, op_apply<double>(op, static_cast<const double2*>(x), static_cast<double2*>(y), op->n, nrhs, ctx->stream));
+  return JL_OK;
+}
+
+jl_status jl_workspace_bytes(jl_op op, const jl_params* p, size_t* bytes) {
+  if (!op || !bytes) return set_err(op ? op->ctx : nullptr, JL_EINVAL, "op and bytes are required");
+  jl_status s = check_params(op->ctx, op, p);
+  if (s != JL_OK) return s;
+  *bytes = make_layout(op, p).total;
+  return JL_OK;
+}
+
+jl_status jl_solve(jl_op op, const jl_params* p, const void* v1, void* ws, size_t ws_bytes,
+                   double* evals, void* X, int64_t ldx, double* res, jl_stats* stats) {
+  if (!op) return set_err(nullptr, JL_EINVAL, "op is NULL");
+  jl_status s = check_params(op->ctx, op, p);
+  if (s != JL_OK) return s;
+  DeviceGuard g(op->ctx->device);
+  if (op->dtype == JL_C64) return solve_impl<float>(op, p, v1, ws, ws_bytes, evals, X, ldx, res, stats);
+  return solve_impl<double>(op, p, v1, ws, ws_bytes, evals, X, ldx, res, stats);
+}
+
+jl_status jl_pair_vectors(jl_ctx ctx, int64_t n, int32_t k, jl_dtype dtype, const void* X,
+                          int64_t ldx, void* Y, int64_t ldy) {
+  if (!ctx) return set_err(nullptr, JL_EINVAL, "ctx is NULL");
+  if (n <= 0 || n % 2 || k < 0 || ldx < n || ldy < n || (k > 0 && (!X || !Y)))
+    return set_err(ctx, JL_EINVAL, "invalid pair_vectors arguments");
+  if (X == Y && ldx != ldy) return set_err(ctx, JL_EINVAL, "in-place pairing needs ldx == ldy");
+  DeviceGuard g(ctx->device);
+  if (dtype == JL_C64)
+    JL_HIP(ctx, launch_pair<float>(static_cast<const float2*>(X), ldx, static_cast<float2*>(Y), ldy, n / 2, k, ctx->stream));
+  else if (dtype == JL_C128)
+    JL_HIP(ctx, launch_pair<double>(static_cast<const double2*>(X), ldx, static_cast<double2*>(Y), ldy, n / 2, k, ctx->stream));
+  else
+    return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
+  return JL_OK;
+}
+
+}  // extern "C"

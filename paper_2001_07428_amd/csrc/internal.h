@@ -1,0 +1,54 @@
+// Internal host-side definitions shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/jlanczos.h"
+#include "common.h"
+
+struct jl_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+};
+
+namespace jl {
+
+// Records the message for jl_last_error(ctx) (and the calling thread) and
+// returns `code`.
+jl_status set_err(jl_ctx ctx, jl_status code, const char* fmt, ...);
+
+#define JL_HIP(ctx, expr)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return ::jl::set_err(ctx, JL_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                           __FILE__, __LINE__);                                                \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+// Scratch doubles the Ritz step needs beyond its outputs for an m x m problem.
+size_t ritz_scratch_doubles(int m);
+
+// Rayleigh-Ritz on the device: eigen-decomposition of Tdev (m x m, ld m) by
+// Jacobi (fro2 = ||T||_F^2 sets the stopping test), then the sort of
+// launch_ritz_sort.  `scratch` holds ritz_scratch_doubles(m) doubles; `hs` is
+// a host double used to read the off-diagonal norm back (stream synchronised).
+template <typename S>
+hipError_t ritz_device(int m, const double* Tdev, double fro2, int descending, int kcols,
+                       double* scratch, double* lam_s, double* Zs, S* Zc, double* zlast,
+                       double* hs, hipStream_t st);
+
+}  // namespace jl

@@ -1,0 +1,195 @@
+// Thick-restart basis update V_k <- V_m Z[:, 0:k] (Alg. 1, V_m := V_m Z_m).
+//
+// Z is real, so the complex basis (interleaved, column-major, one vector per
+// column) is a real (2n) x m column-major matrix and the update is a real
+// GEMM C = A * B with M = 2n rows, K = m, N = k.  It is compute-bound at the
+// stencil shapes, so it runs on the matrix cores: v_mfma_f32_16x16x4f32 for
+// FP32 storage, v_mfma_f64_16x16x4f64 for FP64.
+//
+// Block tile 128 x 128, 4 wavefronts in 2 x 2, each 64 x 64 = 4 x 4 MFMA
+// tiles; K staged through LDS in steps of 16 (FP32) or 8 (FP64) with a
+// register prefetch of the next step and two LDS buffers (one barrier per
+// step).  Consecutive tiles of one row panel are placed on the same XCD so
+// the A panel is shared through that XCD's L2.
+#include "common.h"
+
+namespace jl {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename S> struct Mfma;
+template <> struct Mfma<float> {
+  using acc_t = f32x4;
+  static constexpr int BK = 16;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<double> {
+  using acc_t = f64x4;
+  static constexpr int BK = 8;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int BM = 128, BN = 128, PAD = 16, LDT = BM + PAD;
+constexpr int kThreads = 256;
+
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_gemm_nn(const S* __restrict__ A, int64_t lda,
+                                                      const S* __restrict__ B, int64_t ldb,
+                                                      S* __restrict__ C, int64_t ldc, int64_t M,
+                                                      int N, int K, int64_t tiles_m, int tiles_n) {
+  using MF = Mfma<S>;
+  constexpr int BK = MF::BK;
+  constexpr int AV = 16 / sizeof(S);                    // elements per 16-byte load
+  constexpr int A_PER_T = BM * BK / kThreads;           // A elements per thread per step
+  constexpr int B_PER_T = BN * BK / kThreads;
+  __shared__ S As[2][BK][LDT];
+  __shared__ S Bs[2][BK][LDT];
+
+  // XCD-aware tile order: hardware places block b on XCD b % 8; make the
+  // tiles of one row panel consecutive on one XCD.
+  const int64_t nblk = (int64_t)gridDim.x;
+  const int64_t b = blockIdx.x;
+  const int64_t per_xcd = nblk / 8;
+  const int64_t logical = (b % 8) * per_xcd + b / 8;
+  if (logical >= tiles_m * tiles_n) return;
+  const int64_t tm = logical / tiles_n;
+  const int tn = (int)(logical % tiles_n);
+  const int64_t m0 = tm * BM;
+  const int n0 = tn * BN;
+
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int wm = wave / 2, wn = wave % 2;
+
+  // A tile loader: thread -> (k, row chunk of A_PER_T contiguous rows)
+  constexpr int A_TPK = BM / A_PER_T;                   // threads per k
+  const int a_k = tid / A_TPK;
+  const int a_r = (tid % A_TPK) * A_PER_T;
+  // B tile loader: thread -> (col, k chunk of B_PER_T)
+  constexpr int B_TPC = BK / B_PER_T;                   // threads per column
+  const int b_c = tid / B_TPC;
+  const int b_k = (tid % B_TPC) * B_PER_T;
+
+  S ra[A_PER_T], rb[B_PER_T];
+  auto load = [&](int k0) {
+    const int k = k0 + a_k;
+#pragma unroll
+    for (int v = 0; v < A_PER_T; v += AV) {
+      const int64_t row = m0 + a_r + v;
+      if (k < K && row + AV <= M) {
+        const S* p = A + (int64_t)k * lda + row;
+        if constexpr (AV == 4) {
+          const float4 t = *reinterpret_cast<const float4*>(p);
+          ra[v] = t.x; ra[v + 1] = t.y; ra[v + 2] = t.z; ra[v + 3] = t.w;
+        } else {
+          const double2 t = *reinterpret_cast<const double2*>(p);
+          ra[v] = t.x; ra[v + 1] = t.y;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < AV; ++e) {
+          const int64_t r = row + e;
+          ra[v + e] = (k < K && r < M) ? A[(int64_t)k * lda + r] : (S)0;
+        }
+      }
+    }
+    const int col = n0 + b_c;
+#pragma unroll
+    for (int e = 0; e < B_PER_T; ++e) {
+      const int kk = k0 + b_k + e;
+      rb[e] = (col < N && kk < K) ? B[(int64_t)col * ldb + kk] : (S)0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < A_PER_T; ++e) As[buf][a_k][a_r + e] = ra[e];
+#pragma unroll
+    for (int e = 0; e < B_PER_T; ++e) Bs[buf][b_k + e][b_c] = rb[e];
+  };
+
+  typename MF::acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
+
+  const int nk = (K + BK - 1) / BK;
+  load(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    store(buf);
+    __syncthreads();
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      S a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[buf][kr][wm * 64 + i * 16 + lane % 16];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[buf][kr][wn * 64 + j * 16 + lane % 16];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = MF::op(a[i], bb[j], acc[i][j]);
+    }
+  }
+
+  // acc[i][j][r] = C[m0 + wm*64 + i*16 + 4*(lane/16) + r][n0 + wn*64 + j*16 + lane%16]
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int col = n0 + wn * 64 + j * 16 + lane % 16;
+    if (col >= N) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = m0 + wm * 64 + i * 16 + 4 * (lane / 16);
+      S* p = C + (int64_t)col * ldc + row;
+      if (row + 4 <= M) {
+        if constexpr (sizeof(S) == 4) {
+          *reinterpret_cast<float4*>(p) =
+              make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+        } else {
+          reinterpret_cast<double2*>(p)[0] = make_double2(acc[i][j][0], acc[i][j][1]);
+          reinterpret_cast<double2*>(p)[1] = make_double2(acc[i][j][2], acc[i][j][3]);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (row + r < M) p[r] = acc[i][j][r];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+template <typename S>
+hipError_t launch_gemm_nn(const S* A, int64_t lda, const S* B, int64_t ldb, S* C, int64_t ldc,
+                          int64_t M, int N, int K, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  // 16-byte vector loads/stores of A and C columns need 4-element (FP32) or
+  // 2-element (FP64) alignment of every column start.
+  const int AV = 16 / (int)sizeof(S);
+  if ((lda % AV) || (ldc % AV) || ((uintptr_t)A % 16) || ((uintptr_t)C % 16))
+    return hipErrorInvalidValue;
+  const int64_t tm = (M + BM - 1) / BM;
+  const int tn = (N + BN - 1) / BN;
+  int64_t nblk = tm * tn;
+  nblk = (nblk + 7) / 8 * 8;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gemm_nn<S>, dim3((unsigned)nblk), dim3(kThreads), 0, st, A, lda, B, ldb, C,
+                     ldc, M, N, K, tm, tn);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gemm_nn<float>(const float*, int64_t, const float*, int64_t, float*,
+                                          int64_t, int64_t, int, int, hipStream_t);
+template hipError_t launch_gemm_nn<double>(const double*, int64_t, const double*, int64_t, double*,
+                                           int64_t, int64_t, int, int, hipStream_t);
+
+}  // namespace jl

@@ -1,0 +1,362 @@
+// Operator applies for the J-symmetric eigensolver (gfx950).
+//
+// Both operators only need A11 and A12 (Sec. 1, eq. blockform):
+//   u_top = A11 a + A12 b,   u_bot = A12^H a + A11^T b
+// for v = [a; b].
+//
+// Stencil: one thread per lattice site computes all 4 internal components of
+// both halves; the link U_mu(x) is read once for the forward hop of both
+// halves and U_mu(x - mu) once for the backward hop.
+// Dense: one wavefront per row of [A11 A12]; the row is read once for both
+// right-hand sides [a; b] and [conj(b); -conj(a)] (u_bot = conj(A11 conj(b) -
+// A12 conj(a)) because A11^T = conj(A11) and A12^H = -conj(A12)).
+#include "common.h"
+
+namespace jl {
+namespace {
+
+template <typename C> struct cx { C re, im; };
+
+template <typename C>
+__device__ __forceinline__ void mac(cx<C>& acc, C ar, C ai, C br, C bi) {  // acc += a*b
+  acc.re = fma(ar, br, acc.re);
+  acc.re = fma(-ai, bi, acc.re);
+  acc.im = fma(ar, bi, acc.im);
+  acc.im = fma(ai, br, acc.im);
+}
+template <typename C>
+__device__ __forceinline__ void mac_conj_a(cx<C>& acc, C ar, C ai, C br, C bi) {  // acc += conj(a)*b
+  acc.re = fma(ar, br, acc.re);
+  acc.re = fma(ai, bi, acc.re);
+  acc.im = fma(ar, bi, acc.im);
+  acc.im = fma(-ai, br, acc.im);
+}
+
+// Load the 4 complex components of one site (storage S) into compute type C.
+template <typename S, typename C>
+__device__ __forceinline__ void load_site(const cplx<S>* __restrict__ p, C re[4], C im[4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    cplx<S> v = p[c];
+    re[c] = (C)v.x;
+    im[c] = (C)v.y;
+  }
+}
+template <typename S, typename C>
+__device__ __forceinline__ void load_link(const cplx<S>* __restrict__ p, C re[16], C im[16]) {
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    cplx<S> v = p[c];
+    re[c] = (C)v.x;
+    im[c] = (C)v.y;
+  }
+}
+
+// Computes (A v)(s) for one site: top[4], bot[4] in compute type C.
+template <typename S, typename C>
+__device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx<S>* __restrict__ xt,
+                                             const cplx<S>* __restrict__ xb, int64_t s,
+                                             cx<C> top[4], cx<C> bot[4]) {
+  const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
+  const int64_t st[4] = {(int64_t)L1 * L2 * L3, (int64_t)L2 * L3, (int64_t)L3, 1};
+  int x[4];
+  {
+    int64_t r = s;
+    x[0] = (int)(r / st[0]); r -= (int64_t)x[0] * st[0];
+    x[1] = (int)(r / st[1]); r -= (int64_t)x[1] * st[1];
+    x[2] = (int)(r / st[2]); r -= (int64_t)x[2] * st[2];
+    x[3] = (int)r;
+  }
+  const int Ls[4] = {L0, L1, L2, L3};
+  const C dg = (C)a.diag;
+  const C sc = (C)a.scale;
+  {
+    C ar[4], ai[4], br[4], bi[4];
+    load_site<S, C>(xt + s * 4, ar, ai);
+    load_site<S, C>(xb + s * 4, br, bi);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      top[r].re = dg * ar[r]; top[r].im = dg * ai[r];
+      bot[r].re = dg * br[r]; bot[r].im = dg * bi[r];
+    }
+  }
+  const int64_t V = a.V;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const int64_t sf = (x[mu] == Ls[mu] - 1) ? s - (int64_t)(Ls[mu] - 1) * st[mu] : s + st[mu];
+    const int64_t sb = (x[mu] == 0) ? s + (int64_t)(Ls[mu] - 1) * st[mu] : s - st[mu];
+    // ---- forward hop: U(x) [a(x+mu), conj(b(x+mu))], B(x) b(x+mu), conj(B(x)) a(x+mu)
+    {
+      C ar[4], ai[4], br[4], bi[4];
+      load_site<S, C>(xt + sf * 4, ar, ai);
+      load_site<S, C>(xb + sf * 4, br, bi);
+      C ur[16], ui[16];
+      load_link<S, C>(a.U + ((int64_t)mu * V + s) * 16, ur, ui);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cx<C> t = {0, 0}, q = {0, 0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          mac(t, ur[4 * r + c], ui[4 * r + c], ar[c], ai[c]);          // U a_f
+          mac_conj_a(q, ur[4 * r + c], ui[4 * r + c], br[c], bi[c]);   // conj(U) b_f
+        }
+        top[r].re -= t.re; top[r].im -= t.im;
+        bot[r].re -= q.re; bot[r].im -= q.im;
+      }
+      const cplx<S>* Bp = a.b_per_site ? a.B + ((int64_t)mu * V + s) * 16 : a.B + mu * 16;
+      load_link<S, C>(Bp, ur, ui);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cx<C> t = {0, 0}, q = {0, 0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          mac(t, ur[4 * r + c], ui[4 * r + c], br[c], bi[c]);          // B b_f
+          mac_conj_a(q, ur[4 * r + c], ui[4 * r + c], ar[c], ai[c]);   // conj(B) a_f
+        }
+        top[r].re = fma(sc, t.re, top[r].re); top[r].im = fma(sc, t.im, top[r].im);
+        bot[r].re = fma(-sc, q.re, bot[r].re); bot[r].im = fma(-sc, q.im, bot[r].im);
+      }
+    }
+    // ---- backward hop: U(x-mu)^H a(x-mu), U(x-mu)^T b(x-mu), B(x-mu)^T b, B(x-mu)^H a
+    {
+      C ar[4], ai[4], br[4], bi[4];
+      load_site<S, C>(xt + sb * 4, ar, ai);
+      load_site<S, C>(xb + sb * 4, br, bi);
+      C ur[16], ui[16];
+      load_link<S, C>(a.U + ((int64_t)mu * V + sb) * 16, ur, ui);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cx<C> t = {0, 0}, q = {0, 0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          mac_conj_a(t, ur[4 * c + r], ui[4 * c + r], ar[c], ai[c]);   // U^H a_b
+          mac(q, ur[4 * c + r], ui[4 * c + r], br[c], bi[c]);          // U^T b_b
+        }
+        top[r].re -= t.re; top[r].im -= t.im;
+        bot[r].re -= q.re; bot[r].im -= q.im;
+      }
+      const cplx<S>* Bp = a.b_per_site ? a.B + ((int64_t)mu * V + sb) * 16 : a.B + mu * 16;
+      load_link<S, C>(Bp, ur, ui);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cx<C> t = {0, 0}, q = {0, 0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          mac(t, ur[4 * c + r], ui[4 * c + r], br[c], bi[c]);          // B^T b_b
+          mac_conj_a(q, ur[4 * c + r], ui[4 * c + r], ar[c], ai[c]);   // B^H a_b
+        }
+        top[r].re = fma(-sc, t.re, top[r].re); top[r].im = fma(-sc, t.im, top[r].im);
+        bot[r].re = fma(sc, q.re, bot[r].re); bot[r].im = fma(sc, q.im, bot[r].im);
+      }
+    }
+  }
+}
+
+constexpr int kStencilThreads = 256;
+
+template <typename S>
+__global__ __launch_bounds__(kStencilThreads) void k_stencil_apply(StencilArgs<S> a,
+                                                                   const cplx<S>* __restrict__ x,
+                                                                   cplx<S>* __restrict__ y,
+                                                                   int64_t ld) {
+  const int64_t s = (int64_t)blockIdx.x * kStencilThreads + threadIdx.x;
+  if (s >= a.V) return;
+  const int64_t h = a.V * 4;
+  const cplx<S>* xc = x + (int64_t)blockIdx.y * ld;
+  cplx<S>* yc = y + (int64_t)blockIdx.y * ld;
+  cx<S> top[4], bot[4];
+  stencil_site<S, S>(a, xc, xc + h, s, top, bot);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    cplx<S> t, b;
+    t.x = top[r].re; t.y = top[r].im;
+    b.x = bot[r].re; b.y = bot[r].im;
+    yc[s * 4 + r] = t;
+    yc[h + s * 4 + r] = b;
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+// ||A x_c - lam_c x_c||^2 per block in FP64 (x stored as S).
+template <typename S>
+__global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S> a,
+                                                                   const cplx<S>* __restrict__ X,
+                                                                   int64_t ldx,
+                                                                   const int* __restrict__ cols,
+                                                                   const double* __restrict__ lam,
+                                                                   double* __restrict__ partial) {
+  __shared__ double sh[kStencilThreads / 64];
+  const int64_t s = (int64_t)blockIdx.x * kStencilThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  const int64_t h = a.V * 4;
+  double acc = 0.0;
+  if (s < a.V) {
+    const cplx<S>* xc = X + (int64_t)cols[c] * ldx;
+    cx<double> top[4], bot[4];
+    stencil_site<S, double>(a, xc, xc + h, s, top, bot);
+    const double l = lam[c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const cplx<S> xt = xc[s * 4 + r], xb = xc[h + s * 4 + r];
+      const double tr = top[r].re - l * (double)xt.x, ti = top[r].im - l * (double)xt.y;
+      const double br = bot[r].re - l * (double)xb.x, bi = bot[r].im - l * (double)xb.y;
+      acc += tr * tr + ti * ti + br * br + bi * bi;
+    }
+  }
+  const double tot = block_sum<kStencilThreads>(acc, sh);
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * gridDim.y + c] = tot;
+}
+
+// ------------------------------------------------------------------ dense
+constexpr int kDenseThreads = 256;   // 4 rows per block, one wavefront per row
+
+template <typename S, typename C>
+__device__ __forceinline__ void dense_row(const DenseArgs<S>& a, const cplx<S>* __restrict__ xt,
+                                          const cplx<S>* __restrict__ xb, int64_t r, cx<C>& s1,
+                                          cx<C>& s2) {
+  const int lane = threadIdx.x % 64;
+  const cplx<S>* r11 = a.A11 + r * a.ld;
+  const cplx<S>* r12 = a.A12 + r * a.ld;
+  cx<C> p = {0, 0}, q = {0, 0};
+  for (int64_t c = lane; c < a.h; c += 64) {
+    const cplx<S> m11 = r11[c], m12 = r12[c];
+    const cplx<S> va = xt[c], vb = xb[c];
+    // s1 += A11 a + A12 b
+    mac(p, (C)m11.x, (C)m11.y, (C)va.x, (C)va.y);
+    mac(p, (C)m12.x, (C)m12.y, (C)vb.x, (C)vb.y);
+    // s2 += A11 conj(b) - A12 conj(a)
+    mac(q, (C)m11.x, (C)m11.y, (C)vb.x, -(C)vb.y);
+    mac(q, (C)m12.x, (C)m12.y, -(C)va.x, (C)va.y);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    p.re += __shfl_xor(p.re, o);
+    p.im += __shfl_xor(p.im, o);
+    q.re += __shfl_xor(q.re, o);
+    q.im += __shfl_xor(q.im, o);
+  }
+  s1 = p;
+  s2 = q;
+}
+
+template <typename S>
+__global__ __launch_bounds__(kDenseThreads) void k_dense_apply(DenseArgs<S> a,
+                                                               const cplx<S>* __restrict__ x,
+                                                               cplx<S>* __restrict__ y, int64_t ld) {
+  const int64_t r = (int64_t)blockIdx.x * (kDenseThreads / 64) + threadIdx.x / 64;
+  if (r >= a.h) return;
+  const cplx<S>* xc = x + (int64_t)blockIdx.y * ld;
+  cplx<S>* yc = y + (int64_t)blockIdx.y * ld;
+  cx<S> s1, s2;
+  dense_row<S, S>(a, xc, xc + a.h, r, s1, s2);
+  if (threadIdx.x % 64 == 0) {
+    cplx<S> t, b;
+    t.x = s1.re; t.y = s1.im;
+    b.x = s2.re; b.y = -s2.im;   // u_bot = conj(s2)
+    yc[r] = t;
+    yc[a.h + r] = b;
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kDenseThreads) void k_dense_resid(DenseArgs<S> a,
+                                                               const cplx<S>* __restrict__ X,
+                                                               int64_t ldx,
+                                                               const int* __restrict__ cols,
+                                                               const double* __restrict__ lam,
+                                                               double* __restrict__ partial) {
+  __shared__ double sh[kDenseThreads / 64];
+  const int64_t r = (int64_t)blockIdx.x * (kDenseThreads / 64) + threadIdx.x / 64;
+  const int c = blockIdx.y;
+  double acc = 0.0;
+  if (r < a.h) {
+    const cplx<S>* xc = X + (int64_t)cols[c] * ldx;
+    cx<double> s1, s2;
+    dense_row<S, double>(a, xc, xc + a.h, r, s1, s2);
+    if (threadIdx.x % 64 == 0) {
+      const double l = lam[c];
+      const cplx<S> xt = xc[r], xb = xc[a.h + r];
+      const double tr = s1.re - l * (double)xt.x, ti = s1.im - l * (double)xt.y;
+      const double br = s2.re - l * (double)xb.x, bi = -s2.im - l * (double)xb.y;
+      acc = tr * tr + ti * ti + br * br + bi * bi;
+    }
+  }
+  // only lane 0 of each wave holds a value; block_sum adds zeros elsewhere
+  const double tot = block_sum<kDenseThreads>(acc, sh);
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * gridDim.y + c] = tot;
+}
+
+}  // namespace
+
+int stencil_resid_blocks(int64_t V) { return (int)((V + kStencilThreads - 1) / kStencilThreads); }
+int dense_resid_blocks(int64_t h) { return (int)((h + kDenseThreads / 64 - 1) / (kDenseThreads / 64)); }
+
+template <typename S>
+hipError_t launch_stencil_apply(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
+                                int nrhs, hipStream_t st) {
+  dim3 grid((unsigned)((a.V + kStencilThreads - 1) / kStencilThreads), (unsigned)nrhs);
+  hipLaunchKernelGGL(k_stencil_apply<S>, grid, dim3(kStencilThreads), 0, st, a, x, y, ld);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_stencil_resid(const StencilArgs<S>& a, const cplx<S>* X, int64_t ldx,
+                                const int* cols, const double* lam, int ncols, double* partial,
+                                int* nblk, hipStream_t st) {
+  const int nb = stencil_resid_blocks(a.V);
+  *nblk = nb;
+  hipLaunchKernelGGL(k_stencil_resid<S>, dim3((unsigned)nb, (unsigned)ncols), dim3(kStencilThreads),
+                     0, st, a, X, ldx, cols, lam, partial);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_dense_apply(const DenseArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ldv,
+                              int nrhs, hipStream_t st) {
+  dim3 grid((unsigned)dense_resid_blocks(a.h), (unsigned)nrhs);
+  hipLaunchKernelGGL(k_dense_apply<S>, grid, dim3(kDenseThreads), 0, st, a, x, y, ldv);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_dense_resid(const DenseArgs<S>& a, const cplx<S>* X, int64_t ldx,
+                              const int* cols, const double* lam, int ncols, double* partial,
+                              int* nblk, hipStream_t st) {
+  const int nb = dense_resid_blocks(a.h);
+  *nblk = nb;
+  hipLaunchKernelGGL(k_dense_resid<S>, dim3((unsigned)nb, (unsigned)ncols), dim3(kDenseThreads), 0,
+                     st, a, X, ldx, cols, lam, partial);
+  return hipGetLastError();
+}
+
+#define JL_INST(S)                                                                               \
+  template hipError_t launch_stencil_apply<S>(const StencilArgs<S>&, const cplx<S>*, cplx<S>*,   \
+                                              int64_t, int, hipStream_t);                        \
+  template hipError_t launch_stencil_resid<S>(const StencilArgs<S>&, const cplx<S>*, int64_t,    \
+                                              const int*, const double*, int, double*, int*,     \
+                                              hipStream_t);                                      \
+  template hipError_t launch_dense_apply<S>(const DenseArgs<S>&, const cplx<S>*, cplx<S>*,       \
+                                            int64_t, int, hipStream_t);                          \
+  template hipError_t launch_dense_resid<S>(const DenseArgs<S>&, const cplx<S>*, int64_t,        \
+                                            const int*, const double*, int, double*, int*,       \
+                                            hipStream_t);
+JL_INST(float)
+JL_INST(double)
+#undef JL_INST
+
+}  // namespace jl

@@ -1,0 +1,388 @@
+// J-restricted reorthogonalisation kernels (Alg. 2, the iterated Gram-Schmidt
+// against W_j = J V_j^* and V_j), written as block classical Gram-Schmidt.
+//
+// W is never stored.  With w_i = J v_i^* = [-conj(v_bot); conj(v_top)]:
+//   w_i^H u = sum_p v_top[p] u_bot[p] - v_bot[p] u_top[p]   (no conjugation)
+//   u_top  += conj(v_bot) c_w,   u_bot -= conj(v_top) c_w
+// so one read of the basis serves both projections.  A "pair" p couples
+// element p of the top half with element p of the bottom half.
+//
+// dots:   per block, FP64 partial sums of v_i^H u and w_i^H u for every
+//         column, plus ||u||^2; one wavefront per column at a time, u held in
+//         registers (converted to FP64), FP64 products and accumulation.
+// update: u -= V c_v + W c_w with the FP64 coefficients rounded to the
+//         storage type, then ||u||^2 in FP64; one pass over the basis.
+#include "common.h"
+
+namespace jl {
+namespace {
+
+constexpr int kReorthThreads = 256;   // 4 wavefronts
+constexpr int kPairsPerLane = 8;      // pairs of u each lane holds per chunk
+constexpr int kMaxCols = 2048;        // LDS column accumulators
+
+// E = complex elements per 16-byte load (2 for FP32 with an even half
+// length, else 1).
+template <typename S, int E> struct Ld;
+template <> struct Ld<float, 2> {
+  static __device__ __forceinline__ void get(const float2* p, float* re, float* im) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    re[0] = v.x; im[0] = v.y; re[1] = v.z; im[1] = v.w;
+  }
+};
+template <> struct Ld<float, 1> {
+  static __device__ __forceinline__ void get(const float2* p, float* re, float* im) {
+    const float2 v = *p;
+    re[0] = v.x; im[0] = v.y;
+  }
+};
+template <> struct Ld<double, 1> {
+  static __device__ __forceinline__ void get(const double2* p, double* re, double* im) {
+    const double2 v = *p;
+    re[0] = v.x; im[0] = v.y;
+  }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// grid.x = blocks, each covering `chunks` consecutive chunks of
+// 64*E*kPairsPerLane pairs.  Column c is owned by wavefront c % 4 of every
+// block.  partial row stride = 4*ncol + 1.
+template <typename S, int E>
+__global__ __launch_bounds__(kReorthThreads) void k_dots(const cplx<S>* __restrict__ V, int64_t ldv,
+                                                         int ncol, const cplx<S>* __restrict__ u,
+                                                         int64_t h, int chunks,
+                                                         double* __restrict__ partial) {
+  constexpr int Q = kPairsPerLane / E;     // loads per half per lane per chunk
+  constexpr int CH = 64 * E * Q;           // pairs per chunk
+  extern __shared__ double acc[];          // 4*ncol + 1 column accumulators
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int i = threadIdx.x; i < 4 * ncol + 1; i += kReorthThreads) acc[i] = 0.0;
+  __syncthreads();
+  double unorm = 0.0;
+  for (int ch = 0; ch < chunks; ++ch) {
+    const int64_t p0 = ((int64_t)blockIdx.x * chunks + ch) * CH;
+    if (p0 >= h) break;
+    // this lane's pairs: p0 + q*64*E + lane*E + e
+    double utr[Q][E], uti[Q][E], ubr[Q][E], ubi[Q][E];
+    bool ok[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t p = p0 + (int64_t)q * 64 * E + lane * E;
+      ok[q] = p < h;                       // E divides h, so p < h covers all E elements
+      S tr[E], ti[E], br[E], bi[E];
+      if (ok[q]) {
+        Ld<S, E>::get(u + p, tr, ti);
+        Ld<S, E>::get(u + h + p, br, bi);
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) tr[e] = ti[e] = br[e] = bi[e] = (S)0;
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        utr[q][e] = tr[e]; uti[q][e] = ti[e]; ubr[q][e] = br[e]; ubi[q][e] = bi[e];
+      }
+    }
+    if (wave == 0) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          unorm += utr[q][e] * utr[q][e] + uti[q][e] * uti[q][e] + ubr[q][e] * ubr[q][e] +
+                   ubi[q][e] * ubi[q][e];
+    }
+    for (int c = wave; c < ncol; c += 4) {
+      const cplx<S>* vt = V + (int64_t)c * ldv;
+      const cplx<S>* vb = vt + h;
+      S tr[Q][E], ti[Q][E], br[Q][E], bi[Q][E];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int64_t p = p0 + (int64_t)q * 64 * E + lane * E;
+        if (ok[q]) {
+          Ld<S, E>::get(vt + p, tr[q], ti[q]);
+          Ld<S, E>::get(vb + p, br[q], bi[q]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) tr[q][e] = ti[q][e] = br[q][e] = bi[q][e] = (S)0;
+        }
+      }
+      double cvr = 0, cvi = 0, cwr = 0, cwi = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const double vtr = tr[q][e], vti = ti[q][e], vbr = br[q][e], vbi = bi[q][e];
+          // v^H u = conj(v_t) u_t + conj(v_b) u_b
+          cvr = fma(vtr, utr[q][e], cvr); cvr = fma(vti, uti[q][e], cvr);
+          cvr = fma(vbr, ubr[q][e], cvr); cvr = fma(vbi, ubi[q][e], cvr);
+          cvi = fma(vtr, uti[q][e], cvi); cvi = fma(-vti, utr[q][e], cvi);
+          cvi = fma(vbr, ubi[q][e], cvi); cvi = fma(-vbi, ubr[q][e], cvi);
+          // w^H u = v_t u_b - v_b u_t
+          cwr = fma(vtr, ubr[q][e], cwr); cwr = fma(-vti, ubi[q][e], cwr);
+          cwr = fma(-vbr, utr[q][e], cwr); cwr = fma(vbi, uti[q][e], cwr);
+          cwi = fma(vtr, ubi[q][e], cwi); cwi = fma(vti, ubr[q][e], cwi);
+          cwi = fma(-vbr, uti[q][e], cwi); cwi = fma(-vbi, utr[q][e], cwi);
+        }
+      cvr = wave_sum(cvr); cvi = wave_sum(cvi); cwr = wave_sum(cwr); cwi = wave_sum(cwi);
+      if (lane == 0) {   // column c is only ever touched by this wavefront
+        acc[4 * c + 0] += cvr; acc[4 * c + 1] += cvi;
+        acc[4 * c + 2] += cwr; acc[4 * c + 3] += cwi;
+      }
+    }
+  }
+  if (wave == 0) {
+    unorm = wave_sum(unorm);
+    if (lane == 0) acc[4 * ncol] = unorm;
+  }
+  __syncthreads();
+  double* out = partial + (int64_t)blockIdx.x * (4 * ncol + 1);
+  for (int i = threadIdx.x; i < 4 * ncol + 1; i += kReorthThreads) out[i] = acc[i];
+}
+
+// u -= sum_c v_c cv_c + w_c cw_c; each lane keeps its pairs' corrections in
+// registers across the column loop.  partial[blk] = ||u_new||^2.
+template <typename S, int E>
+__global__ __launch_bounds__(kReorthThreads) void k_update(const cplx<S>* __restrict__ V,
+                                                           int64_t ldv, int ncol,
+                                                           cplx<S>* __restrict__ u, int64_t h,
+                                                           const double* __restrict__ coef,
+                                                           double* __restrict__ partial) {
+  constexpr int Q = kPairsPerLane / E;
+  constexpr int CH = 4 * 64 * E * Q;       // pairs per block
+  __shared__ double sh[4];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int64_t p0 = (int64_t)blockIdx.x * CH + (int64_t)wave * (64 * E * Q);
+  S dtr[Q][E], dti[Q][E], dbr[Q][E], dbi[Q][E];
+  bool ok[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    ok[q] = p0 + (int64_t)q * 64 * E + lane * E < h;
+#pragma unroll
+    for (int e = 0; e < E; ++e) dtr[q][e] = dti[q][e] = dbr[q][e] = dbi[q][e] = (S)0;
+  }
+  for (int c = 0; c < ncol; ++c) {
+    const S cvr = (S)coef[4 * c + 0], cvi = (S)coef[4 * c + 1];
+    const S cwr = (S)coef[4 * c + 2], cwi = (S)coef[4 * c + 3];
+    const cplx<S>* vt = V + (int64_t)c * ldv;
+    const cplx<S>* vb = vt + h;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if (!ok[q]) continue;
+      const int64_t p = p0 + (int64_t)q * 64 * E + lane * E;
+      S tr[E], ti[E], br[E], bi[E];
+      Ld<S, E>::get(vt + p, tr, ti);
+      Ld<S, E>::get(vb + p, br, bi);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        // d_top += v_t cv - conj(v_b) cw
+        dtr[q][e] = fma(tr[e], cvr, dtr[q][e]); dtr[q][e] = fma(-ti[e], cvi, dtr[q][e]);
+        dtr[q][e] = fma(-br[e], cwr, dtr[q][e]); dtr[q][e] = fma(-bi[e], cwi, dtr[q][e]);
+        dti[q][e] = fma(tr[e], cvi, dti[q][e]); dti[q][e] = fma(ti[e], cvr, dti[q][e]);
+        dti[q][e] = fma(-br[e], cwi, dti[q][e]); dti[q][e] = fma(bi[e], cwr, dti[q][e]);
+        // d_bot += v_b cv + conj(v_t) cw
+        dbr[q][e] = fma(br[e], cvr, dbr[q][e]); dbr[q][e] = fma(-bi[e], cvi, dbr[q][e]);
+        dbr[q][e] = fma(tr[e], cwr, dbr[q][e]); dbr[q][e] = fma(ti[e], cwi, dbr[q][e]);
+        dbi[q][e] = fma(br[e], cvi, dbi[q][e]); dbi[q][e] = fma(bi[e], cvr, dbi[q][e]);
+        dbi[q][e] = fma(tr[e], cwi, dbi[q][e]); dbi[q][e] = fma(-ti[e], cwr, dbi[q][e]);
+      }
+    }
+  }
+  double nrm = 0.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (!ok[q]) continue;
+    const int64_t p = p0 + (int64_t)q * 64 * E + lane * E;
+    S tr[E], ti[E], br[E], bi[E];
+    Ld<S, E>::get(u + p, tr, ti);
+    Ld<S, E>::get(u + h + p, br, bi);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      cplx<S> t, b;
+      t.x = tr[e] - dtr[q][e]; t.y = ti[e] - dti[q][e];
+      b.x = br[e] - dbr[q][e]; b.y = bi[e] - dbi[q][e];
+      u[p + e] = t;
+      u[h + p + e] = b;
+      nrm += (double)t.x * t.x + (double)t.y * t.y + (double)b.x * b.x + (double)b.y * b.y;
+    }
+  }
+  nrm = wave_sum(nrm);
+  if (lane == 0) sh[wave] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// out[c] = sum over b of partial[b*stride + c]; 64 columns x 4 block-groups.
+__global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ partial, int nblk,
+                                                     int stride, int ncols,
+                                                     double* __restrict__ out) {
+  __shared__ double sh[4][64];
+  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+  const int c = blockIdx.x * 64 + tx;
+  double s = 0.0;
+  if (c < ncols)
+    for (int b = ty; b < nblk; b += 4) s += partial[(int64_t)b * stride + c];
+  sh[ty][tx] = s;
+  __syncthreads();
+  if (ty == 0 && c < ncols) out[c] = (sh[0][tx] + sh[1][tx]) + (sh[2][tx] + sh[3][tx]);
+}
+
+template <typename S>
+__global__ void k_scale(cplx<S>* __restrict__ u, int64_t n, S s) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    cplx<S> v = u[i];
+    v.x *= s; v.y *= s;
+    u[i] = v;
+  }
+}
+
+template <typename S>
+__global__ void k_fill(cplx<S>* __restrict__ u, int64_t n, S val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    cplx<S> v;
+    v.x = val; v.y = (S)0;
+    u[i] = v;
+  }
+}
+
+// Y = J X^* = [-conj(X_bot); conj(X_top)]; safe in place (each thread reads
+// both halves of its pair before writing).
+template <typename S>
+__global__ void k_pair(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t ldy, int64_t h) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= h) return;
+  const cplx<S>* x = X + (int64_t)blockIdx.y * ldx;
+  cplx<S>* y = Y + (int64_t)blockIdx.y * ldy;
+  const cplx<S> t = x[p], b = x[h + p];
+  cplx<S> yt, yb;
+  yt.x = -b.x; yt.y = b.y;
+  yb.x = t.x; yb.y = -t.y;
+  y[p] = yt;
+  y[h + p] = yb;
+}
+
+template <typename S>
+__global__ void k_copy_cols(const cplx<S>* __restrict__ X, int64_t ldx, cplx<S>* __restrict__ Y,
+                            int64_t ldy, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) Y[(int64_t)blockIdx.y * ldy + i] = X[(int64_t)blockIdx.y * ldx + i];
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+int reorth_update_blocks(int64_t h) {
+  const int64_t per_block = (int64_t)4 * 64 * kPairsPerLane;
+  return (int)((h + per_block - 1) / per_block);
+}
+
+// Chunks per dots block so that about 2048 blocks cover the vector.
+static int dots_chunks(int64_t h) {
+  const int64_t ch = 64 * kPairsPerLane;
+  const int64_t nch = (h + ch - 1) / ch;
+  int64_t per = (nch + 2047) / 2048;
+  if (per < 1) per = 1;
+  return (int)per;
+}
+
+template <typename S>
+hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, const cplx<S>* u, int64_t h,
+                              double* partial, int nblk, hipStream_t st) {
+  if (ncol > kMaxCols) return hipErrorInvalidValue;
+  const int64_t ch = 64 * kPairsPerLane;
+  const int64_t nch = (h + ch - 1) / ch;
+  const int per = (int)((nch + nblk - 1) / nblk);
+  const unsigned grid = (unsigned)((nch + per - 1) / per);
+  if ((int)grid != nblk) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * (4 * (size_t)ncol + 1);
+  if (sizeof(S) == 4 && h % 2 == 0)
+    hipLaunchKernelGGL((k_dots<S, sizeof(S) == 4 ? 2 : 1>), dim3(grid), dim3(kReorthThreads), lds,
+                       st, V, ldv, ncol, u, h, per, partial);
+  else
+    hipLaunchKernelGGL((k_dots<S, 1>), dim3(grid), dim3(kReorthThreads), lds, st, V, ldv, ncol, u,
+                       h, per, partial);
+  return hipGetLastError();
+}
+
+// Number of dots blocks the driver must size the partial buffer for.
+int reorth_dots_blocks(int64_t h) {
+  const int64_t ch = 64 * kPairsPerLane;
+  const int64_t nch = (h + ch - 1) / ch;
+  const int per = dots_chunks(h);
+  return (int)((nch + per - 1) / per);
+}
+
+template <typename S>
+hipError_t launch_reorth_update(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
+                                const double* coef, double* partial, int nblk, hipStream_t st) {
+  const int64_t per_block = (int64_t)4 * 64 * kPairsPerLane;
+  const unsigned grid = (unsigned)((h + per_block - 1) / per_block);
+  if ((int)grid != nblk) return hipErrorInvalidValue;
+  if (sizeof(S) == 4 && h % 2 == 0)
+    hipLaunchKernelGGL((k_update<S, sizeof(S) == 4 ? 2 : 1>), dim3(grid), dim3(kReorthThreads), 0,
+                       st, V, ldv, ncol, u, h, coef, partial);
+  else
+    hipLaunchKernelGGL((k_update<S, 1>), dim3(grid), dim3(kReorthThreads), 0, st, V, ldv, ncol, u,
+                       h, coef, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int ncols, double* out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_cols, dim3(blocks_for(ncols, 64)), dim3(256), 0, st, partial, nblk,
+                     stride, ncols, out);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_scale(cplx<S>* u, int64_t n, double scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale<S>, dim3(blocks_for(n, 256)), dim3(256), 0, st, u, n, (S)scale);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_fill(cplx<S>* u, int64_t n, double value, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill<S>, dim3(blocks_for(n, 256)), dim3(256), 0, st, u, n, (S)value);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_pair(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t ldy, int64_t h, int k,
+                       hipStream_t st) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair<S>, dim3(blocks_for(h, 256), (unsigned)k), dim3(256), 0, st, X, ldx, Y,
+                     ldy, h);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t ldy, int64_t n,
+                            int k, hipStream_t st) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_cols<S>, dim3(blocks_for(n, 256), (unsigned)k), dim3(256), 0, st, X,
+                     ldx, Y, ldy, n);
+  return hipGetLastError();
+}
+
+#define JL_INST(S)                                                                                \
+  template hipError_t launch_reorth_dots<S>(const cplx<S>*, int64_t, int, const cplx<S>*, int64_t, \
+                                            double*, int, hipStream_t);                           \
+  template hipError_t launch_reorth_update<S>(const cplx<S>*, int64_t, int, cplx<S>*, int64_t,    \
+                                              const double*, double*, int, hipStream_t);          \
+  template hipError_t launch_scale<S>(cplx<S>*, int64_t, double, hipStream_t);                    \
+  template hipError_t launch_fill<S>(cplx<S>*, int64_t, double, hipStream_t);                     \
+  template hipError_t launch_pair<S>(const cplx<S>*, int64_t, cplx<S>*, int64_t, int64_t, int,    \
+                                     hipStream_t);                                                \
+  template hipError_t launch_copy_cols<S>(const cplx<S>*, int64_t, cplx<S>*, int64_t, int64_t,    \
+                                          int, hipStream_t);
+JL_INST(float)
+JL_INST(double)
+#undef JL_INST
+
+}  // namespace jl

@@ -1,0 +1,116 @@
+// C ABI of the individual iteration steps (include/jlanczos_kernels.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/jlanczos_kernels.h"
+#include "internal.h"
+
+using namespace jl;
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t reorth_ws(int64_t n, int ncol) {
+  const int64_t h = n / 2;
+  return align_up(sizeof(double) * (size_t)reorth_dots_blocks(h) * (4 * (size_t)ncol + 1)) +
+         align_up(sizeof(double) * (size_t)std::max(reorth_update_blocks(h), 1));
+}
+
+template <typename S>
+hipError_t reorth_pass(int64_t n, int ncol, const cplx<S>* V, int64_t ldv, cplx<S>* u, double* coef,
+                       char* ws, hipStream_t st) {
+  const int64_t h = n / 2;
+  const int nd = reorth_dots_blocks(h), nu = reorth_update_blocks(h);
+  double* dp = reinterpret_cast<double*>(ws);
+  double* up = reinterpret_cast<double*>(ws + align_up(sizeof(double) * (size_t)nd * (4 * (size_t)ncol + 1)));
+  const int stride = 4 * ncol + 1;
+  hipError_t e;
+  if ((e = launch_reorth_dots<S>(V, ldv, ncol, u, h, dp, nd, st)) != hipSuccess) return e;
+  if ((e = launch_reduce_cols(dp, nd, stride, stride, coef, st)) != hipSuccess) return e;
+  if ((e = launch_reorth_update<S>(V, ldv, ncol, u, h, coef, up, nu, st)) != hipSuccess) return e;
+  return launch_reduce_cols(up, nu, 1, 1, coef + 4 * ncol + 1, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+jl_status jl_reorth_pass_workspace_bytes(int64_t n, int32_t ncol, size_t* bytes) {
+  if (!bytes || n <= 0 || n % 2 || ncol < 0 || ncol >= kReorthMaxCols)
+    return set_err(nullptr, JL_EINVAL, "invalid reorth_pass sizes");
+  *bytes = reorth_ws(n, ncol);
+  return JL_OK;
+}
+
+jl_status jl_reorth_pass(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t ncol, const void* V,
+                         int64_t ldv, void* u, double* coef, void* ws, size_t ws_bytes) {
+  if (!ctx) return set_err(nullptr, JL_EINVAL, "ctx is NULL");
+  if (n <= 0 || n % 2 || ncol < 0 || ncol >= kReorthMaxCols || ldv < n || !u || !coef ||
+      (ncol > 0 && !V))
+    return set_err(ctx, JL_EINVAL, "invalid reorth_pass arguments");
+  if (!ws || ws_bytes < reorth_ws(n, ncol))
+    return set_err(ctx, JL_ENOMEM, "workspace too small (%zu < %zu)", ws_bytes, reorth_ws(n, ncol));
+  DeviceGuard g(ctx->device);
+  if (dtype == JL_C64)
+    JL_HIP(ctx, reorth_pass<float>(n, ncol, static_cast<const float2*>(V), ldv,
+                                   static_cast<float2*>(u), coef, static_cast<char*>(ws), ctx->stream));
+  else if (dtype == JL_C128)
+    JL_HIP(ctx, reorth_pass<double>(n, ncol, static_cast<const double2*>(V), ldv,
+                                    static_cast<double2*>(u), coef, static_cast<char*>(ws), ctx->stream));
+  else
+    return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
+  return JL_OK;
+}
+
+jl_status jl_ritz_workspace_bytes(int32_t m, size_t* bytes) {
+  if (!bytes || m < 1) return set_err(nullptr, JL_EINVAL, "invalid ritz size");
+  *bytes = sizeof(double) * (ritz_scratch_doubles(m) + (size_t)m);   // + zlast
+  return JL_OK;
+}
+
+jl_status jl_ritz(jl_ctx ctx, int32_t m, const double* T, int32_t which, double* lam, double* Z,
+                  void* ws, size_t ws_bytes) {
+  if (!ctx) return set_err(nullptr, JL_EINVAL, "ctx is NULL");
+  if (m < 1 || !T || !lam || !Z || (which != JL_LOWEST && which != JL_LARGEST))
+    return set_err(ctx, JL_EINVAL, "invalid ritz arguments");
+  const size_t need = sizeof(double) * (ritz_scratch_doubles(m) + (size_t)m);
+  if (!ws || ws_bytes < need) return set_err(ctx, JL_ENOMEM, "workspace too small (%zu < %zu)", ws_bytes, need);
+  DeviceGuard g(ctx->device);
+  std::vector<double> hT((size_t)m * m);
+  JL_HIP(ctx, hipMemcpyAsync(hT.data(), T, sizeof(double) * hT.size(), hipMemcpyDeviceToHost, ctx->stream));
+  JL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double fro2 = 0.0;
+  for (double v : hT) fro2 += v * v;
+  double* scratch = static_cast<double*>(ws);
+  double* zlast = scratch + ritz_scratch_doubles(m);
+  double hs = 0.0;
+  JL_HIP(ctx, ritz_device<double>(m, T, fro2, which == JL_LARGEST, 0, scratch, lam, Z, nullptr,
+                                  zlast, &hs, ctx->stream));
+  return JL_OK;
+}
+
+jl_status jl_basis_update(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t m, int32_t k,
+                          const void* V, int64_t ldv, const void* Z, int64_t ldz, void* Y,
+                          int64_t ldy) {
+  if (!ctx) return set_err(nullptr, JL_EINVAL, "ctx is NULL");
+  if (n <= 0 || n % 2 || m < 1 || k < 0 || ldv < n || ldy < n || ldz < m || (ldv % 2) ||
+      (ldy % 2) || (k > 0 && (!V || !Z || !Y)))
+    return set_err(ctx, JL_EINVAL, "invalid basis_update arguments");
+  if (k == 0) return JL_OK;
+  DeviceGuard g(ctx->device);
+  if (dtype == JL_C64)
+    JL_HIP(ctx, launch_gemm_nn<float>(static_cast<const float*>(V), 2 * ldv, static_cast<const float*>(Z),
+                                      ldz, static_cast<float*>(Y), 2 * ldy, 2 * n, k, m, ctx->stream));
+  else if (dtype == JL_C128)
+    JL_HIP(ctx, launch_gemm_nn<double>(static_cast<const double*>(V), 2 * ldv,
+                                       static_cast<const double*>(Z), ldz, static_cast<double*>(Y),
+                                       2 * ldy, 2 * n, k, m, ctx->stream));
+  else
+    return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
+  return JL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+"""Step-level parity of the HIP kernels against the FP64 oracle / NumPy
+(through the C ABI)."""
+import numpy as np
+import pytest
+
+from paper_2001_07428_amd import inputs
+from oracle import jsym
+
+from gpu_util import cdt, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2001_07428_amd import jlanczos as J
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return J.Context(0)
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# ------------------------------------------------------------------ operators
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (2, 3, 4, 5), (3, 2, 2, 7)])
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("b_per_site", [False, True])
+def test_stencil_apply(ctx, L, mixed, b_per_site):
+    from paper_2001_07428_amd import jlanczos as J
+    say("stencil_apply", L, mixed, b_per_site)
+    U, B = inputs.stencil_links(4, L, b_per_site=b_per_site)
+    n = 2 * int(np.prod(L)) * 4
+    X = inputs.cn(np.random.default_rng(3), (3, n))
+    dt = cdt(mixed)
+    op = J.jl_op_create_stencil(ctx, L, to_dev(U, dt), to_dev(B, dt))
+    Y = to_np(J.jl_op_apply(op, to_dev(X, dt)))
+    for r in range(3):
+        ref = jsym.stencil_apply(U, B, L, X[r])
+        assert _rel(Y[r], ref) < (2e-6 if mixed else 1e-14)
+
+
+@pytest.mark.parametrize("h", [100, 33, 1])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_dense_apply(ctx, h, mixed):
+    from paper_2001_07428_amd import jlanczos as J
+    say("dense_apply", h, mixed)
+    A11, A12 = inputs.dense_jsym(1, h)
+    A = jsym.dense_from_blocks(A11, A12)
+    X = inputs.cn(np.random.default_rng(4), (2, 2 * h))
+    dt = cdt(mixed)
+    op = J.jl_op_create_dense(ctx, to_dev(A11, dt), to_dev(A12, dt))
+    Y = to_np(J.jl_op_apply(op, to_dev(X, dt)))
+    for r in range(2):
+        assert _rel(Y[r], A @ X[r]) < (2e-6 if mixed else 1e-14)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_pair_vectors(ctx, mixed):
+    from paper_2001_07428_amd import jlanczos as J
+    say("pair_vectors", mixed)
+    X = inputs.cn(np.random.default_rng(5), (4, 202))
+    Y = to_np(J.jl_pair_vectors(ctx, to_dev(X, cdt(mixed))))
+    ref = jsym.partner(X.T).T
+    assert _rel(Y, ref) < (1e-7 if mixed else 0.0) + 1e-300
+    # in place
+    Xd = to_dev(X, cdt(mixed))
+    J.jl_pair_vectors(ctx, Xd, Xd)
+    assert _rel(to_np(Xd), ref) < (1e-7 if mixed else 0.0) + 1e-300
+
+
+# ----------------------------------------------------------- reorthogonalisation
+@pytest.mark.parametrize("h,ncol", [(1000, 7), (33, 5), (5000, 130), (4096, 1), (640, 0)])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_reorth_pass(ctx, h, ncol, mixed):
+    """One block Gram-Schmidt pass against [V, W = J V^*] (Alg. 2)."""
+    from paper_2001_07428_amd import jlanczos as J
+    say("reorth_pass", h, ncol, mixed)
+    rng = np.random.default_rng(6)
+    n = 2 * h
+    V = inputs.cn(rng, (ncol, n)) / np.sqrt(n)
+    u = inputs.cn(rng, n)
+    dt = cdt(mixed)
+    Vd, ud = to_dev(V, dt), to_dev(u, dt)
+    Vq, uq = to_np(Vd).astype(np.complex128), to_np(ud).astype(np.complex128)   # rounded inputs
+    coef = to_np(J.jl_reorth_pass(ctx, Vd if ncol else None, ud))
+    W = jsym.partner(Vq.T).T
+    cv = Vq.conj() @ uq
+    cw = W.conj() @ uq
+    got_cv = coef[0:4 * ncol:4] + 1j * coef[1:4 * ncol:4]
+    got_cw = coef[2:4 * ncol:4] + 1j * coef[3:4 * ncol:4]
+    scale = np.linalg.norm(uq) * np.abs(Vq).max() * np.sqrt(n)
+    if ncol:
+        assert np.abs(got_cv - cv).max() < 1e-13 * scale
+        assert np.abs(got_cw - cw).max() < 1e-13 * scale
+    assert abs(coef[4 * ncol] - np.vdot(uq, uq).real) < 1e-12 * np.vdot(uq, uq).real
+    unew = uq - cv @ Vq - cw @ W
+    got = to_np(ud).astype(np.complex128)
+    tol = 1e-6 if mixed else 1e-13
+    assert np.abs(got - unew).max() < tol * np.abs(uq).max()
+    assert abs(coef[4 * ncol + 1] - np.vdot(got, got).real) < 1e-12 * max(np.vdot(got, got).real, 1e-300)
+
+
+# ------------------------------------------------------------------ Ritz step
+def _arrow(rng, m, k):
+    """Thick-restart projected matrix: diag(theta) (k), arrow row k, then a
+    tridiagonal tail; a few arrow entries are exactly zero (decoupled)."""
+    T = np.zeros((m, m))
+    T[np.arange(k), np.arange(k)] = np.sort(rng.standard_normal(k))
+    s = rng.standard_normal(k) * 0.3
+    s[::3] = 0.0
+    T[k, :k] = s
+    T[:k, k] = s
+    a = rng.standard_normal(m - k) * 2
+    b = np.abs(rng.standard_normal(m - k - 1)) + 0.1
+    T[np.arange(k, m), np.arange(k, m)] = a
+    T[np.arange(k + 1, m), np.arange(k, m - 1)] = b
+    T[np.arange(k, m - 1), np.arange(k + 1, m)] = b
+    return T
+
+
+@pytest.mark.parametrize("m", [1, 2, 10, 41, 59, 60, 61, 160, 301])
+@pytest.mark.parametrize("which", ["lowest", "largest"])
+def test_ritz(ctx, m, which):
+    """T = Z diag(lam) Z^T (Alg. 1), sorted, vs numpy eigh."""
+    import torch
+    from paper_2001_07428_amd import jlanczos as J
+    say("ritz", m, which)
+    rng = np.random.default_rng(m)
+    G = rng.standard_normal((m, m))
+    for T in (G + G.T, _arrow(rng, m, m // 2) if m > 3 else G + G.T):
+        lam, Z = J.jl_ritz(ctx, torch.from_numpy(T).cuda(), which)
+        lam, Z = to_np(lam), to_np(Z)
+        ref = np.linalg.eigvalsh(T)
+        if which == "largest":
+            ref = ref[::-1]
+        nrm = np.linalg.norm(T, 2)
+        assert np.abs(lam - ref).max() < 1e-13 * nrm * max(1, np.sqrt(m) / 4)
+        assert np.abs(T @ Z - Z * lam[None, :]).max() < 1e-12 * nrm
+        assert np.abs(Z.T @ Z - np.eye(m)).max() < 1e-12
+
+
+# -------------------------------------------------------------- restart GEMM
+@pytest.mark.parametrize("h,m,k", [(1000, 37, 29), (2048, 160, 130), (50, 3, 3), (3000, 129, 1),
+                                   (6144, 300, 250)])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_basis_update(ctx, h, m, k, mixed):
+    """V_k = V_m Z[:, :k] (Alg. 1) as a real GEMM on the interleaved basis."""
+    from paper_2001_07428_amd import jlanczos as J
+    say("basis_update", h, m, k, mixed)
+    rng = np.random.default_rng(7)
+    V = inputs.cn(rng, (m, 2 * h))
+    Z = rng.standard_normal((m, k))
+    dt = cdt(mixed)
+    Vd = to_dev(V, dt)
+    import torch
+    Zd = torch.from_numpy(Z).cuda()
+    Y = to_np(J.jl_basis_update(ctx, Vd, Zd)).astype(np.complex128)
+    Vq = to_np(Vd).astype(np.complex128)
+    Zq = Z.astype(np.float32).astype(np.float64) if mixed else Z
+    ref = Zq.T @ Vq
+    err = np.abs(Y - ref).max() / (np.abs(Vq).max() * np.abs(Zq).sum(0).max())
+    assert err < (1e-6 if mixed else 1e-14)

@@ -1,0 +1,188 @@
+"""Whole-solve parity of the HIP TRLAN-JSYM against the FP64 oracle (same
+seeded inputs, same start vector), through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_2001_07428_amd import inputs
+from oracle import casea, jsym, trlan
+
+from gpu_util import cdt, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2001_07428_amd import jlanczos as J
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return J.Context(0)
+
+
+def _check_pairs(apply, X, ev, tol_res, tol_orth):
+    """Residuals of x and of its partner J x^*, and [X, J X^*] orthonormal."""
+    Y = jsym.partner(X.T)
+    for i in range(X.shape[0]):
+        assert np.linalg.norm(apply(X[i]) - ev[i] * X[i]) < tol_res
+        assert np.linalg.norm(apply(Y[:, i]) - ev[i] * Y[:, i]) < tol_res
+    UU = np.concatenate([X.T, Y], axis=1)
+    assert np.abs(UU.conj().T @ UU - np.eye(UU.shape[1])).max() < tol_orth
+
+
+def _releig(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+# --------------------------------------------------------------- dense, n=200
+def test_dense_n200_fp64_vs_oracle(ctx):
+    """n=200, 10 lowest pairs, m=40, mwin=20, tol 1e-10, FP64."""
+    from paper_2001_07428_amd import jlanczos as J
+    say("dense n200 fp64")
+    A11, A12 = inputs.dense_jsym(1, 100)
+    A = jsym.dense_from_blocks(A11, A12)
+    ref = trlan.trlan_jsym(lambda v: A @ v, 200, 10, 20, 40, 1e-10, trace_cap=30)
+    op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(False)), to_dev(A12, cdt(False)))
+    out = J.jl_solve(op, 10, 40, 20, 1e-10, trace_cap=30)
+    assert out.status == J.JL_OK
+    assert _releig(out.evals, ref["ev"]) < 1e-10
+    assert (out.res < 1e-10).all()
+    # alpha/beta of the first 30 Lanczos steps (same v_1)
+    assert _releig(out.trace_alpha, ref["alpha"]) < 1e-10
+    assert _releig(out.trace_beta, ref["beta"]) < 1e-10
+    # same restart count within one cycle, MV count within one cycle's steps
+    assert abs(out.stats["cycles"] - ref["n_conv"]) <= 1
+    X = to_np(out.X)
+    _check_pairs(lambda v: A @ v, X, out.evals, 1e-10, 1e-12)
+    bf, _ = jsym.brute(A)
+    assert _releig(out.evals, bf[:10]) < 1e-10
+
+
+def test_dense_n200_mixed(ctx):
+    from paper_2001_07428_amd import jlanczos as J
+    say("dense n200 mixed")
+    A11, A12 = inputs.dense_jsym(1, 100)
+    A = jsym.dense_from_blocks(A11, A12)
+    bf, _ = jsym.brute(A)
+    op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(True)), to_dev(A12, cdt(True)))
+    out = J.jl_solve(op, 10, 40, 20, 1e-4)
+    assert out.status == J.JL_OK
+    assert _releig(out.evals, bf[:10]) < 1e-5
+    X = to_np(out.X).astype(np.complex128)
+    _check_pairs(lambda v: A @ v, X, out.evals, 2e-4, 1e-5)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_dense_n4096(ctx, mixed):
+    """n=4096, 50 lowest pairs, m=160, mwin=80; tol 1e-10 (FP64) / 1e-5 (mixed)."""
+    from paper_2001_07428_amd import jlanczos as J
+    say("dense n4096", mixed)
+    A11, A12 = inputs.dense_jsym(2, 2048)
+    A = jsym.dense_from_blocks(A11, A12)
+    op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(mixed)), to_dev(A12, cdt(mixed)))
+    tol = 1e-5 if mixed else 1e-10
+    out = J.jl_solve(op, 50, 160, 80, tol, max_cycles=200)
+    assert out.status == J.JL_OK, out.stats
+    ev = np.linalg.eigvalsh(A)[0::2][:50]
+    assert _releig(out.evals, ev) < (1e-5 if mixed else 1e-10)
+    X = to_np(out.X).astype(np.complex128)
+    R = A @ X.T - X.T * out.evals[None, :]
+    assert np.linalg.norm(R, axis=0).max() < tol * 1.01
+
+
+# ------------------------------------------------------------------- stencil
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (3, 4, 2, 5)])
+def test_stencil_fp64_vs_oracle(ctx, L):
+    from paper_2001_07428_amd import jlanczos as J
+    say("stencil fp64", L)
+    U, B = inputs.stencil_links(4, L)
+    n = 2 * int(np.prod(L)) * 4
+    f = lambda v: jsym.stencil_apply(U, B, L, v)
+    ref = trlan.trlan_jsym(f, n, 8, 16, 48, 1e-10)
+    assert ref["status"] == "ok"
+    op = J.jl_op_create_stencil(ctx, L, to_dev(U, cdt(False)), to_dev(B, cdt(False)))
+    out = J.jl_solve(op, 8, 48, 16, 1e-10)
+    assert out.status == J.JL_OK
+    assert _releig(out.evals, ref["ev"]) < 1e-10
+    _check_pairs(f, to_np(out.X), out.evals, 1e-10, 1e-12)
+
+
+def test_stencil_mixed_vs_oracle(ctx):
+    from paper_2001_07428_amd import jlanczos as J
+    L = (4, 4, 4, 4)
+    say("stencil mixed", L)
+    U, B = inputs.stencil_links(4, L)
+    n = 2 * 256 * 4
+    f = lambda v: jsym.stencil_apply(U, B, L, v)
+    ref = trlan.trlan_jsym(f, n, 8, 16, 48, 1e-10)
+    op = J.jl_op_create_stencil(ctx, L, to_dev(U, cdt(True)), to_dev(B, cdt(True)))
+    out = J.jl_solve(op, 8, 48, 16, 1e-5)
+    assert out.status == J.JL_OK
+    assert _releig(out.evals, ref["ev"]) < 1e-5
+    X = to_np(out.X).astype(np.complex128)
+    _check_pairs(f, X, out.evals, 1.2e-5, 1e-5)
+
+
+def test_constant_links_closed_form(ctx):
+    """Translation-invariant stencil, random start: the lowest pairs equal the
+    Fourier closed form (independent of the oracle's Lanczos)."""
+    from paper_2001_07428_amd import jlanczos as J
+    L = (6, 6, 6, 6)
+    say("constant links", L)
+    Uc, B, U = inputs.constant_links(6, L)
+    n = 2 * 1296 * 4
+    cf, _ = jsym.pair_eigenvalues(jsym.constant_link_spectrum(Uc, B, L))
+    op = J.jl_op_create_stencil(ctx, L, to_dev(U, cdt(False)), to_dev(B, cdt(False)))
+    v1 = to_dev(inputs.random_start(7, n), cdt(False))
+    out = J.jl_solve(op, 10, 60, 20, 1e-10, v1=v1)
+    assert out.status == J.JL_OK
+    assert np.abs(out.evals - cf[:10]).max() < 1e-10 * np.abs(cf).max()
+
+
+def test_casea_largest(ctx):
+    """Known spectrum (Case A recipe), largest end."""
+    from paper_2001_07428_amd import jlanczos as J
+    say("casea largest")
+    A11, A12, lam, _ = casea.known_spectrum(8, 400)
+    op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(False)), to_dev(A12, cdt(False)))
+    out = J.jl_solve(op, 10, 50, 20, 1e-12, which="largest")
+    assert out.status == J.JL_OK
+    assert np.abs(out.evals - lam[::-1][:10]).max() < 1e-12
+
+
+def test_exhausted_half_space(ctx):
+    """n=64, m=32 = n/2: one cycle spans the J-half Krylov space (Sec. 2)."""
+    from paper_2001_07428_amd import jlanczos as J
+    say("exhausted n64 m32")
+    A11, A12 = inputs.dense_jsym(9, 32)
+    A = jsym.dense_from_blocks(A11, A12)
+    bf, _ = jsym.brute(A)
+    for mixed in (False, True):
+        op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(mixed)), to_dev(A12, cdt(mixed)))
+        out = J.jl_solve(op, 8, 32, 16, 1e-4 if mixed else 1e-8)
+        assert out.status == J.JL_OK and out.stats["cycles"] == 1
+        assert _releig(out.evals, bf[:8]) < (1e-5 if mixed else 1e-10)
+
+
+def test_breakdown_reported(ctx):
+    """All-ones start on the constant-link stencil spans an invariant
+    subspace (the k = 0 Fourier sector): breakdown is reported."""
+    from paper_2001_07428_amd import jlanczos as J
+    L = (3, 3, 3, 3)
+    say("breakdown", L)
+    Uc, B, U = inputs.constant_links(6, L)
+    op = J.jl_op_create_stencil(ctx, L, to_dev(U, cdt(False)), to_dev(B, cdt(False)))
+    out = J.jl_solve(op, 8, 40, 16, 1e-10)
+    assert out.status == J.JL_BREAKDOWN
+
+
+def test_invalid_arguments(ctx):
+    from paper_2001_07428_amd import jlanczos as J
+    say("invalid args")
+    A11, A12 = inputs.dense_jsym(1, 10)
+    op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(False)), to_dev(A12, cdt(False)))
+    for args in [(2, 11, 4), (5, 8, 4), (2, 8, 8), (0, 8, 4)]:   # m > n/2, nev > mwin, mwin >= m, nev < 1
+        with pytest.raises(J.JLError) as e:
+            J.jl_solve(op, *args, 1e-10)
+        assert e.value.status == J.JL_EINVAL
+    with pytest.raises(J.JLError):
+        J.jl_solve(op, 2, 8, 4, -1.0)
