@@ -103,12 +103,16 @@ typedef struct {
   int32_t m;            /* maximum Krylov dimension (mwin < m <= n/2)          */
   int32_t mwin;         /* restart window: k = min(icnv + mwin, m - 1)         */
   int32_t which;        /* jl_which                                            */
-  double tol;           /* absolute residual tolerance ||A x - lambda x|| < tol */
+  double tol;           /* residual tolerance: ||A x - lambda x|| < tol          */
+  int32_t tol_relative; /* nonzero: the tolerance is tol * max_i |theta_i| over
+                           the current Ritz values (an estimate of ||A||_2)    */
   int32_t max_cycles;   /* outer-iteration cap (<= 0: 10000)                   */
   int32_t max_passes;   /* reorthogonalisation passes per step cap (<= 0: 16)  */
+  int32_t min_passes;   /* passes before the sqrt(2) test applies (<= 0: 1)    */
   int32_t timing;       /* nonzero: time each kernel class with HIP events     */
   int32_t trace_cap;    /* record alpha_j, beta_j of the first trace_cap steps */
   double* trace_ab;     /* host [2 * trace_cap]: alpha then beta (may be NULL) */
+  int32_t verbose;      /* nonzero: one progress line per cycle on stderr      */
 } jl_params;
 
 typedef struct {
@@ -118,6 +122,7 @@ typedef struct {
   int32_t gs_passes;    /* reorthogonalisation passes over all steps            */
   int32_t icnv;         /* converged pairs at return                            */
   int32_t status;       /* same as the return value of jl_solve                 */
+  int64_t sum_ncol;     /* sum over Lanczos steps of the basis width j + 1      */
   /* Per kernel class (only with params.timing): accumulated GPU time [s],
    * launch count and algorithmic bytes (or flops for the GEMM). */
   double t_total;       /* wall time of jl_solve [s] (always set)               */
@@ -130,6 +135,11 @@ typedef struct {
 jl_status jl_workspace_bytes(jl_op op, const jl_params* p, size_t* bytes);
 
 /* Thick-restart J-Lanczos (Algorithm 1 with Algorithm 2 as its inner step).
+ * Each step subtracts the three-term recurrence t_jj v_j + beta_{j-1} v_{j-1}
+ * (t_jj alone on the first step after a restart) before the iterated
+ * Gram-Schmidt against [V_j, J V_j^*] of Alg. 2; the loop stops when
+ * sqrt(2) * (norm after a pass) > (norm before it), the norm before the first
+ * pass being the one after the local step.
  *  v1      device start vector (n, op dtype) or NULL for the all-ones vector
  *          the paper uses; it is normalised internally.
  *  ws      device workspace of ws_bytes >= jl_workspace_bytes.

@@ -39,9 +39,10 @@ jl_status jl_ritz(jl_ctx ctx, int32_t m, const double* T, int32_t which, double*
 
 /* Thick-restart basis update of Alg. 1 (V_m := V_m Z_m, first k columns):
  * Y = V Z with V (device, n x m complex, leading dimension ldv, dtype), Z
- * (device, m x k real column-major, leading dimension ldz, FP32 for JL_C64,
- * FP64 for JL_C128) and Y (device, n x k, leading dimension ldy).  Y must not
- * overlap V.  ldv and ldy must be even (16-byte aligned columns).
+ * (device, m x k real FP64 column-major, leading dimension ldz) and Y
+ * (device, n x k, leading dimension ldy, dtype).  Accumulation is FP64 for
+ * both dtypes (FP32 inputs are widened, the result is rounded once).  Y must
+ * not overlap V.  ldv and ldy must be even (16-byte aligned columns).
  * Errors: JL_EINVAL. */
 jl_status jl_basis_update(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t m, int32_t k,
                           const void* V, int64_t ldv, const void* Z, int64_t ldz, void* Y,

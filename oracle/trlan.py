@@ -23,6 +23,10 @@ with 0-based indices: V has columns v_0..v_m, the projected matrix Tbar is
   dimension, the coupling to v_{m+1}
   is zero, and every candidate's true residual is checked; if not all nev
   pairs converge the solve stops with status "breakdown".
+* tol is absolute as in the paper; tol_relative=True scales it by the largest
+  |Ritz value| of the cycle (an estimate of ||A||_2).
+* min_passes > 1 takes the sqrt(2) test only from that pass on (default 1,
+  the paper's rule; the FP32-storage GPU solver uses 2).
 * The J-restriction uses w_i = J v_i^* (Alg. 2 builds W alongside V).  With
   jsym=False the W-projections are dropped, giving the standard TRLAN that the
   paper compares against (Sec. 3).
@@ -42,7 +46,8 @@ def _w(v):
     return J_apply(np.conj(v))
 
 
-def lanczos_jsym(apply, V, T, k, m, stats, jsym=True, breakdown_tol_fn=None, trace=None):
+def lanczos_jsym(apply, V, T, k, m, stats, jsym=True, breakdown_tol_fn=None, trace=None,
+                 min_passes=1):
     """Algorithm 2: extend the decomposition from dimension k to m.
 
     V: (n, m+1) complex128 with v_0..v_k valid; T: (m+1, m) real with rows
@@ -58,6 +63,7 @@ def lanczos_jsym(apply, V, T, k, m, stats, jsym=True, breakdown_tol_fn=None, tra
         u = u - V[:, j] * t
         b0 = np.linalg.norm(u)
         tolb = breakdown_tol_fn(T, j) if breakdown_tol_fn is not None else 0.0
+        stats["_p"] = 0
         while True:                              # iterated Gram-Schmidt
             for i in range(j + 1):
                 if jsym:
@@ -68,7 +74,9 @@ def lanczos_jsym(apply, V, T, k, m, stats, jsym=True, breakdown_tol_fn=None, tra
                 u = u - V[:, i] * c
             b1 = np.linalg.norm(u)
             stats["gs_passes"] += 1
-            if b1 * gamma > b0 or b1 <= tolb:
+            passes = stats.setdefault("_p", 0) + 1
+            stats["_p"] = passes
+            if (passes >= min_passes and b1 * gamma > b0) or b1 <= tolb:
                 break
             b0 = b1
         if trace is not None and len(trace["alpha"]) < trace["cap"]:
@@ -91,7 +99,7 @@ def _sym_T(T, m):
 def trlan_jsym(apply, n, nev, mwin, m, tol, which="lowest", v1=None,
                max_cycles=100000, jsym=True, unit_roundoff=2.0 ** -53,
                breakdown_factor=64.0, trace_cap=0, record_history=False,
-               time_limit=None, on_cycle=None):
+               time_limit=None, on_cycle=None, min_passes=1, tol_relative=False):
     """Algorithm 1: thick-restart Lanczos for a Hermitian J-symmetric A.
 
     apply(v) -> A v.  Returns a dict with ev (nev, desired order), X (n, nev),
@@ -122,7 +130,7 @@ def trlan_jsym(apply, n, nev, mwin, m, tol, which="lowest", v1=None,
     for cycle in range(max_cycles):
         stats["n_conv"] += 1
         meff, broke = lanczos_jsym(apply, V, T, k, m, stats, jsym=jsym,
-                                   breakdown_tol_fn=btol, trace=trace)
+                                   breakdown_tol_fn=btol, trace=trace, min_passes=min_passes)
         if meff < nev:                           # invariant subspace too small
             status = "breakdown"
             ev = np.full(nev, np.nan)
@@ -140,12 +148,13 @@ def trlan_jsym(apply, n, nev, mwin, m, tol, which="lowest", v1=None,
         res_est = np.abs(s[:nev])
         res = np.full(nev, np.inf)
         is_convd = np.zeros(nev, dtype=bool)
+        tol_c = tol * np.abs(lam).max() if tol_relative else tol
         for i in range(nev):
-            if res_est[i] < tol:                 # check true residuals
+            if res_est[i] < tol_c:               # check true residuals
                 r = apply(V[:, i]) - V[:, i] * ev[i]
                 stats["n_resid_mv"] += 1
                 res[i] = np.linalg.norm(r)
-                is_convd[i] = res[i] < tol
+                is_convd[i] = res[i] < tol_c
         # converged first, desired order kept (stable partition)
         perm = np.concatenate([np.flatnonzero(is_convd), np.flatnonzero(~is_convd),
                                np.arange(nev, meff)]).astype(int)
@@ -175,6 +184,7 @@ def trlan_jsym(apply, n, nev, mwin, m, tol, which="lowest", v1=None,
         V[:, k] = V[:, meff]
         if on_cycle is not None:
             on_cycle(V, T, k)
+    stats.pop("_p", None)
     out = dict(ev=ev, X=V[:, :nev].copy(), res=res, status=status, icnv=icnv,
                history=history, **stats)
     if trace is not None:

@@ -35,10 +35,13 @@ template <typename S> struct StencilArgs {
   double scale;
 };
 
-// y = A x for nrhs columns (ld = n), compute type = S.
+// y = A x for nrhs columns (ld = n), compute type = S.  With apart !=
+// nullptr (nrhs == 1) each block also writes the FP64 partial sum of x^H y
+// to apart[2*blk], apart[2*blk+1] (stencil_apply_blocks blocks).
 template <typename S>
 hipError_t launch_stencil_apply(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
-                                int nrhs, hipStream_t st);
+                                int nrhs, double* apart, hipStream_t st);
+int stencil_apply_blocks(int64_t V);
 // Per-block partial sums of ||A x_c - lam_c x_c||^2 (FP64 compute) for ncols
 // columns x_c = X + cols[c]*ldx (cols, lam on the device); partial layout
 // [blk][c]; *nblk = blocks per column.
@@ -57,7 +60,8 @@ template <typename S> struct DenseArgs {
 };
 template <typename S>
 hipError_t launch_dense_apply(const DenseArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ldv,
-                              int nrhs, hipStream_t st);
+                              int nrhs, double* apart, hipStream_t st);
+int dense_apply_blocks(int64_t h);
 template <typename S>
 hipError_t launch_dense_resid(const DenseArgs<S>& a, const cplx<S>* X, int64_t ldx,
                               const int* cols, const double* lam, int ncols, double* partial,
@@ -69,11 +73,16 @@ int dense_resid_blocks(int64_t h);
 // dots: partial[blk][4*ncol + 1] = per block (Re, Im of v_i^H u, Re, Im of
 // w_i^H u) for each column, then ||u||^2.
 int reorth_dots_blocks(int64_t h);     // partial rows written by dots
-int reorth_update_blocks(int64_t h);   // partial entries written by update
+int reorth_update_blocks(int64_t h, int es);   // partial entries written by update (es: bytes per complex)
 constexpr int kReorthMaxCols = 2048;   // largest basis dots supports
+// With tloc != nullptr the kernel first applies the local three-term step
+// u <- u - t v_jl - beta v_{jl-1} (t = tloc[0] + i tloc[1] on the device,
+// beta = 0 skips the second term), rounds u once to S, stores it, and then
+// takes the inner products of the new u.
 template <typename S>
-hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, const cplx<S>* u, int64_t h,
-                              double* partial, int nblk, hipStream_t st);
+hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
+                              double* partial, int nblk, hipStream_t st,
+                              const double* tloc = nullptr, double beta = 0.0, int jl = 0);
 // update: u -= V c_v + W c_w (W = J V^*), coef = [4*ncol] FP64 (Re cv, Im cv,
 // Re cw, Im cw per column); partial[blk] = ||u_new||^2 per block.
 template <typename S>
@@ -98,9 +107,11 @@ hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t l
                             int k, hipStream_t st);
 
 // ------------------------------------------------------------ restart GEMM
-// C (M x N, ldc) = A (M x K, lda) * B (K x N, ldb), real, column-major.
-template <typename S>
-hipError_t launch_gemm_nn(const S* A, int64_t lda, const S* B, int64_t ldb, S* C, int64_t ldc,
+// C (M x N, ldc) = A (M x K, lda) * B (K x N, ldb), real, column-major; A
+// and C of storage type S, B and the MFMA accumulation of type T
+// (instantiated: <float,double>, <double,double>).
+template <typename S, typename T>
+hipError_t launch_gemm_nn(const S* A, int64_t lda, const T* B, int64_t ldb, S* C, int64_t ldc,
                           int64_t M, int N, int K, hipStream_t st);
 
 // ------------------------------------------------------- Ritz eigenproblem

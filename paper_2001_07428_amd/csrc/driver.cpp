@@ -4,9 +4,10 @@
 // (the J-restricted Lanczos steps) as its inner loop; every vector operation
 // is a kernel on the context's stream and the host only handles the m x m
 // projected matrix bookkeeping and a few scalars per step:
-//   - alpha_j and the norm b0 after the alpha step (read after the first
-//     inner-product pass), and the norm b1 after each reorthogonalisation
-//     pass (the sqrt(2) test of Alg. 2 is taken on the host);
+//   - per Lanczos step: t_jj (accumulated in the operator apply), the norm
+//     b0 after the local three-term step and the norm b1 after each
+//     reorthogonalisation pass (the sqrt(2) test of Alg. 2 is taken on the
+//     host); one stream synchronisation per pass;
 //   - once per cycle the sorted Ritz values, the last row of Z and the true
 //     residuals of the candidates.
 #include <hip/hip_runtime.h>
@@ -130,9 +131,10 @@ template <> struct OpView<double> {
 
 template <typename S>
 hipError_t op_apply(const jl_op_s* op, const cplx<S>* x, cplx<S>* y, int64_t ld, int nrhs,
-                    hipStream_t st) {
-  if (op->kind == OP_STENCIL) return launch_stencil_apply<S>(OpView<S>::st(op), x, y, ld, nrhs, st);
-  return launch_dense_apply<S>(OpView<S>::de(op), x, y, ld, nrhs, st);
+                    double* apart, hipStream_t st) {
+  if (op->kind == OP_STENCIL)
+    return launch_stencil_apply<S>(OpView<S>::st(op), x, y, ld, nrhs, apart, st);
+  return launch_dense_apply<S>(OpView<S>::de(op), x, y, ld, nrhs, apart, st);
 }
 
 template <typename S>
@@ -141,6 +143,10 @@ hipError_t op_resid(const jl_op_s* op, const cplx<S>* X, int64_t ldx, const int*
   if (op->kind == OP_STENCIL)
     return launch_stencil_resid<S>(OpView<S>::st(op), X, ldx, cols, lam, ncols, partial, nblk, st);
   return launch_dense_resid<S>(OpView<S>::de(op), X, ldx, cols, lam, ncols, partial, nblk, st);
+}
+
+int op_apply_blocks(const jl_op_s* op) {
+  return op->kind == OP_STENCIL ? stencil_apply_blocks(op->n / 8) : dense_apply_blocks(op->n / 2);
 }
 
 int op_resid_blocks(const jl_op_s* op) {
@@ -160,7 +166,7 @@ double op_bytes(const jl_op_s* op, int es) {
 
 // ----------------------------------------------------------- workspace layout
 struct Layout {
-  size_t V[2], dots_part, upd_part, coef, scal, Tdev, ritz, lam_s, Zs, Zc, zlast, res_part,
+  size_t V[2], apart, dots_part, upd_part, coef, scal, Tdev, ritz, lam_s, Zs, zlast, res_part,
       res_out, res_lam, res_cols, total;
 };
 
@@ -170,7 +176,6 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   const int es = op->dtype == JL_C64 ? 8 : 16;   // bytes per complex element
   const int64_t n = op->n, h = n / 2;
   const int m = p->m;
-  const int kmax = std::min(p->nev + p->mwin, m - 1);
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -180,15 +185,15 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   };
   L.V[0] = take((size_t)n * (m + 1) * es);
   L.V[1] = take((size_t)n * (m + 1) * es);
+  L.apart = take(sizeof(double) * 2 * (size_t)op_apply_blocks(op));
   L.dots_part = take(sizeof(double) * (size_t)reorth_dots_blocks(h) * (4 * (size_t)(m + 1) + 1));
-  L.upd_part = take(sizeof(double) * (size_t)std::max(reorth_update_blocks(h), 1));
+  L.upd_part = take(sizeof(double) * (size_t)std::max(reorth_update_blocks(h, es), 1));
   L.coef = take(sizeof(double) * (4 * (size_t)(m + 1) + 1));
   L.scal = take(sizeof(double) * 64);
   L.Tdev = take(sizeof(double) * (size_t)m * m);
   L.ritz = take(sizeof(double) * ritz_scratch_doubles(m));
   L.lam_s = take(sizeof(double) * m);
   L.Zs = take(sizeof(double) * (size_t)m * m);
-  L.Zc = take((size_t)(es / 2) * (size_t)m * kmax);
   L.zlast = take(sizeof(double) * m);
   L.res_part = take(sizeof(double) * (size_t)op_resid_blocks(op) * p->nev);
   L.res_out = take(sizeof(double) * p->nev);
@@ -294,6 +299,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   const int kmax = std::min(nev + mwin, m - 1);
   const int max_cycles = prm->max_cycles > 0 ? prm->max_cycles : 10000;
   const int max_passes = prm->max_passes > 0 ? prm->max_passes : 16;
+  const int min_passes = std::min(prm->min_passes > 0 ? prm->min_passes : 1, max_passes);
   const int es = (int)sizeof(cplx<S>);
   const double uround = sizeof(S) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
   const double bd_factor = 64.0;
@@ -308,6 +314,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   char* base = static_cast<char*>(ws);
   cplx<S>* Vb[2] = {reinterpret_cast<cplx<S>*>(base + L.V[0]),
                     reinterpret_cast<cplx<S>*>(base + L.V[1])};
+  double* apart = reinterpret_cast<double*>(base + L.apart);
   double* dots_part = reinterpret_cast<double*>(base + L.dots_part);
   double* upd_part = reinterpret_cast<double*>(base + L.upd_part);
   double* coef = reinterpret_cast<double*>(base + L.coef);
@@ -316,7 +323,6 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   double* ritz_scr = reinterpret_cast<double*>(base + L.ritz);
   double* lam_s = reinterpret_cast<double*>(base + L.lam_s);
   double* Zs = reinterpret_cast<double*>(base + L.Zs);
-  S* Zc = reinterpret_cast<S*>(base + L.Zc);
   double* zlast = reinterpret_cast<double*>(base + L.zlast);
   double* res_part = reinterpret_cast<double*>(base + L.res_part);
   double* res_dev = reinterpret_cast<double*>(base + L.res_out);
@@ -324,7 +330,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   int* res_cols = reinterpret_cast<int*>(base + L.res_cols);
 
   const int ndots = reorth_dots_blocks(h);
-  const int nupd = reorth_update_blocks(h);
+  const int napply = op_apply_blocks(op);
+  const int nupd = reorth_update_blocks(h, es);
   const int64_t ldv = n;
 
   Pinned pin;
@@ -381,48 +388,45 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     for (int j = k; j < m; ++j) {
       cplx<S>* vj = V + (int64_t)j * ldv;
       cplx<S>* u = V + (int64_t)(j + 1) * ldv;
-      tm.start(Timer::MATVEC);
-      JL_HIP(ctx, op_apply<S>(op, vj, u, ldv, 1, st));
-      tm.stop();
-      S_.n_mv++;
-      S_.n_matvec_launch++;
-      S_.bytes_matvec += op_bytes(op, es);
       const int ncol = j + 1;
       const int stride = 4 * ncol + 1;
-      // first pass inner products against [V_j, W_j] (includes t_jj = v_j^H u)
+      // u = A v_j, with the block partial sums of t_jj = v_j^H u
+      tm.start(Timer::MATVEC);
+      JL_HIP(ctx, op_apply<S>(op, vj, u, ldv, 1, apart, st));
+      tm.stop();
+      JL_HIP(ctx, launch_reduce_cols(apart, napply, 2, 2, scal, st));
+      S_.n_mv++;
+      S_.sum_ncol += ncol;
+      S_.n_matvec_launch++;
+      S_.bytes_matvec += op_bytes(op, es);
+      // local three-term step u -= t_jj v_j + beta_{j-1} v_{j-1} fused into the
+      // first inner products against [V_j, W_j]; then the first update pass
+      const double beta_prev = (j > k) ? Tat(j, j - 1) : 0.0;
       tm.start(Timer::DOTS);
-      JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st));
+      JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st, scal, beta_prev, j));
       tm.stop();
       JL_HIP(ctx, launch_reduce_cols(dots_part, ndots, stride, stride, coef, st));
       S_.n_dots_launch++;
       S_.bytes_dots += (double)(ncol + 1) * n * es;
-      JL_HIP(ctx, hipMemcpyAsync(hs, coef + 4 * j, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      JL_HIP(ctx, hipMemcpyAsync(hs + 2, coef + 4 * ncol, sizeof(double), hipMemcpyDeviceToHost, st));
+      tm.start(Timer::UPDATE);
+      JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st));
+      tm.stop();
+      JL_HIP(ctx, launch_reduce_cols(upd_part, nupd, 1, 1, scal + 2, st));
+      S_.n_update_launch++;
+      S_.bytes_update += (double)(ncol + 2) * n * es;
+      JL_HIP(ctx, hipMemcpyAsync(hs, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+      JL_HIP(ctx, hipMemcpyAsync(hs + 3, coef + 4 * ncol, sizeof(double), hipMemcpyDeviceToHost, st));
       JL_HIP(ctx, hipStreamSynchronize(st));
       tm.resolve();
-      const double tr = hs[0], ti = hs[1], unorm2 = hs[2];
-      const double alpha = tr;
+      const double alpha = hs[0];
       Tat(j, j) = alpha;
       maxT = std::max(maxT, std::fabs(alpha));
-      // b0 = ||u - t_jj v_j||
-      double b0 = std::sqrt(std::max(unorm2 - (tr * tr + ti * ti), 0.0));
+      double b0 = std::sqrt(hs[3]);   // norm entering the Gram-Schmidt loop
+      double b1 = std::sqrt(hs[2]);
       const double btol = bd_factor * uround * std::max(maxT, 1e-300);
-      double b1 = 0.0;
-      int passes = 0;
-      for (;;) {
-        tm.start(Timer::UPDATE);
-        JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st));
-        tm.stop();
-        JL_HIP(ctx, launch_reduce_cols(upd_part, nupd, 1, 1, scal, st));
-        S_.n_update_launch++;
-        S_.bytes_update += (double)(ncol + 2) * n * es;
-        JL_HIP(ctx, hipMemcpyAsync(hs, scal, sizeof(double), hipMemcpyDeviceToHost, st));
-        JL_HIP(ctx, hipStreamSynchronize(st));
-        tm.resolve();
-        b1 = std::sqrt(hs[0]);
-        passes++;
-        S_.gs_passes++;
-        if (b1 * sqrt2 > b0 || b1 <= btol || passes >= max_passes) break;
+      int passes = 1;
+      S_.gs_passes++;
+      while (!(passes >= min_passes && b1 * sqrt2 > b0) && b1 > btol && passes < max_passes) {
         b0 = b1;
         tm.start(Timer::DOTS);
         JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st));
@@ -430,6 +434,18 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
         JL_HIP(ctx, launch_reduce_cols(dots_part, ndots, stride, stride, coef, st));
         S_.n_dots_launch++;
         S_.bytes_dots += (double)(ncol + 1) * n * es;
+        tm.start(Timer::UPDATE);
+        JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st));
+        tm.stop();
+        JL_HIP(ctx, launch_reduce_cols(upd_part, nupd, 1, 1, scal + 2, st));
+        S_.n_update_launch++;
+        S_.bytes_update += (double)(ncol + 2) * n * es;
+        JL_HIP(ctx, hipMemcpyAsync(hs + 2, scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+        JL_HIP(ctx, hipStreamSynchronize(st));
+        tm.resolve();
+        b1 = std::sqrt(hs[2]);
+        passes++;
+        S_.gs_passes++;
       }
       if (trace_n < prm->trace_cap) {
         prm->trace_ab[trace_n] = alpha;
@@ -470,15 +486,15 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     JL_HIP(ctx, hipMemcpyAsync(Tdev, Tm.data(), sizeof(double) * (size_t)meff * meff,
                                hipMemcpyHostToDevice, st));
     const int kcols = std::min(kmax, meff);
-    JL_HIP(ctx, ritz_device<S>(meff, Tdev, fro2, prm->which == JL_LARGEST, kcols, ritz_scr, lam_s,
-                               Zs, Zc, zlast, hs, st));
+    JL_HIP(ctx, ritz_device<S>(meff, Tdev, fro2, prm->which == JL_LARGEST, 0, ritz_scr, lam_s, Zs,
+                               nullptr, zlast, hs, st));
     JL_HIP(ctx, hipMemcpyAsync(h_lam, lam_s, sizeof(double) * meff, hipMemcpyDeviceToHost, st));
     JL_HIP(ctx, hipMemcpyAsync(h_zl, zlast, sizeof(double) * meff, hipMemcpyDeviceToHost, st));
     tm.stop();
     // ================= V_k := V_m Z[:, 0:kcols] (real GEMM on the interleaved basis)
     tm.start(Timer::GEMM);
-    JL_HIP(ctx, launch_gemm_nn<S>(reinterpret_cast<const S*>(V), 2 * ldv, Zc, meff,
-                                  reinterpret_cast<S*>(Vn), 2 * ldv, 2 * n, kcols, meff, st));
+    JL_HIP(ctx, (launch_gemm_nn<S, double>)(reinterpret_cast<const S*>(V), 2 * ldv, Zs, meff,
+                                          reinterpret_cast<S*>(Vn), 2 * ldv, 2 * n, kcols, meff, st));
     tm.stop();
     S_.n_gemm_launch++;
     S_.flops_gemm += 2.0 * (double)(2 * n) * kcols * meff;
@@ -490,11 +506,14 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       svec[i] = beta_m * h_zl[i];   // t_{m+1,i} = t_{m+1,m} z_{m,i}
     }
     // ================= convergence check on the true residuals (Alg. 1)
+    const double tol_abs =
+        prm->tol_relative ? prm->tol * std::max(std::fabs(lam_sorted[0]), std::fabs(lam_sorted[meff - 1]))
+                          : prm->tol;
     int ncand = 0;
     for (int i = 0; i < nev; ++i) {
       conv[i] = 0;
       resv[i] = INFINITY;
-      if (std::fabs(svec[i]) < prm->tol) {
+      if (std::fabs(svec[i]) < tol_abs) {
         h_rcols[ncand] = i;
         h_rlam[ncand] = lam_sorted[i];
         ncand++;
@@ -515,7 +534,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       for (int c = 0; c < ncand; ++c) {
         const int i = h_rcols[c];
         resv[i] = std::sqrt(h_res[c]);
-        conv[i] = resv[i] < prm->tol;
+        conv[i] = resv[i] < tol_abs;
       }
     }
     icnv = 0;
@@ -524,6 +543,14 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       if (conv[i]) out_order.push_back(i), icnv++;
     for (int i = 0; i < nev; ++i)
       if (!conv[i]) out_order.push_back(i);
+    if (prm->verbose) {
+      double worst = 0.0;
+      for (int i = 0; i < nev; ++i) worst = std::max(worst, std::fabs(svec[i]));
+      fprintf(stderr, "[jlanczos] cycle %d k %d m %d icnv %d/%d max|s| %.2e n_mv %d t %.2fs\n",
+              cycle + 1, k, meff, icnv, nev, worst, S_.n_mv,
+              std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count());
+      fflush(stderr);
+    }
     const bool last = (cycle + 1 == max_cycles);
     if (icnv == nev || broke || last) {
       status = icnv == nev ? JL_OK : (broke ? JL_BREAKDOWN : JL_NOT_CONVERGED);
@@ -680,9 +707,9 @@ jl_status jl_op_apply(jl_op op, const void* x, void* y, int32_t nrhs) {
   if (nrhs == 0) return JL_OK;
   DeviceGuard g(ctx->device);
   if (op->dtype == JL_C64)
-    JL_HIP(ctx, op_apply<float>(op, static_cast<const float2*>(x), static_cast<float2*>(y), op->n, nrhs, ctx->stream));
+    JL_HIP(ctx, op_apply<float>(op, static_cast<const float2*>(x), static_cast<float2*>(y), op->n, nrhs, nullptr, ctx->stream));
   else
-    JL_HIP(ctx, op_apply<double>(op, static_cast<const double2*>(x), static_cast<double2*>(y), op->n, nrhs, ctx->stream));
+    JL_HIP(ctx, op_apply<double>(op, static_cast<const double2*>(x), static_cast<double2*>(y), op->n, nrhs, nullptr, ctx->stream));
   return JL_OK;
 }
 

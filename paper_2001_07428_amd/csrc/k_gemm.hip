@@ -3,11 +3,15 @@
 // Z is real, so the complex basis (interleaved, column-major, one vector per
 // column) is a real (2n) x m column-major matrix and the update is a real
 // GEMM C = A * B with M = 2n rows, K = m, N = k.  It is compute-bound at the
-// stencil shapes, so it runs on the matrix cores: v_mfma_f32_16x16x4f32 for
-// FP32 storage, v_mfma_f64_16x16x4f64 for FP64.
+// stencil shapes, so it runs on the matrix cores: v_mfma_f64_16x16x4f64 for
+// both bases (FP32 loads are converted to FP64, Z is FP64 and the result is
+// rounded once to the storage type).  FP32 accumulation over K = m terms
+// would leave a
+// Ritz-vector error of about sqrt(m) u_32 that puts the true-residual floor
+// above the mixed-precision tolerance.
 //
 // Block tile 128 x 128, 4 wavefronts in 2 x 2, each 64 x 64 = 4 x 4 MFMA
-// tiles; K staged through LDS in steps of 16 (FP32) or 8 (FP64) with a
+// tiles; K staged through LDS (as FP64) in steps of 8 with a
 // register prefetch of the next step and two LDS buffers (one barrier per
 // step).  Consecutive tiles of one row panel are placed on the same XCD so
 // the A panel is shared through that XCD's L2.
@@ -16,17 +20,9 @@
 namespace jl {
 namespace {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename S> struct Mfma;
-template <> struct Mfma<float> {
-  using acc_t = f32x4;
-  static constexpr int BK = 16;
-  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
 template <> struct Mfma<double> {
   using acc_t = f64x4;
   static constexpr int BK = 8;
@@ -38,18 +34,20 @@ template <> struct Mfma<double> {
 constexpr int BM = 128, BN = 128, PAD = 16, LDT = BM + PAD;
 constexpr int kThreads = 256;
 
-template <typename S>
+// S: storage type of A and C; T: MFMA (accumulation) type, also the type of B.
+template <typename S, typename T>
 __global__ __launch_bounds__(kThreads) void k_gemm_nn(const S* __restrict__ A, int64_t lda,
-                                                      const S* __restrict__ B, int64_t ldb,
+                                                      const T* __restrict__ B, int64_t ldb,
                                                       S* __restrict__ C, int64_t ldc, int64_t M,
                                                       int N, int K, int64_t tiles_m, int tiles_n) {
-  using MF = Mfma<S>;
+  using MF = Mfma<T>;
   constexpr int BK = MF::BK;
   constexpr int AV = 16 / sizeof(S);                    // elements per 16-byte load
   constexpr int A_PER_T = BM * BK / kThreads;           // A elements per thread per step
   constexpr int B_PER_T = BN * BK / kThreads;
-  __shared__ S As[2][BK][LDT];
-  __shared__ S Bs[2][BK][LDT];
+  static_assert(A_PER_T % AV == 0, "A loader");
+  __shared__ T As[2][BK][LDT];
+  __shared__ T Bs[2][BK][LDT];
 
   // XCD-aware tile order: hardware places block b on XCD b % 8; make the
   // tiles of one row panel consecutive on one XCD.
@@ -75,7 +73,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nn(const S* __restrict__ A, i
   const int b_c = tid / B_TPC;
   const int b_k = (tid % B_TPC) * B_PER_T;
 
-  S ra[A_PER_T], rb[B_PER_T];
+  T ra[A_PER_T], rb[B_PER_T];
   auto load = [&](int k0) {
     const int k = k0 + a_k;
 #pragma unroll
@@ -94,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nn(const S* __restrict__ A, i
 #pragma unroll
         for (int e = 0; e < AV; ++e) {
           const int64_t r = row + e;
-          ra[v + e] = (k < K && r < M) ? A[(int64_t)k * lda + r] : (S)0;
+          ra[v + e] = (k < K && r < M) ? (T)A[(int64_t)k * lda + r] : (T)0;
         }
       }
     }
@@ -102,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nn(const S* __restrict__ A, i
 #pragma unroll
     for (int e = 0; e < B_PER_T; ++e) {
       const int kk = k0 + b_k + e;
-      rb[e] = (col < N && kk < K) ? B[(int64_t)col * ldb + kk] : (S)0;
+      rb[e] = (col < N && kk < K) ? B[(int64_t)col * ldb + kk] : (T)0;
     }
   };
   auto store = [&](int buf) {
@@ -128,7 +126,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nn(const S* __restrict__ A, i
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const int kr = ks * 4 + lane / 16;
-      S a[4], bb[4];
+      T a[4], bb[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = As[buf][kr][wm * 64 + i * 16 + lane % 16];
 #pragma unroll
@@ -140,27 +138,20 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nn(const S* __restrict__ A, i
     }
   }
 
-  // acc[i][j][r] = C[m0 + wm*64 + i*16 + 4*(lane/16) + r][n0 + wn*64 + j*16 + lane%16]
+  // Output layout of v_mfma_f64_16x16x4f64: lane l holds column l % 16 of the
+  // 16 x 16 tile, register r holds row 4*r + l/16.
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int col = n0 + wn * 64 + j * 16 + lane % 16;
     if (col >= N) continue;
+    S* pc = C + (int64_t)col * ldc;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t row = m0 + wm * 64 + i * 16 + 4 * (lane / 16);
-      S* p = C + (int64_t)col * ldc + row;
-      if (row + 4 <= M) {
-        if constexpr (sizeof(S) == 4) {
-          *reinterpret_cast<float4*>(p) =
-              make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
-        } else {
-          reinterpret_cast<double2*>(p)[0] = make_double2(acc[i][j][0], acc[i][j][1]);
-          reinterpret_cast<double2*>(p)[1] = make_double2(acc[i][j][2], acc[i][j][3]);
-        }
-      } else {
+      const int64_t tile_row = m0 + wm * 64 + i * 16;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (row + r < M) p[r] = acc[i][j][r];
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = tile_row + 4 * r + lane / 16;
+        if (row < M) pc[row] = (S)acc[i][j][r];
       }
     }
   }
@@ -168,8 +159,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nn(const S* __restrict__ A, i
 
 }  // namespace
 
-template <typename S>
-hipError_t launch_gemm_nn(const S* A, int64_t lda, const S* B, int64_t ldb, S* C, int64_t ldc,
+template <typename S, typename T>
+hipError_t launch_gemm_nn(const S* A, int64_t lda, const T* B, int64_t ldb, S* C, int64_t ldc,
                           int64_t M, int N, int K, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
   // 16-byte vector loads/stores of A and C columns need 4-element (FP32) or
@@ -182,14 +173,15 @@ hipError_t launch_gemm_nn(const S* A, int64_t lda, const S* B, int64_t ldb, S* C
   int64_t nblk = tm * tn;
   nblk = (nblk + 7) / 8 * 8;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gemm_nn<S>, dim3((unsigned)nblk), dim3(kThreads), 0, st, A, lda, B, ldb, C,
-                     ldc, M, N, K, tm, tn);
+  hipLaunchKernelGGL((k_gemm_nn<S, T>), dim3((unsigned)nblk), dim3(kThreads), 0, st, A, lda, B, ldb,
+                     C, ldc, M, N, K, tm, tn);
   return hipGetLastError();
 }
 
-template hipError_t launch_gemm_nn<float>(const float*, int64_t, const float*, int64_t, float*,
-                                          int64_t, int64_t, int, int, hipStream_t);
-template hipError_t launch_gemm_nn<double>(const double*, int64_t, const double*, int64_t, double*,
-                                           int64_t, int64_t, int, int, hipStream_t);
+template hipError_t launch_gemm_nn<float, double>(const float*, int64_t, const double*, int64_t,
+                                                  float*, int64_t, int64_t, int, int, hipStream_t);
+template hipError_t launch_gemm_nn<double, double>(const double*, int64_t, const double*, int64_t,
+                                                   double*, int64_t, int64_t, int, int,
+                                                   hipStream_t);
 
 }  // namespace jl

@@ -154,30 +154,52 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx
 
 constexpr int kStencilThreads = 256;
 
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh);
+
+// y = A x per site; with apart != nullptr (single column) the block also
+// writes its FP64 partial of x^H y (the alpha_j of Alg. 2) to apart[2*blk].
 template <typename S>
 __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply(StencilArgs<S> a,
                                                                    const cplx<S>* __restrict__ x,
                                                                    cplx<S>* __restrict__ y,
-                                                                   int64_t ld) {
+                                                                   int64_t ld,
+                                                                   double* __restrict__ apart) {
+  __shared__ double sh[kStencilThreads / 64];
   const int64_t s = (int64_t)blockIdx.x * kStencilThreads + threadIdx.x;
-  if (s >= a.V) return;
   const int64_t h = a.V * 4;
   const cplx<S>* xc = x + (int64_t)blockIdx.y * ld;
   cplx<S>* yc = y + (int64_t)blockIdx.y * ld;
-  cx<S> top[4], bot[4];
-  stencil_site<S, S>(a, xc, xc + h, s, top, bot);
+  double are = 0.0, aim = 0.0;
+  if (s < a.V) {
+    cx<S> top[4], bot[4];
+    stencil_site<S, S>(a, xc, xc + h, s, top, bot);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    cplx<S> t, b;
-    t.x = top[r].re; t.y = top[r].im;
-    b.x = bot[r].re; b.y = bot[r].im;
-    yc[s * 4 + r] = t;
-    yc[h + s * 4 + r] = b;
+    for (int r = 0; r < 4; ++r) {
+      cplx<S> t, b;
+      t.x = top[r].re; t.y = top[r].im;
+      b.x = bot[r].re; b.y = bot[r].im;
+      yc[s * 4 + r] = t;
+      yc[h + s * 4 + r] = b;
+      if (apart) {
+        const cplx<S> xt = xc[s * 4 + r], xb = xc[h + s * 4 + r];
+        are += (double)xt.x * t.x + (double)xt.y * t.y + (double)xb.x * b.x + (double)xb.y * b.y;
+        aim += (double)xt.x * t.y - (double)xt.y * t.x + (double)xb.x * b.y - (double)xb.y * b.x;
+      }
+    }
+  }
+  if (apart) {   // uniform over the grid
+    are = block_sum<kStencilThreads>(are, sh);
+    aim = block_sum<kStencilThreads>(aim, sh);
+    if (threadIdx.x == 0) {
+      apart[2 * blockIdx.x] = are;
+      apart[2 * blockIdx.x + 1] = aim;
+    }
   }
 }
 
 template <int NT>
-__device__ __forceinline__ double block_sum(double v, double* sh) {
+__device__ __forceinline__ double block_sum(double v, double* sh) {   // result valid in thread 0
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   const int w = threadIdx.x / 64, l = threadIdx.x % 64;
@@ -257,19 +279,36 @@ __device__ __forceinline__ void dense_row(const DenseArgs<S>& a, const cplx<S>* 
 template <typename S>
 __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(DenseArgs<S> a,
                                                                const cplx<S>* __restrict__ x,
-                                                               cplx<S>* __restrict__ y, int64_t ld) {
+                                                               cplx<S>* __restrict__ y, int64_t ld,
+                                                               double* __restrict__ apart) {
+  __shared__ double sh[kDenseThreads / 64];
   const int64_t r = (int64_t)blockIdx.x * (kDenseThreads / 64) + threadIdx.x / 64;
-  if (r >= a.h) return;
   const cplx<S>* xc = x + (int64_t)blockIdx.y * ld;
   cplx<S>* yc = y + (int64_t)blockIdx.y * ld;
-  cx<S> s1, s2;
-  dense_row<S, S>(a, xc, xc + a.h, r, s1, s2);
-  if (threadIdx.x % 64 == 0) {
-    cplx<S> t, b;
-    t.x = s1.re; t.y = s1.im;
-    b.x = s2.re; b.y = -s2.im;   // u_bot = conj(s2)
-    yc[r] = t;
-    yc[a.h + r] = b;
+  double are = 0.0, aim = 0.0;
+  if (r < a.h) {
+    cx<S> s1, s2;
+    dense_row<S, S>(a, xc, xc + a.h, r, s1, s2);
+    if (threadIdx.x % 64 == 0) {
+      cplx<S> t, b;
+      t.x = s1.re; t.y = s1.im;
+      b.x = s2.re; b.y = -s2.im;   // u_bot = conj(s2)
+      yc[r] = t;
+      yc[a.h + r] = b;
+      if (apart) {
+        const cplx<S> xt = xc[r], xb = xc[a.h + r];
+        are = (double)xt.x * t.x + (double)xt.y * t.y + (double)xb.x * b.x + (double)xb.y * b.y;
+        aim = (double)xt.x * t.y - (double)xt.y * t.x + (double)xb.x * b.y - (double)xb.y * b.x;
+      }
+    }
+  }
+  if (apart) {
+    are = block_sum<kDenseThreads>(are, sh);
+    aim = block_sum<kDenseThreads>(aim, sh);
+    if (threadIdx.x == 0) {
+      apart[2 * blockIdx.x] = are;
+      apart[2 * blockIdx.x + 1] = aim;
+    }
   }
 }
 
@@ -304,13 +343,16 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_resid(DenseArgs<S> a,
 }  // namespace
 
 int stencil_resid_blocks(int64_t V) { return (int)((V + kStencilThreads - 1) / kStencilThreads); }
+int stencil_apply_blocks(int64_t V) { return stencil_resid_blocks(V); }
+int dense_apply_blocks(int64_t h) { return (int)((h + kDenseThreads / 64 - 1) / (kDenseThreads / 64)); }
 int dense_resid_blocks(int64_t h) { return (int)((h + kDenseThreads / 64 - 1) / (kDenseThreads / 64)); }
 
 template <typename S>
 hipError_t launch_stencil_apply(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
-                                int nrhs, hipStream_t st) {
+                                int nrhs, double* apart, hipStream_t st) {
+  if (apart && nrhs != 1) return hipErrorInvalidValue;
   dim3 grid((unsigned)((a.V + kStencilThreads - 1) / kStencilThreads), (unsigned)nrhs);
-  hipLaunchKernelGGL(k_stencil_apply<S>, grid, dim3(kStencilThreads), 0, st, a, x, y, ld);
+  hipLaunchKernelGGL(k_stencil_apply<S>, grid, dim3(kStencilThreads), 0, st, a, x, y, ld, apart);
   return hipGetLastError();
 }
 
@@ -327,9 +369,10 @@ hipError_t launch_stencil_resid(const StencilArgs<S>& a, const cplx<S>* X, int64
 
 template <typename S>
 hipError_t launch_dense_apply(const DenseArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ldv,
-                              int nrhs, hipStream_t st) {
+                              int nrhs, double* apart, hipStream_t st) {
+  if (apart && nrhs != 1) return hipErrorInvalidValue;
   dim3 grid((unsigned)dense_resid_blocks(a.h), (unsigned)nrhs);
-  hipLaunchKernelGGL(k_dense_apply<S>, grid, dim3(kDenseThreads), 0, st, a, x, y, ldv);
+  hipLaunchKernelGGL(k_dense_apply<S>, grid, dim3(kDenseThreads), 0, st, a, x, y, ldv, apart);
   return hipGetLastError();
 }
 
@@ -346,12 +389,12 @@ hipError_t launch_dense_resid(const DenseArgs<S>& a, const cplx<S>* X, int64_t l
 
 #define JL_INST(S)                                                                               \
   template hipError_t launch_stencil_apply<S>(const StencilArgs<S>&, const cplx<S>*, cplx<S>*,   \
-                                              int64_t, int, hipStream_t);                        \
+                                              int64_t, int, double*, hipStream_t);               \
   template hipError_t launch_stencil_resid<S>(const StencilArgs<S>&, const cplx<S>*, int64_t,    \
                                               const int*, const double*, int, double*, int*,     \
                                               hipStream_t);                                      \
   template hipError_t launch_dense_apply<S>(const DenseArgs<S>&, const cplx<S>*, cplx<S>*,       \
-                                            int64_t, int, hipStream_t);                          \
+                                            int64_t, int, double*, hipStream_t);                 \
   template hipError_t launch_dense_resid<S>(const DenseArgs<S>&, const cplx<S>*, int64_t,        \
                                             const int*, const double*, int, double*, int*,       \
                                             hipStream_t);

@@ -52,11 +52,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 // grid.x = blocks, each covering `chunks` consecutive chunks of
 // 64*E*kPairsPerLane pairs.  Column c is owned by wavefront c % 4 of every
 // block.  partial row stride = 4*ncol + 1.
-template <typename S, int E>
+// LOCAL: before the inner products apply the local three-term step
+// u <- u - t v_jl - beta v_{jl-1} (t read from the device), rounded once to
+// S and stored back by wavefront 0 after every wavefront has read the chunk.
+template <typename S, int E, bool LOCAL>
 __global__ __launch_bounds__(kReorthThreads) void k_dots(const cplx<S>* __restrict__ V, int64_t ldv,
-                                                         int ncol, const cplx<S>* __restrict__ u,
+                                                         int ncol, cplx<S>* __restrict__ u,
                                                          int64_t h, int chunks,
-                                                         double* __restrict__ partial) {
+                                                         double* __restrict__ partial,
+                                                         const double* __restrict__ tloc,
+                                                         double beta, int jl) {
   constexpr int Q = kPairsPerLane / E;     // loads per half per lane per chunk
   constexpr int CH = 64 * E * Q;           // pairs per chunk
   extern __shared__ double acc[];          // 4*ncol + 1 column accumulators
@@ -85,6 +90,46 @@ __global__ __launch_bounds__(kReorthThreads) void k_dots(const cplx<S>* __restri
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         utr[q][e] = tr[e]; uti[q][e] = ti[e]; ubr[q][e] = br[e]; ubi[q][e] = bi[e];
+      }
+    }
+    if constexpr (LOCAL) {
+      __syncthreads();   // every wavefront holds the raw chunk before it is overwritten
+      const double t_re = tloc[0], t_im = tloc[1];
+      const cplx<S>* vj = V + (int64_t)jl * ldv;
+      const cplx<S>* vm = vj - ldv;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (!ok[q]) continue;
+        const int64_t p = p0 + (int64_t)q * 64 * E + lane * E;
+        S tr[E], ti[E], br[E], bi[E];
+        Ld<S, E>::get(vj + p, tr, ti);
+        Ld<S, E>::get(vj + h + p, br, bi);
+        S mtr[E], mti[E], mbr[E], mbi[E];
+        if (beta != 0.0) {
+          Ld<S, E>::get(vm + p, mtr, mti);
+          Ld<S, E>::get(vm + h + p, mbr, mbi);
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) mtr[e] = mti[e] = mbr[e] = mbi[e] = (S)0;
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          // u - t v_j - beta v_{j-1}, rounded once to the storage type
+          utr[q][e] = (double)(S)(utr[q][e] - (t_re * tr[e] - t_im * ti[e]) - beta * mtr[e]);
+          uti[q][e] = (double)(S)(uti[q][e] - (t_re * ti[e] + t_im * tr[e]) - beta * mti[e]);
+          ubr[q][e] = (double)(S)(ubr[q][e] - (t_re * br[e] - t_im * bi[e]) - beta * mbr[e]);
+          ubi[q][e] = (double)(S)(ubi[q][e] - (t_re * bi[e] + t_im * br[e]) - beta * mbi[e]);
+        }
+        if (wave == 0) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            cplx<S> a, b;
+            a.x = (S)utr[q][e]; a.y = (S)uti[q][e];
+            b.x = (S)ubr[q][e]; b.y = (S)ubi[q][e];
+            u[p + e] = a;
+            u[h + p + e] = b;
+          }
+        }
       }
     }
     if (wave == 0) {
@@ -143,15 +188,15 @@ __global__ __launch_bounds__(kReorthThreads) void k_dots(const cplx<S>* __restri
   for (int i = threadIdx.x; i < 4 * ncol + 1; i += kReorthThreads) out[i] = acc[i];
 }
 
-// u -= sum_c v_c cv_c + w_c cw_c; each lane keeps its pairs' corrections in
-// registers across the column loop.  partial[blk] = ||u_new||^2.
-template <typename S, int E>
+// u -= sum_c v_c cv_c + w_c cw_c; each lane keeps the corrections of its
+// E*Q pairs in registers across the column loop (Q loads of 16 bytes per half
+// per column).  partial[blk] = ||u_new||^2.
+template <typename S, int E, int Q>
 __global__ __launch_bounds__(kReorthThreads) void k_update(const cplx<S>* __restrict__ V,
                                                            int64_t ldv, int ncol,
                                                            cplx<S>* __restrict__ u, int64_t h,
                                                            const double* __restrict__ coef,
                                                            double* __restrict__ partial) {
-  constexpr int Q = kPairsPerLane / E;
   constexpr int CH = 4 * 64 * E * Q;       // pairs per block
   __shared__ double sh[4];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -164,6 +209,7 @@ __global__ __launch_bounds__(kReorthThreads) void k_update(const cplx<S>* __rest
 #pragma unroll
     for (int e = 0; e < E; ++e) dtr[q][e] = dti[q][e] = dbr[q][e] = dbi[q][e] = (S)0;
   }
+#pragma unroll 4
   for (int c = 0; c < ncol; ++c) {
     const S cvr = (S)coef[4 * c + 0], cvi = (S)coef[4 * c + 1];
     const S cwr = (S)coef[4 * c + 2], cwi = (S)coef[4 * c + 3];
@@ -277,8 +323,19 @@ inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t
 
 }  // namespace
 
-int reorth_update_blocks(int64_t h) {
-  const int64_t per_block = (int64_t)4 * 64 * kPairsPerLane;
+// Pairs per lane of the update kernel: the largest of 8, 4, 2 (1 for FP64
+// or an odd half length) that still gives >= 1024 blocks, so small vectors
+// fill the 256 CUs.
+static int update_ppl(int64_t h, int E) {
+  for (int ppl = 8; ppl >= 2 * E; ppl /= 2)
+    if ((h + 256 * ppl - 1) / (256 * ppl) >= 1024) return ppl;
+  return E == 2 ? 2 : 1;
+}
+
+static int elems_per_load(int64_t h, int es) { return (es == 8 && h % 2 == 0) ? 2 : 1; }
+
+int reorth_update_blocks(int64_t h, int es) {
+  const int64_t per_block = (int64_t)256 * update_ppl(h, elems_per_load(h, es));
   return (int)((h + per_block - 1) / per_block);
 }
 
@@ -292,21 +349,34 @@ static int dots_chunks(int64_t h) {
 }
 
 template <typename S>
-hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, const cplx<S>* u, int64_t h,
-                              double* partial, int nblk, hipStream_t st) {
+hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
+                              double* partial, int nblk, hipStream_t st, const double* tloc,
+                              double beta, int jl) {
   if (ncol > kMaxCols) return hipErrorInvalidValue;
+  if (tloc && (jl < 0 || jl >= ncol || (beta != 0.0 && jl < 1))) return hipErrorInvalidValue;
   const int64_t ch = 64 * kPairsPerLane;
   const int64_t nch = (h + ch - 1) / ch;
   const int per = (int)((nch + nblk - 1) / nblk);
   const unsigned grid = (unsigned)((nch + per - 1) / per);
   if ((int)grid != nblk) return hipErrorInvalidValue;
   const size_t lds = sizeof(double) * (4 * (size_t)ncol + 1);
-  if (sizeof(S) == 4 && h % 2 == 0)
-    hipLaunchKernelGGL((k_dots<S, sizeof(S) == 4 ? 2 : 1>), dim3(grid), dim3(kReorthThreads), lds,
-                       st, V, ldv, ncol, u, h, per, partial);
-  else
-    hipLaunchKernelGGL((k_dots<S, 1>), dim3(grid), dim3(kReorthThreads), lds, st, V, ldv, ncol, u,
-                       h, per, partial);
+  const bool e2 = sizeof(S) == 4 && h % 2 == 0;
+  if (tloc) {
+    if (e2)
+      hipLaunchKernelGGL((k_dots<S, sizeof(S) == 4 ? 2 : 1, true>), dim3(grid), dim3(kReorthThreads),
+                         lds, st, V, ldv, ncol, u, h, per, partial, tloc, beta, jl);
+    else
+      hipLaunchKernelGGL((k_dots<S, 1, true>), dim3(grid), dim3(kReorthThreads), lds, st, V, ldv,
+                         ncol, u, h, per, partial, tloc, beta, jl);
+  } else {
+    if (e2)
+      hipLaunchKernelGGL((k_dots<S, sizeof(S) == 4 ? 2 : 1, false>), dim3(grid),
+                         dim3(kReorthThreads), lds, st, V, ldv, ncol, u, h, per, partial, tloc,
+                         beta, jl);
+    else
+      hipLaunchKernelGGL((k_dots<S, 1, false>), dim3(grid), dim3(kReorthThreads), lds, st, V, ldv,
+                         ncol, u, h, per, partial, tloc, beta, jl);
+  }
   return hipGetLastError();
 }
 
@@ -318,18 +388,32 @@ int reorth_dots_blocks(int64_t h) {
   return (int)((nch + per - 1) / per);
 }
 
+template <typename S, int E, int Q>
+static void launch_update_q(unsigned grid, const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u,
+                            int64_t h, const double* coef, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL((k_update<S, E, Q>), dim3(grid), dim3(kReorthThreads), 0, st, V, ldv, ncol, u,
+                     h, coef, partial);
+}
+
 template <typename S>
 hipError_t launch_reorth_update(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
                                 const double* coef, double* partial, int nblk, hipStream_t st) {
-  const int64_t per_block = (int64_t)4 * 64 * kPairsPerLane;
-  const unsigned grid = (unsigned)((h + per_block - 1) / per_block);
+  const int E = elems_per_load(h, (int)sizeof(cplx<S>));
+  const int ppl = update_ppl(h, E);
+  const unsigned grid = (unsigned)((h + 256 * (int64_t)ppl - 1) / (256 * (int64_t)ppl));
   if ((int)grid != nblk) return hipErrorInvalidValue;
-  if (sizeof(S) == 4 && h % 2 == 0)
-    hipLaunchKernelGGL((k_update<S, sizeof(S) == 4 ? 2 : 1>), dim3(grid), dim3(kReorthThreads), 0,
-                       st, V, ldv, ncol, u, h, coef, partial);
-  else
-    hipLaunchKernelGGL((k_update<S, 1>), dim3(grid), dim3(kReorthThreads), 0, st, V, ldv, ncol, u,
-                       h, coef, partial);
+  if (E == 2) {
+    if constexpr (sizeof(S) == 4) {
+      if (ppl == 8) launch_update_q<S, 2, 4>(grid, V, ldv, ncol, u, h, coef, partial, st);
+      else if (ppl == 4) launch_update_q<S, 2, 2>(grid, V, ldv, ncol, u, h, coef, partial, st);
+      else launch_update_q<S, 2, 1>(grid, V, ldv, ncol, u, h, coef, partial, st);
+    }
+  } else {
+    if (ppl == 8) launch_update_q<S, 1, 8>(grid, V, ldv, ncol, u, h, coef, partial, st);
+    else if (ppl == 4) launch_update_q<S, 1, 4>(grid, V, ldv, ncol, u, h, coef, partial, st);
+    else if (ppl == 2) launch_update_q<S, 1, 2>(grid, V, ldv, ncol, u, h, coef, partial, st);
+    else launch_update_q<S, 1, 1>(grid, V, ldv, ncol, u, h, coef, partial, st);
+  }
   return hipGetLastError();
 }
 
@@ -371,8 +455,9 @@ hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t l
 }
 
 #define JL_INST(S)                                                                                \
-  template hipError_t launch_reorth_dots<S>(const cplx<S>*, int64_t, int, const cplx<S>*, int64_t, \
-                                            double*, int, hipStream_t);                           \
+  template hipError_t launch_reorth_dots<S>(const cplx<S>*, int64_t, int, cplx<S>*, int64_t,       \
+                                            double*, int, hipStream_t, const double*, double,     \
+                                            int);                                                 \
   template hipError_t launch_reorth_update<S>(const cplx<S>*, int64_t, int, cplx<S>*, int64_t,    \
                                               const double*, double*, int, hipStream_t);          \
   template hipError_t launch_scale<S>(cplx<S>*, int64_t, double, hipStream_t);                    \

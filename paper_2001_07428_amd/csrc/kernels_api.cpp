@@ -16,14 +16,15 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 size_t reorth_ws(int64_t n, int ncol) {
   const int64_t h = n / 2;
   return align_up(sizeof(double) * (size_t)reorth_dots_blocks(h) * (4 * (size_t)ncol + 1)) +
-         align_up(sizeof(double) * (size_t)std::max(reorth_update_blocks(h), 1));
+         align_up(sizeof(double) *
+                  (size_t)std::max({reorth_update_blocks(h, 8), reorth_update_blocks(h, 16), 1}));
 }
 
 template <typename S>
 hipError_t reorth_pass(int64_t n, int ncol, const cplx<S>* V, int64_t ldv, cplx<S>* u, double* coef,
                        char* ws, hipStream_t st) {
   const int64_t h = n / 2;
-  const int nd = reorth_dots_blocks(h), nu = reorth_update_blocks(h);
+  const int nd = reorth_dots_blocks(h), nu = reorth_update_blocks(h, (int)sizeof(cplx<S>));
   double* dp = reinterpret_cast<double*>(ws);
   double* up = reinterpret_cast<double*>(ws + align_up(sizeof(double) * (size_t)nd * (4 * (size_t)ncol + 1)));
   const int stride = 4 * ncol + 1;
@@ -102,10 +103,11 @@ jl_status jl_basis_update(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t m, int3
   if (k == 0) return JL_OK;
   DeviceGuard g(ctx->device);
   if (dtype == JL_C64)
-    JL_HIP(ctx, launch_gemm_nn<float>(static_cast<const float*>(V), 2 * ldv, static_cast<const float*>(Z),
-                                      ldz, static_cast<float*>(Y), 2 * ldy, 2 * n, k, m, ctx->stream));
+    JL_HIP(ctx, (launch_gemm_nn<float, double>)(static_cast<const float*>(V), 2 * ldv,
+                                              static_cast<const double*>(Z), ldz,
+                                              static_cast<float*>(Y), 2 * ldy, 2 * n, k, m, ctx->stream));
   else if (dtype == JL_C128)
-    JL_HIP(ctx, launch_gemm_nn<double>(static_cast<const double*>(V), 2 * ldv,
+    JL_HIP(ctx, (launch_gemm_nn<double, double>)(static_cast<const double*>(V), 2 * ldv,
                                        static_cast<const double*>(Z), ldz, static_cast<double*>(Y),
                                        2 * ldy, 2 * n, k, m, ctx->stream));
   else

@@ -40,9 +40,11 @@ EXPORTS = (
 class JlParams(ctypes.Structure):
     _fields_ = [
         ("nev", ctypes.c_int32), ("m", ctypes.c_int32), ("mwin", ctypes.c_int32),
-        ("which", ctypes.c_int32), ("tol", ctypes.c_double), ("max_cycles", ctypes.c_int32),
-        ("max_passes", ctypes.c_int32), ("timing", ctypes.c_int32), ("trace_cap", ctypes.c_int32),
-        ("trace_ab", ctypes.POINTER(ctypes.c_double)),
+        ("which", ctypes.c_int32), ("tol", ctypes.c_double), ("tol_relative", ctypes.c_int32),
+        ("max_cycles", ctypes.c_int32),
+        ("max_passes", ctypes.c_int32), ("min_passes", ctypes.c_int32), ("timing", ctypes.c_int32),
+        ("trace_cap", ctypes.c_int32),
+        ("trace_ab", ctypes.POINTER(ctypes.c_double)), ("verbose", ctypes.c_int32),
     ]
 
 
@@ -50,7 +52,7 @@ class JlStats(ctypes.Structure):
     _fields_ = [
         ("cycles", ctypes.c_int32), ("n_mv", ctypes.c_int32), ("n_resid", ctypes.c_int32),
         ("gs_passes", ctypes.c_int32), ("icnv", ctypes.c_int32), ("status", ctypes.c_int32),
-        ("t_total", ctypes.c_double), ("t_matvec", ctypes.c_double), ("t_dots", ctypes.c_double),
+        ("sum_ncol", ctypes.c_int64), ("t_total", ctypes.c_double), ("t_matvec", ctypes.c_double), ("t_dots", ctypes.c_double),
         ("t_update", ctypes.c_double), ("t_gemm", ctypes.c_double), ("t_ritz", ctypes.c_double),
         ("t_resid", ctypes.c_double),
         ("n_matvec_launch", ctypes.c_int64), ("n_dots_launch", ctypes.c_int64),
@@ -240,13 +242,17 @@ class SolveResult:
     trace_beta: np.ndarray | None = None
 
 
-def _params(nev, m, mwin, tol, which, max_cycles, max_passes, timing, trace_buf):
+def _params(nev, m, mwin, tol, which, max_cycles, max_passes, timing, trace_buf, min_passes=0,
+            tol_relative=False, verbose=False):
     p = JlParams()
     p.nev, p.m, p.mwin = nev, m, mwin
     p.which = JL_LARGEST if which in ("largest", JL_LARGEST) else JL_LOWEST
     p.tol = float(tol)
+    p.tol_relative = int(bool(tol_relative))
+    p.verbose = int(bool(verbose))
     p.max_cycles = int(max_cycles)
     p.max_passes = int(max_passes)
+    p.min_passes = int(min_passes)
     p.timing = int(bool(timing))
     if trace_buf is not None:
         p.trace_cap = len(trace_buf) // 2
@@ -266,12 +272,14 @@ def jl_workspace_bytes(op: Operator, nev, m, mwin, tol=1e-10, which="lowest") ->
 
 
 def jl_solve(op: Operator, nev, m, mwin, tol, which="lowest", v1=None, max_cycles=0,
-             max_passes=0, timing=False, trace_cap=0, workspace=None) -> SolveResult:
+             max_passes=0, min_passes=0, timing=False, trace_cap=0, workspace=None,
+             tol_relative=False, verbose=False) -> SolveResult:
     """Thick-restart J-Lanczos for the nev lowest (or largest) pairs."""
     torch = _torch()
     lib = load_library()
     trace_buf = np.zeros(2 * trace_cap) if trace_cap else None
-    p = _params(nev, m, mwin, tol, which, max_cycles, max_passes, timing, trace_buf)
+    p = _params(nev, m, mwin, tol, which, max_cycles, max_passes, timing, trace_buf, min_passes,
+                tol_relative, verbose)
     nb = ctypes.c_size_t()
     _check(lib.jl_workspace_bytes(op.handle, ctypes.byref(p), ctypes.byref(nb)), op.ctx.handle)
     if workspace is None or workspace.numel() < nb.value:
@@ -357,8 +365,7 @@ def jl_basis_update(ctx: Context, V, Z):
     lib = load_library()
     m, n = V.shape
     k = Z.shape[1]
-    zt = torch.float32 if V.dtype == torch.complex64 else torch.float64
-    Zc = Z.to(zt).t().contiguous()        # column-major m x k
+    Zc = Z.to(torch.float64).t().contiguous()        # column-major m x k
     Y = torch.empty((k, n), dtype=V.dtype, device=V.device)
     _check(lib.jl_basis_update(ctx.handle, _dtype_code(V), n, m, k, ctypes.c_void_p(V.data_ptr()), n,
                                ctypes.c_void_p(Zc.data_ptr()), m, ctypes.c_void_p(Y.data_ptr()), n),

@@ -90,7 +90,7 @@ def test_reorth_pass(ctx, h, ncol, mixed):
     cw = W.conj() @ uq
     got_cv = coef[0:4 * ncol:4] + 1j * coef[1:4 * ncol:4]
     got_cw = coef[2:4 * ncol:4] + 1j * coef[3:4 * ncol:4]
-    scale = np.linalg.norm(uq) * np.abs(Vq).max() * np.sqrt(n)
+    scale = np.linalg.norm(uq) * (np.abs(Vq).max() if ncol else 1.0) * np.sqrt(n)
     if ncol:
         assert np.abs(got_cv - cv).max() < 1e-13 * scale
         assert np.abs(got_cw - cw).max() < 1e-13 * scale
@@ -146,7 +146,8 @@ def test_ritz(ctx, m, which):
                                    (6144, 300, 250)])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_basis_update(ctx, h, m, k, mixed):
-    """V_k = V_m Z[:, :k] (Alg. 1) as a real GEMM on the interleaved basis."""
+    """V_k = V_m Z[:, :k] (Alg. 1) as a real GEMM on the interleaved basis,
+    FP64 accumulation for both storage types (mixed: one final rounding)."""
     from paper_2001_07428_amd import jlanczos as J
     say("basis_update", h, m, k, mixed)
     rng = np.random.default_rng(7)
@@ -158,7 +159,7 @@ def test_basis_update(ctx, h, m, k, mixed):
     Zd = torch.from_numpy(Z).cuda()
     Y = to_np(J.jl_basis_update(ctx, Vd, Zd)).astype(np.complex128)
     Vq = to_np(Vd).astype(np.complex128)
-    Zq = Z.astype(np.float32).astype(np.float64) if mixed else Z
+    Zq = Z
     ref = Zq.T @ Vq
     err = np.abs(Y - ref).max() / (np.abs(Vq).max() * np.abs(Zq).sum(0).max())
-    assert err < (1e-6 if mixed else 1e-14)
+    assert err < (1e-7 if mixed else 1e-14)

@@ -73,20 +73,23 @@ def test_dense_n200_mixed(ctx):
 
 @pytest.mark.parametrize("mixed", [False, True])
 def test_dense_n4096(ctx, mixed):
-    """n=4096, 50 lowest pairs, m=160, mwin=80; tol 1e-10 (FP64) / 1e-5 (mixed)."""
+    """n=4096, 50 lowest pairs, m=160, mwin=80; tol 1e-10 absolute (FP64) and
+    1e-5 relative to max|theta| ~ ||A|| = 90 (mixed: the FP32-accumulated
+    matvec alone errs by ~2e-5 at this size, above an absolute 1e-5)."""
     from paper_2001_07428_amd import jlanczos as J
     say("dense n4096", mixed)
     A11, A12 = inputs.dense_jsym(2, 2048)
     A = jsym.dense_from_blocks(A11, A12)
     op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(mixed)), to_dev(A12, cdt(mixed)))
     tol = 1e-5 if mixed else 1e-10
-    out = J.jl_solve(op, 50, 160, 80, tol, max_cycles=200)
+    out = J.jl_solve(op, 50, 160, 80, tol, max_cycles=200, tol_relative=mixed)
     assert out.status == J.JL_OK, out.stats
     ev = np.linalg.eigvalsh(A)[0::2][:50]
     assert _releig(out.evals, ev) < (1e-5 if mixed else 1e-10)
     X = to_np(out.X).astype(np.complex128)
     R = A @ X.T - X.T * out.evals[None, :]
-    assert np.linalg.norm(R, axis=0).max() < tol * 1.01
+    anorm = np.abs(ev).max() if mixed else 1.0
+    assert np.linalg.norm(R, axis=0).max() < tol * anorm * 1.05
 
 
 # ------------------------------------------------------------------- stencil
