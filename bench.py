@@ -183,6 +183,31 @@ def cpu_baseline(w, host, gpu_stats, budget_s):
                         f"sum j={sum_j} (extrapolated); os.cpu_count()={os.cpu_count()}"))
 
 
+def probe(w, reps=3):
+    """Kernel probe for hardware counters: a plain 1 GiB device copy (HBM
+    calibration), then `reps` operator applies and J-restricted Gram-Schmidt
+    passes at the workload's shape (mixed precision, basis width 3m/4)."""
+    import torch
+    from paper_2001_07428_amd import jlanczos as J
+    host = make_host_inputs(w)
+    ctx = J.Context(0)
+    x = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").uniform_()
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    del x, y
+    op = make_op(J, ctx, w, host, torch.complex64)
+    ncol = (3 * w["m"]) // 4
+    g = torch.Generator(device="cuda:0").manual_seed(0)
+    V = torch.randn((ncol, op.n), dtype=torch.complex64, device="cuda:0", generator=g) / np.sqrt(op.n)
+    u = torch.randn(op.n, dtype=torch.complex64, device="cuda:0", generator=g)
+    for _ in range(reps):
+        J.jl_op_apply(op, V[0], u)
+        J.jl_reorth_pass(ctx, V, u)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(probe=w, ncol=ncol, n=op.n, reps=reps, copy_bytes=2 * (1 << 30))), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +218,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--verbose", action="store_true", help="per-cycle progress on stderr")
+    ap.add_argument("--probe", action="store_true",
+                    help="run the counter probe (copy + apply + reorth pass) instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the multi-GPU "
@@ -205,6 +232,9 @@ def main():
         sys.exit(1)
     J.load_library()
     w = WORKLOADS[args.workload]
+    if args.probe:
+        probe(w)
+        return
     host = make_host_inputs(w)
     ctx = J.Context(0)
     print(f"[bench] {describe(w)}: mixed solves", file=sys.stderr, flush=True)
