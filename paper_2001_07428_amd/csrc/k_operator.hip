@@ -42,23 +42,27 @@ __device__ __forceinline__ void load_site(const cplx<S>* __restrict__ p, C re[4]
     im[c] = (C)v.y;
   }
 }
-template <typename S, typename C>
-__device__ __forceinline__ void load_link(const cplx<S>* __restrict__ p, C re[16], C im[16]) {
+// Four link entries M[r][0..3] (row) or M[0..3][r] (column) of a row-major 4x4.
+template <typename S, typename C, bool ROW>
+__device__ __forceinline__ void load_line(const cplx<S>* __restrict__ M, int r, C re[4], C im[4]) {
 #pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    cplx<S> v = p[c];
+  for (int c = 0; c < 4; ++c) {
+    cplx<S> v = ROW ? M[4 * r + c] : M[4 * c + r];
     re[c] = (C)v.x;
     im[c] = (C)v.y;
   }
 }
 
-// Computes (A v)(s) for one site: top[4], bot[4] in compute type C.
+// Computes (A v)(s) for one site: top[4], bot[4] in compute type C.  One
+// direction and one hop are live at a time and the links are consumed one
+// row (forward hop) or column (backward hop) at a time, which keeps the
+// register footprint small enough for full occupancy without spills.
 template <typename S, typename C>
 __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx<S>* __restrict__ xt,
                                              const cplx<S>* __restrict__ xb, int64_t s,
                                              cx<C> top[4], cx<C> bot[4]) {
-  const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2], L3 = a.L[3];
-  const int64_t st[4] = {(int64_t)L1 * L2 * L3, (int64_t)L2 * L3, (int64_t)L3, 1};
+  const int Ls[4] = {a.L[0], a.L[1], a.L[2], a.L[3]};
+  const int64_t st[4] = {(int64_t)Ls[1] * Ls[2] * Ls[3], (int64_t)Ls[2] * Ls[3], (int64_t)Ls[3], 1};
   int x[4];
   {
     int64_t r = s;
@@ -67,7 +71,6 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx
     x[2] = (int)(r / st[2]); r -= (int64_t)x[2] * st[2];
     x[3] = (int)r;
   }
-  const int Ls[4] = {L0, L1, L2, L3};
   const C dg = (C)a.diag;
   const C sc = (C)a.scale;
   {
@@ -81,72 +84,56 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx
     }
   }
   const int64_t V = a.V;
-#pragma unroll
+#pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
     const int64_t sf = (x[mu] == Ls[mu] - 1) ? s - (int64_t)(Ls[mu] - 1) * st[mu] : s + st[mu];
     const int64_t sb = (x[mu] == 0) ? s + (int64_t)(Ls[mu] - 1) * st[mu] : s - st[mu];
-    // ---- forward hop: U(x) [a(x+mu), conj(b(x+mu))], B(x) b(x+mu), conj(B(x)) a(x+mu)
+    // ---- forward hop: U(x) a(x+mu), conj(U(x)) b(x+mu), B(x) b(x+mu), conj(B(x)) a(x+mu)
     {
       C ar[4], ai[4], br[4], bi[4];
       load_site<S, C>(xt + sf * 4, ar, ai);
       load_site<S, C>(xb + sf * 4, br, bi);
-      C ur[16], ui[16];
-      load_link<S, C>(a.U + ((int64_t)mu * V + s) * 16, ur, ui);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        cx<C> t = {0, 0}, q = {0, 0};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          mac(t, ur[4 * r + c], ui[4 * r + c], ar[c], ai[c]);          // U a_f
-          mac_conj_a(q, ur[4 * r + c], ui[4 * r + c], br[c], bi[c]);   // conj(U) b_f
-        }
-        top[r].re -= t.re; top[r].im -= t.im;
-        bot[r].re -= q.re; bot[r].im -= q.im;
-      }
+      const cplx<S>* Up = a.U + ((int64_t)mu * V + s) * 16;
       const cplx<S>* Bp = a.b_per_site ? a.B + ((int64_t)mu * V + s) * 16 : a.B + mu * 16;
-      load_link<S, C>(Bp, ur, ui);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        cx<C> t = {0, 0}, q = {0, 0};
+        C ur[4], ui[4], wr[4], wi[4];
+        load_line<S, C, true>(Up, r, ur, ui);
+        load_line<S, C, true>(Bp, r, wr, wi);
+        cx<C> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          mac(t, ur[4 * r + c], ui[4 * r + c], br[c], bi[c]);          // B b_f
-          mac_conj_a(q, ur[4 * r + c], ui[4 * r + c], ar[c], ai[c]);   // conj(B) a_f
+          mac(t, ur[c], ui[c], ar[c], ai[c]);          // U a_f
+          mac_conj_a(q, ur[c], ui[c], br[c], bi[c]);   // conj(U) b_f
+          mac(tb, wr[c], wi[c], br[c], bi[c]);         // B b_f
+          mac_conj_a(qb, wr[c], wi[c], ar[c], ai[c]);  // conj(B) a_f
         }
-        top[r].re = fma(sc, t.re, top[r].re); top[r].im = fma(sc, t.im, top[r].im);
-        bot[r].re = fma(-sc, q.re, bot[r].re); bot[r].im = fma(-sc, q.im, bot[r].im);
+        top[r].re += sc * tb.re - t.re; top[r].im += sc * tb.im - t.im;
+        bot[r].re -= q.re + sc * qb.re; bot[r].im -= q.im + sc * qb.im;
       }
     }
-    // ---- backward hop: U(x-mu)^H a(x-mu), U(x-mu)^T b(x-mu), B(x-mu)^T b, B(x-mu)^H a
+    // ---- backward hop: U(x-mu)^H a, U(x-mu)^T b, B(x-mu)^T b, B(x-mu)^H a at x-mu
     {
       C ar[4], ai[4], br[4], bi[4];
       load_site<S, C>(xt + sb * 4, ar, ai);
       load_site<S, C>(xb + sb * 4, br, bi);
-      C ur[16], ui[16];
-      load_link<S, C>(a.U + ((int64_t)mu * V + sb) * 16, ur, ui);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        cx<C> t = {0, 0}, q = {0, 0};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          mac_conj_a(t, ur[4 * c + r], ui[4 * c + r], ar[c], ai[c]);   // U^H a_b
-          mac(q, ur[4 * c + r], ui[4 * c + r], br[c], bi[c]);          // U^T b_b
-        }
-        top[r].re -= t.re; top[r].im -= t.im;
-        bot[r].re -= q.re; bot[r].im -= q.im;
-      }
+      const cplx<S>* Up = a.U + ((int64_t)mu * V + sb) * 16;
       const cplx<S>* Bp = a.b_per_site ? a.B + ((int64_t)mu * V + sb) * 16 : a.B + mu * 16;
-      load_link<S, C>(Bp, ur, ui);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        cx<C> t = {0, 0}, q = {0, 0};
+        C ur[4], ui[4], wr[4], wi[4];
+        load_line<S, C, false>(Up, r, ur, ui);
+        load_line<S, C, false>(Bp, r, wr, wi);
+        cx<C> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          mac(t, ur[4 * c + r], ui[4 * c + r], br[c], bi[c]);          // B^T b_b
-          mac_conj_a(q, ur[4 * c + r], ui[4 * c + r], ar[c], ai[c]);   // B^H a_b
+          mac_conj_a(t, ur[c], ui[c], ar[c], ai[c]);   // U^H a_b
+          mac(q, ur[c], ui[c], br[c], bi[c]);          // U^T b_b
+          mac(tb, wr[c], wi[c], br[c], bi[c]);         // B^T b_b
+          mac_conj_a(qb, wr[c], wi[c], ar[c], ai[c]);  // B^H a_b
         }
-        top[r].re = fma(-sc, t.re, top[r].re); top[r].im = fma(-sc, t.im, top[r].im);
-        bot[r].re = fma(sc, q.re, bot[r].re); bot[r].im = fma(sc, q.im, bot[r].im);
+        top[r].re -= t.re + sc * tb.re; top[r].im -= t.im + sc * tb.im;
+        bot[r].re += sc * qb.re - q.re; bot[r].im += sc * qb.im - q.im;
       }
     }
   }

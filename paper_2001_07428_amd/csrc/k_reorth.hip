@@ -261,19 +261,29 @@ __global__ __launch_bounds__(kReorthThreads) void k_update(const cplx<S>* __rest
   if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
-// out[c] = sum over b of partial[b*stride + c]; 64 columns x 4 block-groups.
+// out[c] = sum over b of partial[b*stride + c].  A block of 256 threads
+// covers C consecutive columns with 256/C threads per column, each summing
+// every (256/C)-th row; the per-column partials are then combined in LDS in
+// a fixed tree order (deterministic).
+template <int C>
 __global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ partial, int nblk,
                                                      int stride, int ncols,
                                                      double* __restrict__ out) {
-  __shared__ double sh[4][64];
-  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
-  const int c = blockIdx.x * 64 + tx;
+  constexpr int G = 256 / C;
+  __shared__ double sh[256];
+  const int tx = threadIdx.x % C, ty = threadIdx.x / C;
+  const int c = blockIdx.x * C + tx;
   double s = 0.0;
   if (c < ncols)
-    for (int b = ty; b < nblk; b += 4) s += partial[(int64_t)b * stride + c];
-  sh[ty][tx] = s;
+    for (int b = ty; b < nblk; b += G) s += partial[(int64_t)b * stride + c];
+  sh[threadIdx.x] = s;
   __syncthreads();
-  if (ty == 0 && c < ncols) out[c] = (sh[0][tx] + sh[1][tx]) + (sh[2][tx] + sh[3][tx]);
+#pragma unroll
+  for (int g = G / 2; g > 0; g /= 2) {
+    if (ty < g) sh[threadIdx.x] += sh[threadIdx.x + g * C];
+    __syncthreads();
+  }
+  if (ty == 0 && c < ncols) out[c] = sh[tx];
 }
 
 template <typename S>
@@ -419,8 +429,13 @@ hipError_t launch_reorth_update(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>
 
 hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int ncols, double* out,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_cols, dim3(blocks_for(ncols, 64)), dim3(256), 0, st, partial, nblk,
-                     stride, ncols, out);
+  if (ncols <= 1)
+    hipLaunchKernelGGL(k_reduce_cols<1>, dim3(1), dim3(256), 0, st, partial, nblk, stride, ncols, out);
+  else if (ncols <= 4)
+    hipLaunchKernelGGL(k_reduce_cols<4>, dim3(1), dim3(256), 0, st, partial, nblk, stride, ncols, out);
+  else
+    hipLaunchKernelGGL(k_reduce_cols<16>, dim3(blocks_for(ncols, 16)), dim3(256), 0, st, partial,
+                       nblk, stride, ncols, out);
   return hipGetLastError();
 }
 
