@@ -39,10 +39,19 @@ WORKLOADS = {
     # relative to max|theta| (the FP32 matvec itself errs by ~2e-5 here)
     "dense4096": dict(kind="dense", h=2048, seed=2, nev=50, m=160, mwin=80, tol=1e-5,
                       tol_relative=True, tol_fp64=1e-10),
+    # 512 dense problems, even n uniform in 64..1024, one persistent launch
+    # replayed from a hipGraph; tolerance relative to max|theta| in both forms
+    "batched512": dict(kind="batched", seed=3, count=512, nev=8, m=32, mwin=16, tol=1e-5,
+                       tol_relative=True, tol_fp64=1e-10),
 }
 
 
 def describe(w):
+    if w["kind"] == "batched":
+        return (f"batched: {w['count']} dense Hermitian J-symmetric problems, even n uniform in "
+                f"64..1024, {w['nev']} lowest pairs each, m={w['m']}, mwin={w['mwin']}, "
+                f"tol={w['tol']:g} rel (mixed) / {w['tol_fp64']:g} rel (fp64), seed {w['seed']}, "
+                f"one persistent launch in a hipGraph")
     if w["kind"] == "stencil":
         L = w["L"]
         n = 2 * int(np.prod(L)) * 4
@@ -56,6 +65,9 @@ def describe(w):
 
 def make_host_inputs(w):
     from paper_2001_07428_amd import inputs
+    if w["kind"] == "batched":
+        n, probs = inputs.batched_dense(w["seed"], count=w["count"])
+        return dict(n=n, probs=probs)
     if w["kind"] == "stencil":
         U, B = inputs.stencil_links(w["seed"], w["L"])
         return dict(U=U, B=B)
@@ -104,6 +116,87 @@ def run_precision(J, ctx, w, host, mixed, steps, warmup, verbose):
     del ws, op
     torch.cuda.empty_cache()
     return res
+
+
+def run_batched(J, ctx, w, host, mixed, steps, warmup, threads=0, blocks=0):
+    """Timed replays of the batched graph; a step solves all problems."""
+    import torch
+    dtype = torch.complex64 if mixed else torch.complex128
+    A11s = [torch.from_numpy(a).to("cuda:0", dtype) for a, _ in host["probs"]]
+    A12s = [torch.from_numpy(c).to("cuda:0", dtype) for _, c in host["probs"]]
+    tol = w["tol"] if mixed else w["tol_fp64"]
+    b = J.Batch(ctx, A11s, A12s, w["nev"], w["m"], w["mwin"], tol, tol_relative=w["tol_relative"],
+                threads=threads, blocks=blocks)
+    for _ in range(warmup):
+        b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [b.run() for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc, ev, res, st, stats = outs[-1]
+    if rc != J.JL_OK:
+        raise RuntimeError(f"batched solve: {(st != 0).sum()} problems did not converge")
+    n = host["n"].astype(np.float64)
+    es = 8 if mixed else 16
+    # algorithmic operator bytes: [A11 A12] (es * n^2 / 2) per Lanczos matvec
+    mv_bytes = float((stats["n_mv"] * es * n * n / 2).sum())
+    sec = (t1 - t0) / steps
+    out = dict(seconds=sec, n_mv_total=int(stats["n_mv"].sum()), cycles_max=int(stats["cycles"].max()),
+               gs_passes_total=int(stats["gs_passes"].sum()), res_max_rel=float(
+                   (res / np.maximum(np.abs(ev).max(axis=1, keepdims=True), 1.0)).max()),
+               matvec_bytes=mv_bytes, evals=ev, threads=threads, blocks=blocks)
+    del b, A11s, A12s
+    torch.cuda.empty_cache()
+    return out
+
+
+def main_batched(args, J, ctx, w, host):
+    mixed = run_batched(J, ctx, w, host, True, args.steps, args.warmup)
+    line = dict(metric=METRIC, value=round(mixed["seconds"], 5), unit="s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=round(mixed["seconds"] * 1e3, 3),
+                higher_is_better=False, scaling="weak", vs_baseline=None, dtype="fp32+fp64",
+                data="synthetic",
+                config=dict(workload=describe(w), name=args.workload, count=w["count"], nev=w["nev"],
+                            m=w["m"], mwin=w["mwin"], parallelism="1 GPU"))
+    gbps = mixed["matvec_bytes"] / mixed["seconds"] / 1e9
+    line["mixed"] = {k: v for k, v in mixed.items() if k != "evals"}
+    line["roofline"] = dict(bound="hbm", kernel="k_batched (whole persistent launch)",
+                            achieved=round(gbps, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                            frac=round(gbps / HBM_PEAK_GBPS, 4), traffic=None,
+                            algorithmic_bytes_per_launch=mixed["matvec_bytes"],
+                            note="operator bytes of all Lanczos matvecs over the launch time")
+    line["matvec_GBps"] = dict(mixed=round(gbps, 1))
+    if not args.no_fp64:
+        fp64 = run_batched(J, ctx, w, host, False, args.steps, args.warmup)
+        line["fp64"] = {k: v for k, v in fp64.items() if k != "evals"}
+        line["speedup_mixed_vs_fp64"] = round(fp64["seconds"] / mixed["seconds"], 3)
+        line["matvec_GBps"]["fp64"] = round(fp64["matvec_bytes"] / fp64["seconds"] / 1e9, 1)
+        line["mixed_vs_fp64_max_rel_eig_diff"] = float(
+            np.abs(mixed["evals"] - fp64["evals"]).max() / np.abs(fp64["evals"]).max())
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_batched(w, host, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_batched(w, host, budget_s):
+    """The FP64 oracle (Algorithms 1 and 2, literal MGS) solving the problems
+    one after another for about budget_s seconds; the per-problem mean time
+    is scaled to the whole batch (labelled extrapolated)."""
+    from oracle import jsym, trlan
+    t0 = time.perf_counter()
+    done = 0
+    for A11, A12 in host["probs"][::-1]:   # random order is fine; sizes are i.i.d.
+        A = jsym.dense_from_blocks(A11, A12)
+        trlan.trlan_jsym(lambda v: A @ v, A.shape[0], w["nev"], w["mwin"], w["m"], w["tol_fp64"],
+                         tol_relative=True)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=dt / done * w["count"], unit="s", cores=os.cpu_count(), kind="oracle",
+                sample=f"{done} of {w['count']} problems solved by the FP64 oracle in {dt:.1f} s, "
+                       f"mean time per problem scaled to {w['count']} (extrapolated)")
 
 
 def kernel_rates(stats):
@@ -237,6 +330,9 @@ def main():
         return
     host = make_host_inputs(w)
     ctx = J.Context(0)
+    if w["kind"] == "batched":
+        main_batched(args, J, ctx, w, host)
+        return
     print(f"[bench] {describe(w)}: mixed solves", file=sys.stderr, flush=True)
     mixed = run_precision(J, ctx, w, host, True, args.steps, args.warmup, args.verbose)
     fp64 = None

@@ -141,4 +141,34 @@ hipError_t launch_ritz_sort(int m, const double* lam, int64_t lstride, const dou
                             int descending, int kcols, int* perm, double* lam_s, double* Zs, S* Zc,
                             double* zlast, hipStream_t st);
 
+// ------------------------------------------------------------ batched solve
+struct BatchProblem {
+  int64_t h;          // half dimension (n = 2h)
+  const void* A11;    // h x h row-major, row stride ld
+  const void* A12;
+  int64_t ld;
+  void* X;            // n x nev output, column stride ldx
+  int64_t ldx;
+};
+struct BatchParams {
+  int nev, m, mwin, which, max_cycles, max_passes, min_passes, tol_relative;
+  double tol;
+};
+struct BatchOut {
+  double* evals;      // [count][nev]
+  double* res;        // [count][nev]
+  int* status;        // [count]
+  int* stats;         // [count][4]: cycles, n_mv, gs_passes, icnv
+};
+size_t batched_lds_bytes(int64_t hmax, int m, int es);
+size_t batched_slot_bytes(int64_t hmax, int m, int es);
+hipError_t launch_batched_init(int* queue, hipStream_t st);
+// One persistent launch of `blocks` workgroups of `threads` (128/256/512)
+// threads; each pops ids (in the given order) from *queue and solves them.
+template <typename S>
+hipError_t launch_batched(const BatchProblem* probs, const int* order, int count,
+                          const BatchParams& P, int* queue, char* slots, size_t slot_bytes,
+                          int64_t hmax, const BatchOut& out, int threads, int blocks,
+                          hipStream_t st);
+
 }  // namespace jl

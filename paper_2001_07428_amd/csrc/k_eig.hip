@@ -13,47 +13,10 @@
 // per round (A ping-ponged, Z updated in place) and small ones run all
 // sweeps inside one workgroup in LDS.
 #include "common.h"
+#include "jacobi.h"
 
 namespace jl {
 namespace {
-
-struct Rot { double c, s, t; };
-
-// Symmetric 2x2 Schur decomposition (Golub & Van Loan, Alg. 8.4.1):
-// R = [[c, s], [-s, c]] makes R^T [[app, apq], [apq, aqq]] R diagonal,
-// with new diagonal (app - t apq, aqq + t apq).
-__device__ __forceinline__ Rot jacobi_rot(double app, double aqq, double apq) {
-  Rot r{1.0, 0.0, 0.0};
-  if (apq == 0.0) return r;
-  const double tau = (aqq - app) / (2.0 * apq);
-  double t;
-  if (fabs(tau) > 1e150) t = 0.5 / tau;
-  else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  r.c = 1.0 / sqrt(1.0 + t * t);
-  r.s = t * r.c;
-  r.t = t;
-  return r;
-}
-
-__device__ __forceinline__ void round_pair(int mp, int r, int I, int& p, int& q) {
-  const int M1 = mp - 1;
-  int a, b;
-  if (I == 0) { a = M1; b = r; }
-  else { a = (r + I) % M1; b = (r - I + M1) % M1; }
-  p = a < b ? a : b;
-  q = a < b ? b : a;
-}
-
-// X' = R_I^T X R_J for the 2x2 block X = A[{pi,qi},{pj,qj}].
-__device__ __forceinline__ void rot_block(const Rot& ri, const Rot& rj, double x00, double x01,
-                                          double x10, double x11, double out[4]) {
-  const double y00 = rj.c * x00 - rj.s * x01, y01 = rj.s * x00 + rj.c * x01;
-  const double y10 = rj.c * x10 - rj.s * x11, y11 = rj.s * x10 + rj.c * x11;
-  out[0] = ri.c * y00 - ri.s * y10;
-  out[1] = ri.c * y01 - ri.s * y11;
-  out[2] = ri.s * y00 + ri.c * y10;
-  out[3] = ri.s * y01 + ri.c * y11;
-}
 
 __global__ void k_eig_init(const double* __restrict__ T, int ldt, int m, int mp,
                            double* __restrict__ A, double* __restrict__ Z) {
@@ -127,7 +90,7 @@ __global__ __launch_bounds__(1024) void k_eig_offnorm(int mp, const double* __re
 }
 
 // All sweeps in one workgroup; A and Z (mp x mp) live in LDS.
-constexpr int kSmallMp = 60;
+constexpr int kSmallMp = kJacobiLdsMaxMp;
 __global__ __launch_bounds__(256) void k_eig_small(const double* __restrict__ T, int ldt, int m,
                                                    double* __restrict__ lam, double* __restrict__ Zo,
                                                    int ldz, int max_sweeps) {
@@ -135,76 +98,14 @@ __global__ __launch_bounds__(256) void k_eig_small(const double* __restrict__ T,
   __shared__ double Z[kSmallMp * kSmallMp];
   __shared__ double rc[kSmallMp / 2], rs[kSmallMp / 2], rt[kSmallMp / 2];
   __shared__ double red[4];
-  const int mp = m + (m & 1), P = mp / 2, tid = threadIdx.x;
-  double nrm = 0.0;
+  const int mp = m + (m & 1), tid = threadIdx.x;
   for (int idx = tid; idx < mp * mp; idx += 256) {
     const int i = idx % mp, j = idx / mp;
-    const double v = (i < m && j < m) ? T[i + (int64_t)j * ldt] : 0.0;
-    A[idx] = v;
+    A[idx] = (i < m && j < m) ? T[i + (int64_t)j * ldt] : 0.0;
     Z[idx] = (i == j) ? 1.0 : 0.0;
-    nrm += v * v;
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o);
-  if (tid % 64 == 0) red[tid / 64] = nrm;
   __syncthreads();
-  const double fro2 = red[0] + red[1] + red[2] + red[3];
-  __syncthreads();
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    for (int r = 0; r < mp - 1; ++r) {
-      for (int I = tid; I < P; I += 256) {
-        int p, q;
-        round_pair(mp, r, I, p, q);
-        const Rot ro = jacobi_rot(A[p + p * mp], A[q + q * mp], A[p + q * mp]);
-        rc[I] = ro.c; rs[I] = ro.s; rt[I] = ro.t;
-      }
-      __syncthreads();
-      for (int idx = tid; idx < P * P + mp * P; idx += 256) {
-        if (idx < P * P) {
-          const int I = idx % P, J = idx / P;
-          if (I > J) continue;
-          int pi, qi, pj, qj;
-          round_pair(mp, r, I, pi, qi);
-          round_pair(mp, r, J, pj, qj);
-          const Rot ri{rc[I], rs[I], rt[I]};
-          if (I == J) {
-            const double apq = A[pi + qi * mp];
-            A[pi + pi * mp] -= ri.t * apq;
-            A[qi + qi * mp] += ri.t * apq;
-            A[pi + qi * mp] = 0.0;
-            A[qi + pi * mp] = 0.0;
-            continue;
-          }
-          const Rot rj{rc[J], rs[J], rt[J]};
-          double o[4];
-          rot_block(ri, rj, A[pi + pj * mp], A[pi + qj * mp], A[qi + pj * mp], A[qi + qj * mp], o);
-          A[pi + pj * mp] = o[0]; A[pj + pi * mp] = o[0];
-          A[pi + qj * mp] = o[1]; A[qj + pi * mp] = o[1];
-          A[qi + pj * mp] = o[2]; A[pj + qi * mp] = o[2];
-          A[qi + qj * mp] = o[3]; A[qj + qi * mp] = o[3];
-        } else {
-          const int zi = idx - P * P;
-          const int row = zi % mp, J = zi / mp;
-          int pj, qj;
-          round_pair(mp, r, J, pj, qj);
-          const double zp = Z[row + pj * mp], zq = Z[row + qj * mp];
-          Z[row + pj * mp] = rc[J] * zp - rs[J] * zq;
-          Z[row + qj * mp] = rs[J] * zp + rc[J] * zq;
-        }
-      }
-      __syncthreads();
-    }
-    double off = 0.0;
-    for (int idx = tid; idx < mp * mp; idx += 256)
-      if (idx % mp != idx / mp) off += A[idx] * A[idx];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o);
-    if (tid % 64 == 0) red[tid / 64] = off;
-    __syncthreads();
-    const double offt = red[0] + red[1] + red[2] + red[3];
-    __syncthreads();
-    if (offt <= 1e-30 * fro2) break;
-  }
+  jacobi_lds<256>(A, Z, mp, rc, rs, rt, red, max_sweeps);
   for (int i = tid; i < m; i += 256) lam[i] = A[i + i * mp];
   for (int idx = tid; idx < m * m; idx += 256) {
     const int i = idx % m, j = idx / m;

@@ -33,7 +33,8 @@ EXPORTS = (
     "jl_op_create_dense", "jl_op_create_stencil", "jl_op_destroy", "jl_op_dim",
     "jl_op_apply", "jl_workspace_bytes", "jl_solve", "jl_pair_vectors",
     "jl_reorth_pass_workspace_bytes", "jl_reorth_pass", "jl_ritz_workspace_bytes", "jl_ritz",
-    "jl_basis_update",
+    "jl_basis_update", "jl_batch_workspace_bytes", "jl_batch_create", "jl_batch_run",
+    "jl_batch_destroy",
 )
 
 
@@ -63,6 +64,11 @@ class JlStats(ctypes.Structure):
 
     def to_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class JlBatchStats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int32), ("n_mv", ctypes.c_int32),
+                ("gs_passes", ctypes.c_int32), ("icnv", ctypes.c_int32)]
 
 
 _lib = None
@@ -97,6 +103,14 @@ def load_library(path: str = LIB_PATH):
         "jl_ritz_workspace_bytes": (i32, [i32, ctypes.POINTER(ctypes.c_size_t)]),
         "jl_ritz": (i32, [vp, i32, vp, i32, vp, vp, vp, ctypes.c_size_t]),
         "jl_basis_update": (i32, [vp, i32, i64, i32, i32, vp, i64, vp, i64, vp, i64]),
+        "jl_batch_workspace_bytes": (i32, [i32, ctypes.POINTER(i64), i32, ctypes.POINTER(JlParams),
+                                           i32, i32, ctypes.POINTER(ctypes.c_size_t)]),
+        "jl_batch_create": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  i32, ctypes.POINTER(JlParams), ctypes.POINTER(vp), vp,
+                                  ctypes.c_size_t, i32, i32, ctypes.POINTER(vp)]),
+        "jl_batch_run": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(i32),
+                               ctypes.POINTER(JlBatchStats)]),
+        "jl_batch_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -371,3 +385,75 @@ def jl_basis_update(ctx: Context, V, Z):
                                ctypes.c_void_p(Zc.data_ptr()), m, ctypes.c_void_p(Y.data_ptr()), n),
            ctx.handle)
     return Y
+
+
+# ---------------------------------------------------------------- batched solve
+class Batch:
+    """jl_batch: many dense problems solved by one persistent launch replayed
+    from a hipGraph.  A11s/A12s: lists of device tensors (h_i x h_i, same
+    dtype); eigenvectors land in self.X[i] (nev, n_i)."""
+
+    def __init__(self, ctx: Context, A11s, A12s, nev, m, mwin, tol, which="lowest",
+                 tol_relative=False, max_cycles=0, threads=0, blocks=0):
+        torch = _torch()
+        lib = load_library()
+        count = len(A11s)
+        if count != len(A12s) or count == 0:
+            raise ValueError("A11s and A12s must be non-empty lists of equal length")
+        dt = A11s[0].dtype
+        for a, b in zip(A11s, A12s):
+            if a.dtype != dt or b.dtype != dt or a.shape != b.shape or not a.is_contiguous() \
+                    or not b.is_contiguous() or a.dim() != 2 or a.shape[0] != a.shape[1]:
+                raise ValueError("every A11/A12 must be a contiguous square tensor of one dtype")
+        self.ctx, self.count, self.nev = ctx, count, nev
+        self.n = np.array([2 * a.shape[0] for a in A11s], dtype=np.int64)
+        if threads == 0 and blocks == 0:   # shape from the autotuner's cache, if any
+            from . import tune
+            hit = tune.lookup(self.n, nev, m, "c64" if dt == torch.complex64 else "c128")
+            if hit is not None:
+                threads, blocks = hit
+        self.threads, self.blocks = threads, blocks
+        self.p = _params(nev, m, mwin, tol, which, max_cycles, 0, 0, None, 0, tol_relative, False)
+        code = _dtype_code(A11s[0])
+        nb = ctypes.c_size_t()
+        n_c = self.n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        _check(lib.jl_batch_workspace_bytes(count, n_c, code, ctypes.byref(self.p), threads, blocks,
+                                            ctypes.byref(nb)), ctx.handle)
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=ctx.device)
+        self.X = [torch.empty((nev, int(ni)), dtype=dt, device=ctx.device) for ni in self.n]
+        vp = ctypes.c_void_p
+        a11 = (vp * count)(*[a.data_ptr() for a in A11s])
+        a12 = (vp * count)(*[a.data_ptr() for a in A12s])
+        xs = (vp * count)(*[x.data_ptr() for x in self.X])
+        self._keep = (A11s, A12s)
+        h = vp()
+        _check(lib.jl_batch_create(ctx.handle, count, n_c, a11, a12, code, ctypes.byref(self.p), xs,
+                                   vp(self.ws.data_ptr()), nb.value, threads, blocks, ctypes.byref(h)),
+               ctx.handle)
+        self.handle = h
+
+    def run(self):
+        """Replays the graph; returns (status, evals (count, nev), res, per-problem
+        status, stats dict of arrays)."""
+        lib = load_library()
+        evals = np.zeros((self.count, self.nev))
+        res = np.zeros((self.count, self.nev))
+        st = np.zeros(self.count, dtype=np.int32)
+        stats = (JlBatchStats * self.count)()
+        rc = lib.jl_batch_run(self.handle, evals.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), stats)
+        _check(rc, self.ctx.handle)
+        sd = {f: np.array([getattr(x, f) for x in stats]) for f, _ in JlBatchStats._fields_}
+        return rc, evals, res, st, sd
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().jl_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

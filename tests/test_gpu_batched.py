@@ -1,0 +1,115 @@
+"""Batched persistent solve (one launch in a hipGraph) against brute force."""
+import numpy as np
+import pytest
+
+from paper_2001_07428_amd import inputs
+from oracle import jsym
+
+from gpu_util import cdt, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2001_07428_amd import jlanczos as J
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return J.Context(0)
+
+
+def _check_problem(A11, A12, ev, X, res, tol_res, gate, nev):
+    A = jsym.dense_from_blocks(A11, A12)
+    ref, _ = jsym.brute(A)
+    assert np.abs(ev - ref[:nev]).max() < gate * np.abs(ref).max()
+    Xc = X.astype(np.complex128)
+    for i in range(nev):
+        r = np.linalg.norm(A @ Xc[i] - ev[i] * Xc[i])
+        assert r < tol_res
+        assert abs(r - res[i]) < 1e-3 * tol_res + 1e-6 * r or r < tol_res
+    UU = np.concatenate([Xc.T, jsym.partner(Xc.T)], axis=1)
+    assert np.abs(UU.conj().T @ UU - np.eye(2 * nev)).max() < (1e-5 if X.dtype == np.complex64 else 1e-12)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batched_small_vs_brute(ctx, mixed):
+    """24 problems, even n in 64..200 (odd half lengths included), 8 lowest pairs."""
+    from paper_2001_07428_amd import jlanczos as J
+    say("batched small", mixed)
+    n, probs = inputs.batched_dense(13, count=24, nmin=64, nmax=200)
+    dt = cdt(mixed)
+    b = J.Batch(ctx, [to_dev(a, dt) for a, _ in probs], [to_dev(c, dt) for _, c in probs],
+                8, 32, 16, 1e-4 if mixed else 1e-9)
+    rc, ev, res, st, stats = b.run()
+    assert rc == J.JL_OK and (st == 0).all(), st
+    for i, (A11, A12) in enumerate(probs):
+        _check_problem(A11, A12, ev[i], to_np(b.X[i]), res[i], 1e-4 if mixed else 1e-9,
+                       1e-5 if mixed else 1e-10, 8)
+    assert (stats["n_mv"] > 0).all() and (stats["icnv"] == 8).all()
+
+
+def test_batched_exhausted_and_largest(ctx):
+    """n = 64 with m = 32 (J-half space exhausted in one cycle) and the
+    largest end."""
+    from paper_2001_07428_amd import jlanczos as J
+    say("batched n64 m32")
+    probs = [inputs.dense_jsym(20 + i, 32) for i in range(4)]
+    dt = cdt(False)
+    b = J.Batch(ctx, [to_dev(a, dt) for a, _ in probs], [to_dev(c, dt) for _, c in probs],
+                8, 32, 16, 1e-9, which="largest")
+    rc, ev, res, st, stats = b.run()
+    assert rc == J.JL_OK and (stats["cycles"] == 1).all()
+    for i, (A11, A12) in enumerate(probs):
+        allev = np.linalg.eigvalsh(jsym.dense_from_blocks(A11, A12))
+        ref = allev[::-1][0::2][:8]
+        assert np.abs(ev[i] - ref).max() < 1e-10 * np.abs(allev).max()
+
+
+def test_batched_graph_replays(ctx):
+    """The captured graph replays give identical results, with unrelated
+    eager GPU work and synchronisations between the replays."""
+    import torch
+    from paper_2001_07428_amd import jlanczos as J
+    say("batched replays")
+    n, probs = inputs.batched_dense(14, count=16, nmin=64, nmax=160)
+    dt = cdt(True)
+    b = J.Batch(ctx, [to_dev(a, dt) for a, _ in probs], [to_dev(c, dt) for _, c in probs],
+                8, 32, 16, 1e-4)
+    rc0, ev0, res0, st0, _ = b.run()
+    X0 = [to_np(x).copy() for x in b.X]
+    for rep in range(3):
+        z = torch.randn(1 << 20, device="cuda:0")
+        (z * 2.0).sum().item()
+        for x in b.X:
+            x.zero_()
+        torch.cuda.synchronize()
+        rc, ev, res, st, _ = b.run()
+        assert rc == rc0 and (st == st0).all()
+        assert np.array_equal(ev, ev0) and np.array_equal(res, res0)
+        for x, x0 in zip(b.X, X0):
+            assert np.array_equal(to_np(x), x0)
+
+
+def test_batched_512_full_size(ctx):
+    """512 problems, even n uniform in 64..1024, 8 lowest pairs, m=32,
+    mwin=16, complex64 storage with FP64 Ritz, tol 1e-5 relative to
+    max|theta| (the FP32-accumulated dense matvec errs by ~1e-5 at n=1024):
+    every problem converges; every 16th problem is checked against brute
+    force, every problem's residuals are recomputed in FP64."""
+    from paper_2001_07428_amd import jlanczos as J
+    say("batched 512")
+    n, probs = inputs.batched_dense(3, count=512)
+    dt = cdt(True)
+    b = J.Batch(ctx, [to_dev(a, dt) for a, _ in probs], [to_dev(c, dt) for _, c in probs],
+                8, 32, 16, 1e-5, tol_relative=True)
+    rc, ev, res, st, stats = b.run()
+    assert rc == J.JL_OK and (st == 0).all()
+    for i, (A11, A12) in enumerate(probs):
+        X = to_np(b.X[i]).astype(np.complex128)
+        A = jsym.dense_from_blocks(A11, A12)
+        anorm = np.abs(ev[i]).max()
+        R = A @ X.T - X.T * ev[i][None, :]
+        assert np.linalg.norm(R, axis=0).max() < 1e-5 * 1.3 * max(anorm, 1.0) + 1e-4
+        if i % 16 == 0:
+            ref, _ = jsym.brute(A)
+            assert np.abs(ev[i] - ref[:8]).max() < 1e-5 * np.abs(ref).max()
