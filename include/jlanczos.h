@@ -104,8 +104,10 @@ typedef struct {
   int32_t mwin;         /* restart window: k = min(icnv + mwin, m - 1)         */
   int32_t which;        /* jl_which                                            */
   double tol;           /* residual tolerance: ||A x - lambda x|| < tol          */
-  int32_t tol_relative; /* nonzero: the tolerance is tol * max_i |theta_i| over
-                           the current Ritz values (an estimate of ||A||_2)    */
+  int32_t tol_relative; /* nonzero: the tolerance is tol * max |theta| over
+                           every Ritz value of this and the earlier cycles (a
+                           non-decreasing estimate of ||A||_2, so a pair
+                           decoupled as converged stays converged)            */
   int32_t max_cycles;   /* outer-iteration cap (<= 0: 10000)                   */
   int32_t max_passes;   /* reorthogonalisation passes per step cap (<= 0: 16)  */
   int32_t min_passes;   /* passes before the sqrt(2) test applies (<= 0: 1)    */
@@ -161,6 +163,46 @@ jl_status jl_solve(jl_op op, const jl_params* p, const void* v1, void* ws, size_
  * X == Y and ldx == ldy. */
 jl_status jl_pair_vectors(jl_ctx ctx, int64_t n, int32_t k, jl_dtype dtype, const void* X,
                           int64_t ldx, void* Y, int64_t ldy);
+
+/* ------------------------------------------------------------------------
+ * Batched solve: many independent dense problems of (possibly different)
+ * even sizes, each A = [[A11, A12], [A12^H, A11^T]] with h_i x h_i row-major
+ * contiguous blocks (device), solved with the same jl_params in one
+ * persistent launch.  Every workgroup runs the whole of Algorithms 1 and 2
+ * for the problems it takes from a shared queue, largest first.  The launch,
+ * the queue reset and the result copies are captured once in a hipGraph at
+ * jl_batch_create and replayed by every jl_batch_run.
+ *
+ * Limits: m + (m mod 2) <= 60, 2 <= n_i, m <= n_i / 2, nev <= mwin < m.
+ * threads: workgroup size (128, 256 or 512; 0 = 256); blocks: persistent
+ * workgroups (0 = min(count, 2 x compute units)); both are tuning knobs.
+ * X[i] (device, n_i x nev column-major, leading dimension n_i) receives the
+ * eigenvectors of problem i; the operator and X pointers are borrowed until
+ * jl_batch_destroy.  Errors: JL_EINVAL, JL_ENOMEM, JL_EHIP.
+ * ------------------------------------------------------------------------ */
+typedef struct jl_batch_s* jl_batch;
+
+typedef struct {
+  int32_t cycles;       /* outer iterations                                     */
+  int32_t n_mv;         /* Lanczos matvecs                                      */
+  int32_t gs_passes;    /* reorthogonalisation passes                           */
+  int32_t icnv;         /* converged pairs                                      */
+} jl_batch_stats;
+
+jl_status jl_batch_workspace_bytes(int32_t count, const int64_t* n, jl_dtype dtype,
+                                   const jl_params* p, int32_t threads, int32_t blocks,
+                                   size_t* bytes);
+jl_status jl_batch_create(jl_ctx ctx, int32_t count, const int64_t* n, const void* const* A11,
+                          const void* const* A12, jl_dtype dtype, const jl_params* p,
+                          void* const* X, void* ws, size_t ws_bytes, int32_t threads,
+                          int32_t blocks, jl_batch* out);
+/* Runs the captured graph and waits for it.  evals, res: host [count * nev]
+ * (problem-major, converged pairs first); status: host [count] (JL_OK,
+ * JL_NOT_CONVERGED or JL_BREAKDOWN per problem); stats: host [count] or NULL.
+ * Returns JL_OK if every problem converged, else JL_NOT_CONVERGED. */
+jl_status jl_batch_run(jl_batch b, double* evals, double* res, int32_t* status,
+                       jl_batch_stats* stats);
+jl_status jl_batch_destroy(jl_batch b);
 
 #ifdef __cplusplus
 }

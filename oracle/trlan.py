@@ -24,7 +24,11 @@ with 0-based indices: V has columns v_0..v_m, the projected matrix Tbar is
   is zero, and every candidate's true residual is checked; if not all nev
   pairs converge the solve stops with status "breakdown".
 * tol is absolute as in the paper; tol_relative=True scales it by the largest
-  |Ritz value| of the cycle (an estimate of ||A||_2).
+  |Ritz value| seen so far, a running maximum over the cycles (an estimate of
+  ||A||_2 that never shrinks).  A per-cycle scale would move with the window's
+  extreme Ritz value, and a pair decoupled as converged is frozen, so a pair
+  whose residual sits at the threshold could drop out of the converged set
+  and never return.
 * min_passes > 1 takes the sqrt(2) test only from that pass on (default 1,
   the paper's rule; the FP32-storage GPU solver uses 2).
 * The J-restriction uses w_i = J v_i^* (Alg. 2 builds W alongside V).  With
@@ -127,6 +131,7 @@ def trlan_jsym(apply, n, nev, mwin, m, tol, which="lowest", v1=None,
     status = "not_converged"
     ev = res = None
     icnv = 0
+    scale = 0.0                                  # running max |theta| (tol_relative)
     for cycle in range(max_cycles):
         stats["n_conv"] += 1
         meff, broke = lanczos_jsym(apply, V, T, k, m, stats, jsym=jsym,
@@ -148,7 +153,8 @@ def trlan_jsym(apply, n, nev, mwin, m, tol, which="lowest", v1=None,
         res_est = np.abs(s[:nev])
         res = np.full(nev, np.inf)
         is_convd = np.zeros(nev, dtype=bool)
-        tol_c = tol * np.abs(lam).max() if tol_relative else tol
+        scale = max(scale, np.abs(lam).max())
+        tol_c = tol * scale if tol_relative else tol
         for i in range(nev):
             if res_est[i] < tol_c:               # check true residuals
                 r = apply(V[:, i]) - V[:, i] * ev[i]

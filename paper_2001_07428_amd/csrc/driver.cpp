@@ -369,6 +369,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   double maxT = 0.0;
   std::vector<double> Tm((size_t)m * m);
   std::vector<double> lam_sorted(m), svec(m);
+  double tol_scale = 0.0;   // running max |theta| for tol_relative
   std::vector<char> conv(nev);
   std::vector<double> resv(nev);
   int k = 0;
@@ -506,9 +507,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       svec[i] = beta_m * h_zl[i];   // t_{m+1,i} = t_{m+1,m} z_{m,i}
     }
     // ================= convergence check on the true residuals (Alg. 1)
-    const double tol_abs =
-        prm->tol_relative ? prm->tol * std::max(std::fabs(lam_sorted[0]), std::fabs(lam_sorted[meff - 1]))
-                          : prm->tol;
+    tol_scale = std::max(tol_scale, std::max(std::fabs(lam_sorted[0]), std::fabs(lam_sorted[meff - 1])));
+    const double tol_abs = prm->tol_relative ? prm->tol * tol_scale : prm->tol;
     int ncand = 0;
     for (int i = 0; i < nev; ++i) {
       conv[i] = 0;

@@ -257,7 +257,7 @@ __device__ void solve_one(const BatchProblem& pb, int pid, const BatchParams& P,
   __syncthreads();
   auto Tat = [&](int i, int j) -> double& { return L.T[i + j * (m + 1)]; };
   int k = 0, icnv = 0, status = 1, n_mv = 0, passes_tot = 0, cycles = 0;
-  double maxT = 0.0;
+  double maxT = 0.0, tol_scale = 0.0;
   const double sqrt2 = 1.4142135623730951;
   for (int cycle = 0; cycle < P.max_cycles; ++cycle) {
     ++cycles;
@@ -354,8 +354,8 @@ __device__ void solve_one(const BatchProblem& pb, int pid, const BatchParams& P,
     }
     __syncthreads();
     // ---- true residuals of the candidates
-    double tolc = P.tol;
-    if (P.tol_relative) tolc *= fmax(fabs(L.lam[0]), fabs(L.lam[meff - 1]));
+    tol_scale = fmax(tol_scale, fmax(fabs(L.lam[0]), fabs(L.lam[meff - 1])));
+    const double tolc = P.tol_relative ? P.tol * tol_scale : P.tol;
     for (int i = 0; i < nev; ++i) {
       double r2 = INFINITY;
       if (fabs(L.svec[i]) < tolc) {

@@ -252,6 +252,36 @@ def test_breakdown_on_invariant_start():
     assert out["status"] == "breakdown"
 
 
+def _batched_problem(seed, index):
+    """Problem `index` of the 512-problem batched recipe, without keeping the
+    others in memory."""
+    rng, n = inputs.batched_sizes(seed)
+    for i in range(index + 1):
+        A11, A12 = inputs.dense_jsym(rng, int(n[i]) // 2)
+    return jsym.dense_from_blocks(A11, A12)
+
+
+def test_relative_tolerance_keeps_converged_pairs():
+    """With tol_relative the scale is a running maximum of |theta|: a pair
+    decoupled as converged (its coupling set to zero, Alg. 1) is frozen, so it
+    must never leave the converged set.  Problem 331 of the batched recipe
+    (n = 580) has a pair whose residual sits at 1e-5 max|theta|; a per-cycle
+    scale dropped it at the fourth cycle."""
+    A = _batched_problem(3, 331).astype(np.complex64).astype(np.complex128)
+    ref, _ = jsym.brute(A)
+    out = trlan.trlan_jsym(lambda v: A @ v, A.shape[0], 8, 16, 32, 1e-5, "lowest",
+                           np.ones(A.shape[0], complex), max_cycles=60, tol_relative=True,
+                           record_history=True)
+    assert out["status"] == "ok"
+    assert np.abs(np.sort(out["ev"]) - ref[:8]).max() < 1e-5 * np.abs(ref).max()
+    prev = np.zeros(0)
+    for h in out["history"]:
+        now = h["ev"][:h["icnv"]]
+        for e in prev:
+            assert np.abs(now - e).min() < 1e-12 * abs(e)
+        prev = now
+
+
 def test_invalid_parameters():
     A = _dense(1, 10)
     f = lambda v: A @ v
