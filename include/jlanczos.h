@@ -28,12 +28,14 @@
  *    column-major with a leading dimension in elements.
  *  - "device" pointers are HIP device memory on the context's device;
  *    "host" pointers are ordinary host memory.  The library never takes
- *    ownership of caller buffers; operator data are borrowed for the
+ *    ownership of caller buffers; dense operator data are borrowed for the
  *    lifetime of the operator, other buffers for the duration of the call.
- *  - All GPU work is ordered on the context's stream.  Calls that return
- *    host results (jl_solve) synchronise that stream before returning.
- *  - The library allocates no device memory: the solver's scratch space is
- *    the caller's workspace (size from jl_workspace_bytes).
+ *  - All GPU work is ordered after the context's stream.  Calls that return
+ *    host results (jl_solve) wait for their own work before returning.
+ *  - The solver's scratch space is the caller's workspace (size from
+ *    jl_workspace_bytes).  The only device memory the library allocates is
+ *    the stencil operator's copy of its links (jl_op_create_stencil); a
+ *    batch also holds pinned host memory for its results (jl_batch_create).
  */
 #ifndef JLANCZOS_H
 #define JLANCZOS_H
@@ -63,7 +65,10 @@ typedef struct jl_ctx_s* jl_ctx;
 typedef struct jl_op_s* jl_op;
 
 /* Context on HIP device `device`, ordering all work on `hip_stream`
- * (a hipStream_t, borrowed; NULL = the device's null stream). */
+ * (a hipStream_t, borrowed; NULL = the device's null stream).  jl_solve
+ * issues its launches on a non-blocking stream the context owns (created on
+ * first use, default priority), started after the work already queued on
+ * hip_stream, and synchronises it before returning. */
 jl_status jl_ctx_create(jl_ctx* out, int32_t device, void* hip_stream);
 jl_status jl_ctx_destroy(jl_ctx ctx);
 /* Last error message of `ctx` (or of the calling thread when ctx is NULL). */
@@ -84,8 +89,13 @@ jl_status jl_op_create_dense(jl_ctx ctx, int64_t n, const void* A11, const void*
  * (T_mu a)(x) = a(x + mu_hat) periodic.  U: device [4][V][d][d] row-major
  * complex links (unitarity not required); B: device [4][d][d] (b_per_site =
  * 0) or [4][V][d][d] (b_per_site = 1).  The result is Hermitian J-symmetric
- * by construction.  Errors: JL_EINVAL for L[i] < 2 or NULL pointers;
- * JL_EUNSUPPORTED for d != 4. */
+ * by construction.  The operator keeps its own device copy of U and B with
+ * the lattice site as the fastest index (64 V complex elements of the dtype,
+ * twice that with per-site B; freed by jl_op_destroy), made on the ctx
+ * stream before the call returns: U and B are not referenced afterwards.
+ * Vectors passed to this operator must be 16-byte aligned.  Errors:
+ * JL_EINVAL for L[i] < 2 or NULL pointers; JL_EUNSUPPORTED for d != 4;
+ * JL_ENOMEM when the link copy cannot be allocated. */
 jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double diag,
                                double a12_scale, const void* U, const void* B,
                                int32_t b_per_site, jl_dtype dtype, jl_op* out);

@@ -25,6 +25,9 @@ constexpr int kWave = 64;
 // Every launcher enqueues on `st` and returns the launch error (if any).
 
 // Stencil operator data (d = 4).  U: [4][V][4][4], B: [4][4][4] or [4][V][4][4].
+// Stencil operator data.  U: links in site-fastest order, entry e of U_mu(s)
+// at U[(mu * 16 + e) * V + s]; B: the 4 direction matrices [mu][16], or with
+// b_per_site the layout of U.
 template <typename S> struct StencilArgs {
   const cplx<S>* U;
   const cplx<S>* B;
@@ -45,6 +48,10 @@ int stencil_apply_blocks(int64_t V);
 // Per-block partial sums of ||A x_c - lam_c x_c||^2 (FP64 compute) for ncols
 // columns x_c = X + cols[c]*ldx (cols, lam on the device); partial layout
 // [blk][c]; *nblk = blocks per column.
+// dst[(mu * 16 + e) * V + s] = src[(mu * V + s) * 16 + e] for 4 directions.
+template <typename S>
+hipError_t launch_links_site_fastest(const cplx<S>* src, cplx<S>* dst, int64_t V, hipStream_t st);
+
 template <typename S>
 hipError_t launch_stencil_resid(const StencilArgs<S>& a, const cplx<S>* X, int64_t ldx,
                                 const int* cols, const double* lam, int ncols, double* partial,

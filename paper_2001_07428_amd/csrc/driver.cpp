@@ -43,9 +43,29 @@ struct jl_op_s {
   StencilArgs<double> sd{};
   DenseArgs<float> df{};
   DenseArgs<double> dd{};
+  void* links = nullptr;   // stencil: owned site-fastest copy of U (and per-site B)
+  ~jl_op_s() {
+    if (links) (void)hipFree(links);
+  }
 };
 
 namespace jl {
+
+hipError_t work_stream(jl_ctx ctx, hipStream_t* out) {
+  hipError_t e;
+  if (!ctx->work && (e = hipStreamCreateWithFlags(&ctx->work, hipStreamNonBlocking)) != hipSuccess) {
+    ctx->work = nullptr;
+    return e;
+  }
+  if (!ctx->order && (e = hipEventCreateWithFlags(&ctx->order, hipEventDisableTiming)) != hipSuccess) {
+    ctx->order = nullptr;
+    return e;
+  }
+  if ((e = hipEventRecord(ctx->order, ctx->stream)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(ctx->work, ctx->order, 0)) != hipSuccess) return e;
+  *out = ctx->work;
+  return hipSuccess;
+}
 
 jl_status set_err(jl_ctx ctx, jl_status code, const char* fmt, ...) {
   char buf[512];
@@ -291,7 +311,8 @@ template <typename S>
 jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws, size_t ws_bytes,
                      double* evals, void* Xout, int64_t ldx, double* res_out, jl_stats* stats) {
   jl_ctx ctx = op->ctx;
-  hipStream_t st = ctx->stream;
+  hipStream_t st = nullptr;
+  JL_HIP(ctx, work_stream(ctx, &st));
   const auto t_begin = std::chrono::steady_clock::now();
   jl_stats S_{};
   const int64_t n = op->n, h = n / 2;
@@ -667,11 +688,44 @@ jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double
   if (!U || !B) return set_err(ctx, JL_EINVAL, "U and B are required");
   if (dtype != JL_C64 && dtype != JL_C128) return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
   const int64_t V = (int64_t)L[0] * L[1] * L[2] * L[3];
+  const size_t es = dtype == JL_C64 ? sizeof(float2) : sizeof(double2);
+  const size_t ubytes = (size_t)64 * V * es;
+  const size_t bbytes = b_per_site ? ubytes : 64 * es;
+  DeviceGuard g(ctx->device);
+  void* links = nullptr;
+  hipError_t e = hipMalloc(&links, ubytes + bbytes);
+  if (e != hipSuccess) {
+    return set_err(ctx, JL_ENOMEM, "stencil link copy (%zu bytes): %s", ubytes + bbytes,
+                   hipGetErrorString(e));
+  }
+  char* ub = static_cast<char*>(links);
+  char* bb = ub + ubytes;
+  if (dtype == JL_C64) {
+    e = launch_links_site_fastest<float>(static_cast<const float2*>(U), reinterpret_cast<float2*>(ub), V,
+                                         ctx->stream);
+    if (e == hipSuccess)
+      e = b_per_site ? launch_links_site_fastest<float>(static_cast<const float2*>(B),
+                                                        reinterpret_cast<float2*>(bb), V, ctx->stream)
+                     : hipMemcpyAsync(bb, B, bbytes, hipMemcpyDeviceToDevice, ctx->stream);
+  } else {
+    e = launch_links_site_fastest<double>(static_cast<const double2*>(U), reinterpret_cast<double2*>(ub),
+                                          V, ctx->stream);
+    if (e == hipSuccess)
+      e = b_per_site ? launch_links_site_fastest<double>(static_cast<const double2*>(B),
+                                                         reinterpret_cast<double2*>(bb), V, ctx->stream)
+                     : hipMemcpyAsync(bb, B, bbytes, hipMemcpyDeviceToDevice, ctx->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(links);
+    return set_err(ctx, JL_EHIP, "stencil link copy: %s", hipGetErrorString(e));
+  }
   jl_op o = new jl_op_s();
   o->ctx = ctx;
   o->kind = OP_STENCIL;
   o->dtype = dtype;
   o->n = 2 * V * 4;
+  o->links = links;
   StencilArgs<float> sf{};
   StencilArgs<double> sd{};
   for (int i = 0; i < 4; ++i) sf.L[i] = sd.L[i] = L[i];
@@ -679,10 +733,10 @@ jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double
   sf.b_per_site = sd.b_per_site = b_per_site ? 1 : 0;
   sf.diag = sd.diag = diag;
   sf.scale = sd.scale = a12_scale;
-  sf.U = static_cast<const float2*>(U);
-  sf.B = static_cast<const float2*>(B);
-  sd.U = static_cast<const double2*>(U);
-  sd.B = static_cast<const double2*>(B);
+  sf.U = reinterpret_cast<const float2*>(ub);
+  sf.B = reinterpret_cast<const float2*>(bb);
+  sd.U = reinterpret_cast<const double2*>(ub);
+  sd.B = reinterpret_cast<const double2*>(bb);
   o->sf = sf;
   o->sd = sd;
   *out = o;
@@ -705,6 +759,9 @@ jl_status jl_op_apply(jl_op op, const void* x, void* y, int32_t nrhs) {
   jl_ctx ctx = op->ctx;
   if (!x || !y || nrhs < 0) return set_err(ctx, JL_EINVAL, "x, y required and nrhs >= 0");
   if (nrhs == 0) return JL_OK;
+  if (op->kind == OP_STENCIL &&
+      ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % 16 != 0))
+    return set_err(ctx, JL_EINVAL, "stencil vectors must be 16-byte aligned");
   DeviceGuard g(ctx->device);
   if (op->dtype == JL_C64)
     JL_HIP(ctx, op_apply<float>(op, static_cast<const float2*>(x), static_cast<float2*>(y), op->n, nrhs, nullptr, ctx->stream));

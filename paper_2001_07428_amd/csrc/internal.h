@@ -10,11 +10,23 @@
 
 struct jl_ctx_s {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // caller's stream (borrowed; NULL = legacy default stream)
+  hipStream_t work = nullptr;     // owned non-blocking stream for jl_solve's launch sequence
+  hipEvent_t order = nullptr;     // orders `work` after `stream`
   std::string err;
+  ~jl_ctx_s() {
+    if (order) (void)hipEventDestroy(order);
+    if (work) (void)hipStreamDestroy(work);
+  }
 };
 
 namespace jl {
+
+// The ctx's own non-blocking stream (created on first use, default
+// priority), made to wait for the work already queued on the caller's
+// stream.  A solve issues thousands of small launches; on the legacy default
+// stream each one also synchronises with the other blocking streams.
+hipError_t work_stream(jl_ctx ctx, hipStream_t* out);
 
 // Records the message for jl_last_error(ctx) (and the calling thread) and
 // returns `code`.

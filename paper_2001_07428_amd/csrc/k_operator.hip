@@ -6,7 +6,8 @@
 //
 // Stencil: one thread per lattice site computes all 4 internal components of
 // both halves; the link U_mu(x) is read once for the forward hop of both
-// halves and U_mu(x - mu) once for the backward hop.
+// halves and U_mu(x - mu) once for the backward hop, from the operator's
+// site-fastest copy of the links (coalesced across the wavefront).
 // Dense: one wavefront per row of [A11 A12]; the row is read once for both
 // right-hand sides [a; b] and [conj(b); -conj(a)] (u_bot = conj(A11 conj(b) -
 // A12 conj(a)) because A11^T = conj(A11) and A12^H = -conj(A12)).
@@ -32,32 +33,48 @@ __device__ __forceinline__ void mac_conj_a(cx<C>& acc, C ar, C ai, C br, C bi) {
   acc.im = fma(-ai, br, acc.im);
 }
 
-// Load the 4 complex components of one site (storage S) into compute type C.
+// Site vectors: the 4 complex components of one site are contiguous (32 B
+// in FP32, 64 B in FP64) and move as 16-byte vector loads and stores.
 template <typename S, typename C>
 __device__ __forceinline__ void load_site(const cplx<S>* __restrict__ p, C re[4], C im[4]) {
+  if constexpr (sizeof(S) == 4) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+    const float4 u = q[0], v = q[1];
+    re[0] = (C)u.x; im[0] = (C)u.y; re[1] = (C)u.z; im[1] = (C)u.w;
+    re[2] = (C)v.x; im[2] = (C)v.y; re[3] = (C)v.z; im[3] = (C)v.w;
+  } else {
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    cplx<S> v = p[c];
-    re[c] = (C)v.x;
-    im[c] = (C)v.y;
+    for (int c = 0; c < 4; ++c) {
+      const cplx<S> v = p[c];
+      re[c] = (C)v.x;
+      im[c] = (C)v.y;
+    }
   }
 }
-// Four link entries M[r][0..3] (row) or M[0..3][r] (column) of a row-major 4x4.
-template <typename S, typename C, bool ROW>
-__device__ __forceinline__ void load_line(const cplx<S>* __restrict__ M, int r, C re[4], C im[4]) {
+template <typename S, typename C>
+__device__ __forceinline__ void store_site(cplx<S>* __restrict__ p, const cx<C> v[4]) {
+  if constexpr (sizeof(S) == 4) {
+    float4* q = reinterpret_cast<float4*>(p);
+    q[0] = make_float4((float)v[0].re, (float)v[0].im, (float)v[1].re, (float)v[1].im);
+    q[1] = make_float4((float)v[2].re, (float)v[2].im, (float)v[3].re, (float)v[3].im);
+  } else {
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    cplx<S> v = ROW ? M[4 * r + c] : M[4 * c + r];
-    re[c] = (C)v.x;
-    im[c] = (C)v.y;
+    for (int c = 0; c < 4; ++c) {
+      cplx<S> o;
+      o.x = (S)v[c].re;
+      o.y = (S)v[c].im;
+      p[c] = o;
+    }
   }
 }
 
-// Computes (A v)(s) for one site: top[4], bot[4] in compute type C.  One
-// direction and one hop are live at a time and the links are consumed one
-// row (forward hop) or column (backward hop) at a time, which keeps the
-// register footprint small enough for full occupancy without spills.
-template <typename S, typename C>
+// Computes (A v)(s) for one site: top[4], bot[4] in compute type C.  Links are site-fastest: entry e (row-major
+// index in the 4x4 link) of U_mu(s) is U[(mu * 16 + e) * V + s], so the 64
+// lanes of a wavefront read 64 consecutive elements per entry.  Without
+// BSITE, B holds the 4 direction matrices B_mu (16 entries each), read at
+// wavefront-uniform addresses (scalar loads); with BSITE it has the layout of
+// U.  One direction and one hop are live at a time.
+template <typename S, typename C, bool BSITE>
 __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx<S>* __restrict__ xt,
                                              const cplx<S>* __restrict__ xb, int64_t s,
                                              cx<C> top[4], cx<C> bot[4]) {
@@ -88,25 +105,25 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx
   for (int mu = 0; mu < 4; ++mu) {
     const int64_t sf = (x[mu] == Ls[mu] - 1) ? s - (int64_t)(Ls[mu] - 1) * st[mu] : s + st[mu];
     const int64_t sb = (x[mu] == 0) ? s + (int64_t)(Ls[mu] - 1) * st[mu] : s - st[mu];
+    const cplx<S>* Um = a.U + (int64_t)mu * 16 * V;
+    const cplx<S>* Bm = BSITE ? a.B + (int64_t)mu * 16 * V : a.B + mu * 16;
     // ---- forward hop: U(x) a(x+mu), conj(U(x)) b(x+mu), B(x) b(x+mu), conj(B(x)) a(x+mu)
     {
       C ar[4], ai[4], br[4], bi[4];
       load_site<S, C>(xt + sf * 4, ar, ai);
       load_site<S, C>(xb + sf * 4, br, bi);
-      const cplx<S>* Up = a.U + ((int64_t)mu * V + s) * 16;
-      const cplx<S>* Bp = a.b_per_site ? a.B + ((int64_t)mu * V + s) * 16 : a.B + mu * 16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        C ur[4], ui[4], wr[4], wi[4];
-        load_line<S, C, true>(Up, r, ur, ui);
-        load_line<S, C, true>(Bp, r, wr, wi);
         cx<C> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          mac(t, ur[c], ui[c], ar[c], ai[c]);          // U a_f
-          mac_conj_a(q, ur[c], ui[c], br[c], bi[c]);   // conj(U) b_f
-          mac(tb, wr[c], wi[c], br[c], bi[c]);         // B b_f
-          mac_conj_a(qb, wr[c], wi[c], ar[c], ai[c]);  // conj(B) a_f
+          const cplx<S> u = Um[(int64_t)(4 * r + c) * V + s];
+          const cplx<S> w = BSITE ? Bm[(int64_t)(4 * r + c) * V + s] : Bm[4 * r + c];
+          const C ur = (C)u.x, ui = (C)u.y, wr = (C)w.x, wi = (C)w.y;
+          mac(t, ur, ui, ar[c], ai[c]);          // U a_f
+          mac_conj_a(q, ur, ui, br[c], bi[c]);   // conj(U) b_f
+          mac(tb, wr, wi, br[c], bi[c]);         // B b_f
+          mac_conj_a(qb, wr, wi, ar[c], ai[c]);  // conj(B) a_f
         }
         top[r].re += sc * tb.re - t.re; top[r].im += sc * tb.im - t.im;
         bot[r].re -= q.re + sc * qb.re; bot[r].im -= q.im + sc * qb.im;
@@ -117,20 +134,18 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx
       C ar[4], ai[4], br[4], bi[4];
       load_site<S, C>(xt + sb * 4, ar, ai);
       load_site<S, C>(xb + sb * 4, br, bi);
-      const cplx<S>* Up = a.U + ((int64_t)mu * V + sb) * 16;
-      const cplx<S>* Bp = a.b_per_site ? a.B + ((int64_t)mu * V + sb) * 16 : a.B + mu * 16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        C ur[4], ui[4], wr[4], wi[4];
-        load_line<S, C, false>(Up, r, ur, ui);
-        load_line<S, C, false>(Bp, r, wr, wi);
         cx<C> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          mac_conj_a(t, ur[c], ui[c], ar[c], ai[c]);   // U^H a_b
-          mac(q, ur[c], ui[c], br[c], bi[c]);          // U^T b_b
-          mac(tb, wr[c], wi[c], br[c], bi[c]);         // B^T b_b
-          mac_conj_a(qb, wr[c], wi[c], ar[c], ai[c]);  // B^H a_b
+          const cplx<S> u = Um[(int64_t)(4 * c + r) * V + sb];
+          const cplx<S> w = BSITE ? Bm[(int64_t)(4 * c + r) * V + sb] : Bm[4 * c + r];
+          const C ur = (C)u.x, ui = (C)u.y, wr = (C)w.x, wi = (C)w.y;
+          mac_conj_a(t, ur, ui, ar[c], ai[c]);   // U^H a_b
+          mac(q, ur, ui, br[c], bi[c]);          // U^T b_b
+          mac(tb, wr, wi, br[c], bi[c]);         // B^T b_b
+          mac_conj_a(qb, wr, wi, ar[c], ai[c]);  // B^H a_b
         }
         top[r].re -= t.re + sc * tb.re; top[r].im -= t.im + sc * tb.im;
         bot[r].re += sc * qb.re - q.re; bot[r].im += sc * qb.im - q.im;
@@ -146,7 +161,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh);
 
 // y = A x per site; with apart != nullptr (single column) the block also
 // writes its FP64 partial of x^H y (the alpha_j of Alg. 2) to apart[2*blk].
-template <typename S>
+template <typename S, bool BSITE>
 __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply(StencilArgs<S> a,
                                                                    const cplx<S>* __restrict__ x,
                                                                    cplx<S>* __restrict__ y,
@@ -160,18 +175,19 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply(StencilArgs<S
   double are = 0.0, aim = 0.0;
   if (s < a.V) {
     cx<S> top[4], bot[4];
-    stencil_site<S, S>(a, xc, xc + h, s, top, bot);
+    stencil_site<S, S, BSITE>(a, xc, xc + h, s, top, bot);
+    store_site<S, S>(yc + s * 4, top);
+    store_site<S, S>(yc + h + s * 4, bot);
+    if (apart) {   // the site's own components again (cache hit)
+      S a0r[4], a0i[4], b0r[4], b0i[4];
+      load_site<S, S>(xc + s * 4, a0r, a0i);
+      load_site<S, S>(xc + h + s * 4, b0r, b0i);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      cplx<S> t, b;
-      t.x = top[r].re; t.y = top[r].im;
-      b.x = bot[r].re; b.y = bot[r].im;
-      yc[s * 4 + r] = t;
-      yc[h + s * 4 + r] = b;
-      if (apart) {
-        const cplx<S> xt = xc[s * 4 + r], xb = xc[h + s * 4 + r];
-        are += (double)xt.x * t.x + (double)xt.y * t.y + (double)xb.x * b.x + (double)xb.y * b.y;
-        aim += (double)xt.x * t.y - (double)xt.y * t.x + (double)xb.x * b.y - (double)xb.y * b.x;
+      for (int r = 0; r < 4; ++r) {
+        are += (double)a0r[r] * top[r].re + (double)a0i[r] * top[r].im +
+               (double)b0r[r] * bot[r].re + (double)b0i[r] * bot[r].im;
+        aim += (double)a0r[r] * top[r].im - (double)a0i[r] * top[r].re +
+               (double)b0r[r] * bot[r].im - (double)b0i[r] * bot[r].re;
       }
     }
   }
@@ -202,7 +218,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {   // result 
 }
 
 // ||A x_c - lam_c x_c||^2 per block in FP64 (x stored as S).
-template <typename S>
+template <typename S, bool BSITE>
 __global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S> a,
                                                                    const cplx<S>* __restrict__ X,
                                                                    int64_t ldx,
@@ -217,18 +233,31 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S
   if (s < a.V) {
     const cplx<S>* xc = X + (int64_t)cols[c] * ldx;
     cx<double> top[4], bot[4];
-    stencil_site<S, double>(a, xc, xc + h, s, top, bot);
+    stencil_site<S, double, BSITE>(a, xc, xc + h, s, top, bot);
+    double a0r[4], a0i[4], b0r[4], b0i[4];
+    load_site<S, double>(xc + s * 4, a0r, a0i);
+    load_site<S, double>(xc + h + s * 4, b0r, b0i);
     const double l = lam[c];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const cplx<S> xt = xc[s * 4 + r], xb = xc[h + s * 4 + r];
-      const double tr = top[r].re - l * (double)xt.x, ti = top[r].im - l * (double)xt.y;
-      const double br = bot[r].re - l * (double)xb.x, bi = bot[r].im - l * (double)xb.y;
+      const double tr = top[r].re - l * a0r[r], ti = top[r].im - l * a0i[r];
+      const double br = bot[r].re - l * b0r[r], bi = bot[r].im - l * b0i[r];
       acc += tr * tr + ti * ti + br * br + bi * bi;
     }
   }
   const double tot = block_sum<kStencilThreads>(acc, sh);
   if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * gridDim.y + c] = tot;
+}
+
+// Links from the caller's [mu][V][16] (site-major) layout into the
+// operator's [mu][16][V] (site-fastest) copy.
+template <typename S>
+__global__ void k_links_site_fastest(const cplx<S>* __restrict__ src, cplx<S>* __restrict__ dst,
+                                     int64_t V) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // destination index
+  if (i >= 64 * V) return;
+  const int64_t s = i % V, me = i / V;                                 // me = mu * 16 + e
+  dst[i] = src[((me / 16) * V + s) * 16 + me % 16];
 }
 
 // ------------------------------------------------------------------ dense
@@ -339,7 +368,10 @@ hipError_t launch_stencil_apply(const StencilArgs<S>& a, const cplx<S>* x, cplx<
                                 int nrhs, double* apart, hipStream_t st) {
   if (apart && nrhs != 1) return hipErrorInvalidValue;
   dim3 grid((unsigned)((a.V + kStencilThreads - 1) / kStencilThreads), (unsigned)nrhs);
-  hipLaunchKernelGGL(k_stencil_apply<S>, grid, dim3(kStencilThreads), 0, st, a, x, y, ld, apart);
+  if (a.b_per_site)
+    hipLaunchKernelGGL((k_stencil_apply<S, true>), grid, dim3(kStencilThreads), 0, st, a, x, y, ld, apart);
+  else
+    hipLaunchKernelGGL((k_stencil_apply<S, false>), grid, dim3(kStencilThreads), 0, st, a, x, y, ld, apart);
   return hipGetLastError();
 }
 
@@ -349,8 +381,20 @@ hipError_t launch_stencil_resid(const StencilArgs<S>& a, const cplx<S>* X, int64
                                 int* nblk, hipStream_t st) {
   const int nb = stencil_resid_blocks(a.V);
   *nblk = nb;
-  hipLaunchKernelGGL(k_stencil_resid<S>, dim3((unsigned)nb, (unsigned)ncols), dim3(kStencilThreads),
-                     0, st, a, X, ldx, cols, lam, partial);
+  if (a.b_per_site)
+    hipLaunchKernelGGL((k_stencil_resid<S, true>), dim3((unsigned)nb, (unsigned)ncols),
+                       dim3(kStencilThreads), 0, st, a, X, ldx, cols, lam, partial);
+  else
+    hipLaunchKernelGGL((k_stencil_resid<S, false>), dim3((unsigned)nb, (unsigned)ncols),
+                       dim3(kStencilThreads), 0, st, a, X, ldx, cols, lam, partial);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_links_site_fastest(const cplx<S>* src, cplx<S>* dst, int64_t V, hipStream_t st) {
+  const int64_t total = 64 * V;
+  hipLaunchKernelGGL(k_links_site_fastest<S>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     src, dst, V);
   return hipGetLastError();
 }
 
@@ -380,6 +424,7 @@ hipError_t launch_dense_resid(const DenseArgs<S>& a, const cplx<S>* X, int64_t l
   template hipError_t launch_stencil_resid<S>(const StencilArgs<S>&, const cplx<S>*, int64_t,    \
                                               const int*, const double*, int, double*, int*,     \
                                               hipStream_t);                                      \
+  template hipError_t launch_links_site_fastest<S>(const cplx<S>*, cplx<S>*, int64_t, hipStream_t); \
   template hipError_t launch_dense_apply<S>(const DenseArgs<S>&, const cplx<S>*, cplx<S>*,       \
                                             int64_t, int, double*, hipStream_t);                 \
   template hipError_t launch_dense_resid<S>(const DenseArgs<S>&, const cplx<S>*, int64_t,        \
