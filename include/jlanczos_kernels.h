@@ -37,6 +37,22 @@ jl_status jl_ritz_workspace_bytes(int32_t m, size_t* bytes);
 jl_status jl_ritz(jl_ctx ctx, int32_t m, const double* T, int32_t which, double* lam, double* Z,
                   void* ws, size_t ws_bytes);
 
+/* The same Rayleigh-Ritz step for the structure the thick restart of Alg. 1
+ * gives T_m (the shrink to k + 1 and eq. dynamicwin): diagonal theta_0..k-1
+ * (kept Ritz values), their couplings s_i = t_{k,i} in row and column k, and
+ * from index k on the tridiagonal t_jj / t_{j+1,j} of the cycle's Lanczos
+ * steps (k = 0: a plain tridiagonal matrix).  `packed` (host, FP64) holds
+ * theta[k], s[k], alpha[m - k] (t_kk .. t_{m-1,m-1}), beta[m - k - 1]
+ * (t_{k+1,k} .. t_{m-1,m-2}).  Solved by divide and conquer on the device
+ * (tears at the tridiagonal couplings and at t_{k+1,k}; secular equations
+ * with deflation; Gu-Eisenstat weights).  lam (device, m) and Z (device,
+ * m x m column-major) as for jl_ritz.  Returns after the work is queued on
+ * the ctx stream; `packed` is copied before the call returns.
+ * Errors: JL_EINVAL (m < 1, m > 1024, k < 0, k >= m, NULL), JL_ENOMEM. */
+jl_status jl_ritz_restart_workspace_bytes(int32_t m, size_t* bytes);
+jl_status jl_ritz_restart(jl_ctx ctx, int32_t m, int32_t k, const double* packed, int32_t which,
+                          double* lam, double* Z, void* ws, size_t ws_bytes);
+
 /* Thick-restart basis update of Alg. 1 (V_m := V_m Z_m, first k columns):
  * Y = V Z with V (device, n x m complex, leading dimension ldv, dtype), Z
  * (device, m x k real FP64 column-major, leading dimension ldz) and Y

@@ -140,6 +140,15 @@ hipError_t launch_eig_offnorm(int m, EigWork w, int cur, hipStream_t st);
 // Small problems: all sweeps in one workgroup; lam[m], Z (m x m, ldz).
 hipError_t launch_eig_small(const double* T, int ldt, int m, double* lam, double* Z, int ldz,
                             int max_sweeps, hipStream_t st);
+// Divide and conquer for the restart structure of T_m (m <= dc_max_m()):
+// hs / ds hold theta[k], s[k], alpha[m - k], beta[m - k - 1] on the host /
+// device (for k > 0 alpha[0] = t_kk and beta[0] = t_{k+1,k}; for k = 0 the
+// whole tridiagonal).  *lam (m, unsorted) and *Z (m x m, ld *ldz) point into
+// `work` (dc_work_doubles(m) doubles).
+int dc_max_m();
+size_t dc_work_doubles(int m);
+hipError_t ritz_dc(int m, int k, const double* hs, const double* ds, double* work, const double** lam,
+                   const double** Z, int* ldz, hipStream_t st);
 // Sort: perm[r] = index of the r-th desired Ritz value (ascending unless
 // descending), with lam_i = lam[i * lstride]; then lam_s[r], Zs[:, r] (FP64,
 // m rows), Zc[:, r] (storage type, r < kcols), zlast[r] = Zs[m-1, r].

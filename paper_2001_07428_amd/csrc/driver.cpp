@@ -79,8 +79,34 @@ jl_status set_err(jl_ctx ctx, jl_status code, const char* fmt, ...) {
 }
 
 size_t ritz_scratch_doubles(int m) {
-  return eig_work_doubles(m) + (size_t)m + (size_t)m * m + (size_t)m;   // eig, lam, Z, perm
+  const size_t jac = eig_work_doubles(m) + (size_t)m + (size_t)m * m + (size_t)m;   // eig, lam, Z, perm
+  const size_t dc = m <= dc_max_m() ? 3 * (size_t)m + dc_work_doubles(m) : 0;      // struct, perm, D&C
+  return std::max(jac, dc);
 }
+
+template <typename S>
+hipError_t ritz_arrow_device(int m, int k, const double* hstruct, int descending, int kcols,
+                             double* scratch, double* lam_s, double* Zs, S* Zc, double* zlast,
+                             hipStream_t st) {
+  if (m > dc_max_m() || k < 0 || k >= m) return hipErrorInvalidValue;
+  double* ds = scratch;                                    // 2m packed structure
+  int* perm = reinterpret_cast<int*>(scratch + 2 * (size_t)m);
+  double* work = scratch + 3 * (size_t)m;
+  const size_t nstruct = 2 * (size_t)k + (size_t)(m - k) + (size_t)(m - k - 1);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(ds, hstruct, sizeof(double) * nstruct, hipMemcpyHostToDevice, st)) != hipSuccess)
+    return e;
+  const double* lam = nullptr;
+  const double* Z = nullptr;
+  int ldz = 0;
+  if ((e = ritz_dc(m, k, hstruct, ds, work, &lam, &Z, &ldz, st)) != hipSuccess) return e;
+  return launch_ritz_sort<S>(m, lam, 1, Z, ldz, descending, kcols, perm, lam_s, Zs, Zc, zlast, st);
+}
+
+template hipError_t ritz_arrow_device<float>(int, int, const double*, int, int, double*, double*,
+                                             double*, float*, double*, hipStream_t);
+template hipError_t ritz_arrow_device<double>(int, int, const double*, int, int, double*, double*,
+                                              double*, double*, double*, hipStream_t);
 
 template <typename S>
 hipError_t ritz_device(int m, const double* Tdev, double fro2, int descending, int kcols,
@@ -497,19 +523,32 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       break;
     }
     // ================= Rayleigh-Ritz: T_m = Z Lambda Z^T, sort (Alg. 1)
-    for (int jj = 0; jj < meff; ++jj)
-      for (int ii = 0; ii < meff; ++ii) {
-        const double v = ii >= jj ? Tat(ii, jj) : Tat(jj, ii);
-        Tm[(size_t)ii + (size_t)jj * meff] = v;
-      }
-    double fro2 = 0.0;
-    for (int i = 0; i < meff * meff; ++i) fro2 += Tm[i] * Tm[i];
-    tm.start(Timer::RITZ);
-    JL_HIP(ctx, hipMemcpyAsync(Tdev, Tm.data(), sizeof(double) * (size_t)meff * meff,
-                               hipMemcpyHostToDevice, st));
     const int kcols = std::min(kmax, meff);
-    JL_HIP(ctx, ritz_device<S>(meff, Tdev, fro2, prm->which == JL_LARGEST, 0, ritz_scr, lam_s, Zs,
-                               nullptr, zlast, hs, st));
+    tm.start(Timer::RITZ);
+    if (meff <= dc_max_m()) {
+      // restart structure: kept Ritz values and couplings, then this cycle's
+      // tridiagonal (divide and conquer)
+      for (int i = 0; i < k; ++i) {
+        Tm[i] = Tat(i, i);
+        Tm[k + i] = Tat(k, i);
+      }
+      for (int j = k; j < meff; ++j) Tm[2 * k + (j - k)] = Tat(j, j);
+      for (int j = k; j + 1 < meff; ++j) Tm[2 * k + (meff - k) + (j - k)] = Tat(j + 1, j);
+      JL_HIP(ctx, ritz_arrow_device<S>(meff, k, Tm.data(), prm->which == JL_LARGEST, 0, ritz_scr, lam_s,
+                                       Zs, nullptr, zlast, st));
+    } else {
+      for (int jj = 0; jj < meff; ++jj)
+        for (int ii = 0; ii < meff; ++ii) {
+          const double v = ii >= jj ? Tat(ii, jj) : Tat(jj, ii);
+          Tm[(size_t)ii + (size_t)jj * meff] = v;
+        }
+      double fro2 = 0.0;
+      for (int i = 0; i < meff * meff; ++i) fro2 += Tm[i] * Tm[i];
+      JL_HIP(ctx, hipMemcpyAsync(Tdev, Tm.data(), sizeof(double) * (size_t)meff * meff,
+                                 hipMemcpyHostToDevice, st));
+      JL_HIP(ctx, ritz_device<S>(meff, Tdev, fro2, prm->which == JL_LARGEST, 0, ritz_scr, lam_s, Zs,
+                                 nullptr, zlast, hs, st));
+    }
     JL_HIP(ctx, hipMemcpyAsync(h_lam, lam_s, sizeof(double) * meff, hipMemcpyDeviceToHost, st));
     JL_HIP(ctx, hipMemcpyAsync(h_zl, zlast, sizeof(double) * meff, hipMemcpyDeviceToHost, st));
     tm.stop();

@@ -63,4 +63,15 @@ hipError_t ritz_device(int m, const double* Tdev, double fro2, int descending, i
                        double* scratch, double* lam_s, double* Zs, S* Zc, double* zlast,
                        double* hs, hipStream_t st);
 
+// Rayleigh-Ritz for the restart structure of T_m (k kept Ritz values theta
+// with couplings s, then the tridiagonal alpha/beta of the cycle, packed as
+// theta[k], s[k], alpha[m - k], beta[m - k - 1] in host memory `hstruct`,
+// which must stay unchanged until the stream is synchronised) by divide and
+// conquer, then the sort of launch_ritz_sort.  m <= dc_max_m();
+// `scratch` holds ritz_scratch_doubles(m) doubles.
+template <typename S>
+hipError_t ritz_arrow_device(int m, int k, const double* hstruct, int descending, int kcols,
+                             double* scratch, double* lam_s, double* Zs, S* Zc, double* zlast,
+                             hipStream_t st);
+
 }  // namespace jl

@@ -93,6 +93,29 @@ jl_status jl_ritz(jl_ctx ctx, int32_t m, const double* T, int32_t which, double*
   return JL_OK;
 }
 
+jl_status jl_ritz_restart_workspace_bytes(int32_t m, size_t* bytes) {
+  if (!bytes || m < 1 || m > dc_max_m()) return set_err(nullptr, JL_EINVAL, "invalid ritz size");
+  *bytes = sizeof(double) * (ritz_scratch_doubles(m) + (size_t)m);   // + zlast
+  return JL_OK;
+}
+
+jl_status jl_ritz_restart(jl_ctx ctx, int32_t m, int32_t k, const double* packed, int32_t which,
+                          double* lam, double* Z, void* ws, size_t ws_bytes) {
+  if (!ctx) return set_err(nullptr, JL_EINVAL, "ctx is NULL");
+  if (m < 1 || m > dc_max_m() || k < 0 || k >= m || !packed || !lam || !Z ||
+      (which != JL_LOWEST && which != JL_LARGEST))
+    return set_err(ctx, JL_EINVAL, "invalid ritz_restart arguments");
+  const size_t need = sizeof(double) * (ritz_scratch_doubles(m) + (size_t)m);
+  if (!ws || ws_bytes < need) return set_err(ctx, JL_ENOMEM, "workspace too small (%zu < %zu)", ws_bytes, need);
+  DeviceGuard g(ctx->device);
+  double* scratch = static_cast<double*>(ws);
+  double* zlast = scratch + ritz_scratch_doubles(m);
+  JL_HIP(ctx, ritz_arrow_device<double>(m, k, packed, which == JL_LARGEST, 0, scratch, lam, Z, nullptr,
+                                        zlast, ctx->stream));
+  JL_HIP(ctx, hipStreamSynchronize(ctx->stream));   // `packed` may be reused by the caller
+  return JL_OK;
+}
+
 jl_status jl_basis_update(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t m, int32_t k,
                           const void* V, int64_t ldv, const void* Z, int64_t ldz, void* Y,
                           int64_t ldy) {

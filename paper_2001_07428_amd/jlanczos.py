@@ -33,6 +33,7 @@ EXPORTS = (
     "jl_op_create_dense", "jl_op_create_stencil", "jl_op_destroy", "jl_op_dim",
     "jl_op_apply", "jl_workspace_bytes", "jl_solve", "jl_pair_vectors",
     "jl_reorth_pass_workspace_bytes", "jl_reorth_pass", "jl_ritz_workspace_bytes", "jl_ritz",
+    "jl_ritz_restart_workspace_bytes", "jl_ritz_restart",
     "jl_basis_update", "jl_batch_workspace_bytes", "jl_batch_create", "jl_batch_run",
     "jl_batch_destroy",
 )
@@ -102,6 +103,9 @@ def load_library(path: str = LIB_PATH):
         "jl_reorth_pass": (i32, [vp, i32, i64, i32, vp, i64, vp, vp, vp, ctypes.c_size_t]),
         "jl_ritz_workspace_bytes": (i32, [i32, ctypes.POINTER(ctypes.c_size_t)]),
         "jl_ritz": (i32, [vp, i32, vp, i32, vp, vp, vp, ctypes.c_size_t]),
+        "jl_ritz_restart_workspace_bytes": (i32, [i32, ctypes.POINTER(ctypes.c_size_t)]),
+        "jl_ritz_restart": (i32, [vp, i32, i32, ctypes.POINTER(ctypes.c_double), i32, vp, vp, vp,
+                                  ctypes.c_size_t]),
         "jl_basis_update": (i32, [vp, i32, i64, i32, i32, vp, i64, vp, i64, vp, i64]),
         "jl_batch_workspace_bytes": (i32, [i32, ctypes.POINTER(i64), i32, ctypes.POINTER(JlParams),
                                            i32, i32, ctypes.POINTER(ctypes.c_size_t)]),
@@ -370,6 +374,31 @@ def jl_ritz(ctx: Context, T, which="lowest"):
                        JL_LARGEST if which == "largest" else JL_LOWEST,
                        ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(Zc.data_ptr()),
                        ctypes.c_void_p(ws.data_ptr()), nb.value), ctx.handle)
+    return lam, Zc.t()
+
+
+def jl_ritz_restart(ctx: Context, theta, s, alpha, beta, which="lowest"):
+    """Rayleigh-Ritz for the restart structure of T_m: kept Ritz values theta
+    (k), couplings s (k), then the tridiagonal alpha (m - k) / beta (m - k - 1)
+    starting at index k.  Returns (lam (m,), Z (m, m) with eigenvectors as
+    columns), sorted like jl_ritz."""
+    torch = _torch()
+    lib = load_library()
+    theta, s = np.asarray(theta, float).ravel(), np.asarray(s, float).ravel()
+    alpha, beta = np.asarray(alpha, float).ravel(), np.asarray(beta, float).ravel()
+    k, m = len(theta), len(theta) + len(alpha)
+    if len(s) != k or len(beta) != max(len(alpha) - 1, 0):
+        raise ValueError("inconsistent restart structure")
+    packed = np.ascontiguousarray(np.concatenate([theta, s, alpha, beta]))
+    nb = ctypes.c_size_t()
+    _check(lib.jl_ritz_restart_workspace_bytes(m, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=ctx.device)
+    lam = torch.empty(m, dtype=torch.float64, device=ctx.device)
+    Zc = torch.empty((m, m), dtype=torch.float64, device=ctx.device)   # rows = eigenvectors
+    _check(lib.jl_ritz_restart(ctx.handle, m, k, packed.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               JL_LARGEST if which == "largest" else JL_LOWEST,
+                               ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(Zc.data_ptr()),
+                               ctypes.c_void_p(ws.data_ptr()), nb.value), ctx.handle)
     return lam, Zc.t()
 
 
