@@ -54,78 +54,92 @@ constexpr int kJacobiLdsMaxMp = 60;
 // Sweeps of parallel cyclic Jacobi on A (mp x mp, symmetric, column-major)
 // with eigenvector accumulation Z (mp x mp, column-major, on entry the
 // identity or any orthogonal start), both in LDS, by one workgroup of NT
-// threads.  rc/rs/rt hold mp/2 rotations, red NT/64 doubles.  Stops when the
-// off-diagonal sum of squares is <= 1e-30 ||A||_F^2 or after max_sweeps.
-// Must be called by every thread of the workgroup (it synchronises).
+// threads.  rc/rs/rt hold mp/2 rotations, pq (ints) the mp indices of the
+// round's pairs, red NT/64 doubles.  A pair is rotated only while
+// |a_pq| > max(2 eps sqrt(|a_pp a_qq|), eps ||A||_F): smaller entries are
+// left in place, a perturbation at the rounding level (the absolute floor
+// keeps rounding noise around eigenvalues near zero from rotating forever);
+// the sweeps stop after one without any rotation, or after max_sweeps.  Must be called by every thread of the
+// workgroup (it synchronises).
 template <int NT>
-__device__ void jacobi_lds(double* A, double* Z, int mp, double* rc, double* rs, double* rt,
+__device__ void jacobi_lds(double* A, double* Z, int mp, double* rc, double* rs, double* rt, int* pq,
                            double* red, int max_sweeps) {
   static_assert(NT % 64 == 0 && NT / 64 <= 16, "jacobi_lds reduces over at most 16 wavefronts");
   const int P = mp / 2, tid = threadIdx.x;
-  double nrm = 0.0;
-  for (int idx = tid; idx < mp * mp; idx += NT) nrm += A[idx] * A[idx];
+  constexpr double kSkip = 2.0 * 2.220446049250313e-16;
+  // flat index -> (row, column) by a float reciprocal: exact for the index
+  // ranges here (< 2^12), which keeps integer division out of the inner loops
+  const float invP = 1.0f / (float)P, invM = 1.0f / (float)mp;
+  double f2 = 0.0;
+  for (int idx = tid; idx < mp * mp; idx += NT) f2 += A[idx] * A[idx];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o);
-  if (tid % 64 == 0) red[tid / 64] = nrm;
+  for (int o = 32; o > 0; o >>= 1) f2 += __shfl_xor(f2, o);
+  if (tid % 64 == 0) red[tid / 64] = f2;
   __syncthreads();
   double fro2 = 0.0;
   for (int w = 0; w < NT / 64; ++w) fro2 += red[w];
   __syncthreads();
+  const double floor_abs = 2.220446049250313e-16 * sqrt(fro2);
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) red[0] = 0.0;   // set to 1 by any rotation of this sweep
+    __syncthreads();
     for (int r = 0; r < mp - 1; ++r) {
       for (int I = tid; I < P; I += NT) {
         int p, q;
         round_pair(mp, r, I, p, q);
-        const Rot ro = jacobi_rot(A[p + p * mp], A[q + q * mp], A[p + q * mp]);
+        pq[2 * I] = p;
+        pq[2 * I + 1] = q;
+        const double app = A[p + p * mp], aqq = A[q + q * mp], apq = A[p + q * mp];
+        Rot ro{1.0, 0.0, 0.0};
+        if (fabs(apq) > fmax(kSkip * sqrt(fabs(app * aqq)), floor_abs) && apq != 0.0) {
+          ro = jacobi_rot(app, aqq, apq);
+          if (ro.s != 0.0) red[0] = 1.0;   // an underflowed rotation changes nothing
+        }
         rc[I] = ro.c; rs[I] = ro.s; rt[I] = ro.t;
       }
       __syncthreads();
-      for (int idx = tid; idx < P * P + mp * P; idx += NT) {
-        if (idx < P * P) {
-          const int I = idx % P, J = idx / P;
-          if (I > J) continue;
-          int pi, qi, pj, qj;
-          round_pair(mp, r, I, pi, qi);
-          round_pair(mp, r, J, pj, qj);
-          const Rot ri{rc[I], rs[I], rt[I]};
-          if (I == J) {
-            const double apq = A[pi + qi * mp];
-            A[pi + pi * mp] -= ri.t * apq;
-            A[qi + qi * mp] += ri.t * apq;
-            A[pi + qi * mp] = 0.0;
-            A[qi + pi * mp] = 0.0;
-            continue;
-          }
-          const Rot rj{rc[J], rs[J], rt[J]};
-          double o[4];
-          rot_block(ri, rj, A[pi + pj * mp], A[pi + qj * mp], A[qi + pj * mp], A[qi + qj * mp], o);
-          A[pi + pj * mp] = o[0]; A[pj + pi * mp] = o[0];
-          A[pi + qj * mp] = o[1]; A[qj + pi * mp] = o[1];
-          A[qi + pj * mp] = o[2]; A[pj + qi * mp] = o[2];
-          A[qi + qj * mp] = o[3]; A[qj + qi * mp] = o[3];
-        } else {
-          const int zi = idx - P * P;
-          const int row = zi % mp, J = zi / mp;
-          int pj, qj;
-          round_pair(mp, r, J, pj, qj);
-          const double zp = Z[row + pj * mp], zq = Z[row + qj * mp];
-          Z[row + pj * mp] = rc[J] * zp - rs[J] * zq;
-          Z[row + qj * mp] = rs[J] * zp + rc[J] * zq;
+      for (int idx = tid; idx < P * P; idx += NT) {
+        const int J = (int)(((float)idx + 0.5f) * invP);
+        const int I = idx - J * P;
+        if (I > J) continue;
+        const int pi = pq[2 * I], qi = pq[2 * I + 1];
+        const double si = rs[I];
+        if (I == J) {
+          if (si == 0.0) continue;   // not rotated: the block stays as it is
+          const double apq = A[pi + qi * mp], t = rt[I];
+          A[pi + pi * mp] -= t * apq;
+          A[qi + qi * mp] += t * apq;
+          A[pi + qi * mp] = 0.0;
+          A[qi + pi * mp] = 0.0;
+          continue;
         }
+        const double sj = rs[J];
+        if (si == 0.0 && sj == 0.0) continue;
+        const int pj = pq[2 * J], qj = pq[2 * J + 1];
+        const Rot ri{rc[I], si, 0.0}, rj{rc[J], sj, 0.0};
+        double o[4];
+        rot_block(ri, rj, A[pi + pj * mp], A[pi + qj * mp], A[qi + pj * mp], A[qi + qj * mp], o);
+        A[pi + pj * mp] = o[0]; A[pj + pi * mp] = o[0];
+        A[pi + qj * mp] = o[1]; A[qj + pi * mp] = o[1];
+        A[qi + pj * mp] = o[2]; A[pj + qi * mp] = o[2];
+        A[qi + qj * mp] = o[3]; A[qj + qi * mp] = o[3];
+      }
+      for (int zi = tid; zi < mp * P; zi += NT) {
+        const int J = (int)(((float)zi + 0.5f) * invM);
+        const int row = zi - J * mp;
+        const double sj = rs[J];
+        if (sj == 0.0) continue;
+        const int pj = pq[2 * J], qj = pq[2 * J + 1];
+        const double cj = rc[J];
+        const double zp = Z[row + pj * mp], zq = Z[row + qj * mp];
+        Z[row + pj * mp] = cj * zp - sj * zq;
+        Z[row + qj * mp] = sj * zp + cj * zq;
       }
       __syncthreads();
     }
-    double off = 0.0;
-    for (int idx = tid; idx < mp * mp; idx += NT)
-      if (idx % mp != idx / mp) off += A[idx] * A[idx];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o);
-    if (tid % 64 == 0) red[tid / 64] = off;
+    const bool done = red[0] == 0.0;   // read by every thread after the last barrier
     __syncthreads();
-    double offt = 0.0;
-    for (int w = 0; w < NT / 64; ++w) offt += red[w];
-    __syncthreads();
-    if (offt <= 1e-30 * fro2) break;
+    if (done) break;
   }
 }
 

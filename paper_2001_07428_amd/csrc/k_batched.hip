@@ -58,6 +58,7 @@ template <typename S> struct Lds {
   double* resv;     // m
   double* misc;     // 16 scalars
   int* perm;        // mp
+  int* pq;          // mp (pair table of a Jacobi round)
   int* conv;        // m
   int* order;       // m
 };
@@ -69,7 +70,7 @@ __host__ __device__ inline size_t lds_bytes(int64_t hmax, int m) {
   b += 2 * 2 * (size_t)hmax * sizeof(cplx<S>);
   b += sizeof(double) * ((size_t)(m + 1) * m + 2 * (size_t)mp * mp + 4 * (m + 1) + 2 + 2 * mp +
                          3 * (mp / 2) + 16 + m + 16);
-  b += sizeof(int) * ((size_t)mp + 2 * m);
+  b += sizeof(int) * (2 * (size_t)mp + 2 * m);
   return b + 64;
 }
 
@@ -94,6 +95,7 @@ __device__ inline Lds<S> carve(char* base, int64_t hmax, int m) {
   L.misc = d; d += 16;
   int* ip = reinterpret_cast<int*>(d);
   L.perm = ip; ip += mp;
+  L.pq = ip; ip += mp;
   L.conv = ip; ip += m;
   L.order = ip;
   return L;
@@ -315,7 +317,7 @@ __device__ void solve_one(const BatchProblem& pb, int pid, const BatchParams& P,
       L.JZ[idx] = (i == jj) ? 1.0 : 0.0;
     }
     __syncthreads();
-    jacobi_lds<NT>(L.JA, L.JZ, mp, L.rc, L.rs, L.rt, L.red, 60);
+    jacobi_lds<NT>(L.JA, L.JZ, mp, L.rc, L.rs, L.rt, L.pq, L.red, 60);
     for (int i = tid; i < meff; i += NT) {
       const double li = L.JA[i + i * mp];
       int rank = 0;

@@ -98,6 +98,7 @@ __global__ __launch_bounds__(256) void k_eig_small(const double* __restrict__ T,
   __shared__ double Z[kSmallMp * kSmallMp];
   __shared__ double rc[kSmallMp / 2], rs[kSmallMp / 2], rt[kSmallMp / 2];
   __shared__ double red[4];
+  __shared__ int pq[kSmallMp];
   const int mp = m + (m & 1), tid = threadIdx.x;
   for (int idx = tid; idx < mp * mp; idx += 256) {
     const int i = idx % mp, j = idx / mp;
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void k_eig_small(const double* __restrict__ T,
     Z[idx] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi_lds<256>(A, Z, mp, rc, rs, rt, red, max_sweeps);
+  jacobi_lds<256>(A, Z, mp, rc, rs, rt, pq, red, max_sweeps);
   for (int i = tid; i < m; i += 256) lam[i] = A[i + i * mp];
   for (int idx = tid; idx < m * m; idx += 256) {
     const int i = idx % m, j = idx / m;

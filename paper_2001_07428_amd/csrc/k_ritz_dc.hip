@@ -30,9 +30,9 @@ namespace jl {
 namespace {
 
 constexpr double kEps = 2.220446049250313e-16;
-constexpr int kDcLeaf = 48;     // largest tail block solved directly (cyclic Jacobi in LDS)
+constexpr int kDcLeaf = 32;     // largest tail block solved directly (cyclic Jacobi in LDS)
 constexpr int kDcMaxM = 1024;   // LDS of one secular solve: about 100 bytes per pole
-constexpr int kLeafThreads = 256;
+constexpr int kLeafThreads = 1024;   // about one update item per thread and Jacobi round
 constexpr int kSecThreads = 512;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -76,17 +76,30 @@ __device__ double wg_max(double v, double* red) {
 // differences D_j - lam = (D_j - org) - tau keep their relative accuracy.
 // Each step takes, inside the current bracket, the root of the osculating
 // model A + B / (pole - lam) at the origin pole, else a Newton step, else a
-// bisection (geometric when the bracket spans orders of magnitude).
+// bisection (geometric when the bracket spans orders of magnitude).  One
+// wavefront finds one root: the lanes share the sums over the poles, and
+// every lane takes the same (uniform) decisions.
 struct Root { double org, tau; };
 
-__device__ Root secular_root(double c0, double c1, double w, const double* __restrict__ D,
-                             const double* __restrict__ z2, int n, int lo_pole, int hi_pole,
-                             double lo_bound, double hi_bound) {
+__device__ __forceinline__ void wave_sum2(double& a, double& b) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+}
+
+__device__ Root secular_root_wave(double c0, double c1, double w, const double* __restrict__ D,
+                                  const double* __restrict__ z2, int n, int lo_pole, int hi_pole,
+                                  double lo_bound, double hi_bound) {
+  const int lane = threadIdx.x % 64;
   const double a = lo_pole >= 0 ? D[lo_pole] : lo_bound;
   const double b = hi_pole >= 0 ? D[hi_pole] : hi_bound;
   const double mid = 0.5 * (a + b);
-  double fm = c0 + c1 * mid;
-  for (int j = 0; j < n; ++j) fm += w * z2[j] / (D[j] - mid);
+  double fm = 0.0, dummy = 0.0;
+  for (int j = lane; j < n; j += 64) fm += z2[j] / (D[j] - mid);
+  wave_sum2(fm, dummy);
+  fm = c0 + c1 * mid + w * fm;
   const bool inc = w > 0.0;
   const bool left = inc ? (fm >= 0.0) : (fm <= 0.0);   // root in (a, mid]
   const int o = left ? lo_pole : hi_pole;
@@ -96,13 +109,15 @@ __device__ Root secular_root(double c0, double c1, double w, const double* __res
   double tau = (o < 0) ? 0.5 * (lo + hi) : (left ? 0.5 * hi : 0.5 * lo);
   const double cc0 = c0 + c1 * org;
   for (int it = 0; it < 200; ++it) {
-    double f = cc0 + c1 * tau, fp = c1;
-    for (int j = 0; j < n; ++j) {
+    double sf = 0.0, sp = 0.0;
+    for (int j = lane; j < n; j += 64) {
       const double r = 1.0 / ((D[j] - org) - tau);
       const double t = z2[j] * r;
-      f += w * t;
-      fp += w * t * r;
+      sf += t;
+      sp += t * r;
     }
+    wave_sum2(sf, sp);
+    const double f = cc0 + c1 * tau + w * sf, fp = c1 + w * sp;
     if (f == 0.0) break;
     if (inc ? (f < 0.0) : (f > 0.0)) lo = tau; else hi = tau;
     if (hi - lo <= 4.0 * kEps * fmax(fabs(lo), fabs(hi))) break;
@@ -131,8 +146,8 @@ __device__ Root secular_root(double c0, double c1, double w, const double* __res
   return Root{org, tau};
 }
 
-// LDS carve-up shared by the arrowhead and the rank-one kernels, for at most
-// `cap` poles.
+// LDS carve-up shared by the prepare and finish kernels, for at most `cap`
+// poles.
 struct SecLds {
   double *d, *z, *Dk, *z2, *org, *tau, *zh, *cn, *rc, *rs, *red;
   int *perm, *defl, *K, *ri, *rj, *misc;
@@ -164,9 +179,40 @@ size_t sec_lds_bytes(int cap) {
   return sizeof(double) * (10 * (size_t)cap + 3 + 16) + sizeof(int) * (5 * (size_t)cap + 4);
 }
 
-// Sorts the N poles L.d (with weights L.z) ascending into L.Dk / L.z2 order
-// positions: after the call L.d and L.z hold the sorted values and
-// L.perm[r] the input index of sorted position r (ties keep input order).
+// The state a secular solve keeps in device memory between its prepare,
+// roots and finish kernels (one block per problem, `cap` poles):
+// hdr = [n, nrot, sgn, w, c0, c1, lo_bound, hi_bound], then d, Dk, z2, zh,
+// org, tau, rc, rs (doubles) and perm, defl, K, ri, rj (ints).
+struct SecState {
+  double *hdr, *d, *Dk, *z2, *zh, *org, *tau, *rc, *rs;
+  int *perm, *defl, *K, *ri, *rj;
+};
+__host__ __device__ inline size_t sec_state_doubles(int cap) {
+  return 16 + 8 * (size_t)cap + 2 + (5 * (size_t)cap + 1) / 2 + 2;
+}
+__device__ SecState state_view(double* g, int cap) {
+  SecState S;
+  S.hdr = g; g += 16;
+  S.d = g; g += cap;
+  S.Dk = g; g += cap;
+  S.z2 = g; g += cap;
+  S.zh = g; g += cap;
+  S.org = g; g += cap + 1;
+  S.tau = g; g += cap + 1;
+  S.rc = g; g += cap;
+  S.rs = g; g += cap;
+  int* q = reinterpret_cast<int*>(g);
+  S.perm = q; q += cap;
+  S.defl = q; q += cap;
+  S.K = q; q += cap;
+  S.ri = q; q += cap;
+  S.rj = q;
+  return S;
+}
+
+// Sorts the N poles L.d (with weights L.z) ascending: afterwards L.d and L.z
+// hold the sorted values and L.perm[r] the input index of sorted position r
+// (ties keep input order).
 template <int NT>
 __device__ void sort_poles(const SecLds& L, int N) {
   for (int i = threadIdx.x; i < N; i += NT) {
@@ -197,13 +243,12 @@ __device__ void sort_poles(const SecLds& L, int N) {
 // |(d_j - d_i) c s| <= tol, the first deflates.  Rotations are recorded in
 // order (L.ri, L.rj, L.rc, L.rs); the live poles (still ascending) go to
 // L.K / L.Dk / L.z2 (squared weights) and keep their signed weight in L.zh.
+// With all_deflate every pole deflates (no coupling).
 template <int NT>
-__device__ void deflate(const SecLds& L, int N, double wscale, double tol) {
+__device__ void deflate(const SecLds& L, int N, double wscale, double tol, bool all_deflate) {
   if (threadIdx.x == 0) {
     int nrot = 0, prev = -1;
-    for (int j = 0; j < N; ++j) {
-      L.defl[j] = fabs(wscale * L.z[j]) <= tol ? 1 : 0;
-    }
+    for (int j = 0; j < N; ++j) L.defl[j] = (all_deflate || fabs(wscale * L.z[j]) <= tol) ? 1 : 0;
     for (int j = 0; j < N; ++j) {
       if (L.defl[j]) continue;
       if (prev >= 0) {
@@ -234,6 +279,59 @@ __device__ void deflate(const SecLds& L, int N, double wscale, double tol) {
     }
     L.misc[0] = n;
     L.misc[1] = nrot;
+  }
+  __syncthreads();
+}
+
+// Saves the prepared problem (after sort_poles and deflate) to the state.
+template <int NT>
+__device__ void save_state(const SecLds& L, const SecState& S, int N, double sgn, double w, double c0,
+                           double c1, double lo_b, double hi_b) {
+  const int n = L.misc[0], nrot = L.misc[1];
+  if (threadIdx.x == 0) {
+    S.hdr[0] = n; S.hdr[1] = nrot; S.hdr[2] = sgn; S.hdr[3] = w;
+    S.hdr[4] = c0; S.hdr[5] = c1; S.hdr[6] = lo_b; S.hdr[7] = hi_b;
+  }
+  for (int i = threadIdx.x; i < N; i += NT) {
+    S.d[i] = L.d[i];
+    S.perm[i] = L.perm[i];
+    S.defl[i] = L.defl[i];
+  }
+  for (int i = threadIdx.x; i < n; i += NT) {
+    S.Dk[i] = L.Dk[i];
+    S.z2[i] = L.z2[i];
+    S.zh[i] = L.zh[i];
+    S.K[i] = L.K[i];
+  }
+  for (int i = threadIdx.x; i < nrot; i += NT) {
+    S.ri[i] = L.ri[i]; S.rj[i] = L.rj[i]; S.rc[i] = L.rc[i]; S.rs[i] = L.rs[i];
+  }
+}
+
+// Loads a solved problem (state plus roots) back into LDS for the finish.
+template <int NT>
+__device__ void load_state(const SecLds& L, const SecState& S, int N, int nroots) {
+  const int n = (int)S.hdr[0], nrot = (int)S.hdr[1];
+  if (threadIdx.x == 0) {
+    L.misc[0] = n;
+    L.misc[1] = nrot;
+  }
+  for (int i = threadIdx.x; i < N; i += NT) {
+    L.d[i] = S.d[i];
+    L.perm[i] = S.perm[i];
+    L.defl[i] = S.defl[i];
+  }
+  for (int i = threadIdx.x; i < n; i += NT) {
+    L.Dk[i] = S.Dk[i];
+    L.zh[i] = S.zh[i];
+    L.K[i] = S.K[i];
+  }
+  for (int i = threadIdx.x; i < nroots; i += NT) {
+    L.org[i] = S.org[i];
+    L.tau[i] = S.tau[i];
+  }
+  for (int i = threadIdx.x; i < nrot; i += NT) {
+    L.ri[i] = S.ri[i]; L.rj[i] = S.rj[i]; L.rc[i] = S.rc[i]; L.rs[i] = S.rs[i];
   }
   __syncthreads();
 }
@@ -274,6 +372,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_dc_leaves(LeafJobs jobs, const
   __shared__ double Z[kJacobiLdsMaxMp * kJacobiLdsMaxMp];
   __shared__ double rc[kJacobiLdsMaxMp / 2], rs[kJacobiLdsMaxMp / 2], rt[kJacobiLdsMaxMp / 2];
   __shared__ double red[kLeafThreads / 64];
+  __shared__ int pq[kJacobiLdsMaxMp];
   const int lo = jobs.lo[blockIdx.x], n = jobs.n[blockIdx.x];
   const int mp = n + (n & 1), tid = threadIdx.x;
   for (int idx = tid; idx < mp * mp; idx += kLeafThreads) {
@@ -295,7 +394,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_dc_leaves(LeafJobs jobs, const
     Z[idx] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi_lds<kLeafThreads>(A, Z, mp, rc, rs, rt, red, 60);
+  jacobi_lds<kLeafThreads>(A, Z, mp, rc, rs, rt, pq, red, 60);
   for (int c = tid; c < n; c += kLeafThreads) D[lo + c] = A[c + c * mp];
   for (int idx = tid; idx < n * n; idx += kLeafThreads) {
     const int r = idx % n, c = idx / n;
@@ -303,18 +402,18 @@ __global__ __launch_bounds__(kLeafThreads) void k_dc_leaves(LeafJobs jobs, const
   }
 }
 
+
 // ------------------------------------------------------------ arrowhead
-// eig([[diag(theta), s], [s^T, a]]) for k poles: eigenvalues to DA (k + 1),
-// eigenvectors to QA ((k + 1) x (k + 1), column-major, ld k + 1); X is a
-// (k + 1)^2 scratch.  One workgroup.
-__global__ __launch_bounds__(kSecThreads) void k_dc_arrow(const double* __restrict__ theta,
-                                                          const double* __restrict__ s, double a, int k,
-                                                          double* __restrict__ DA, double* __restrict__ QA,
-                                                          double* __restrict__ X) {
+// eig([[diag(theta), s], [s^T, a]]) for k poles in three launches: prepare
+// (sort, deflate; state of capacity k + 1), the roots, finish -> DA (k + 1),
+// QA ((k + 1) x (k + 1), column-major, ld k + 1); X is a (k + 1)^2 scratch.
+__global__ __launch_bounds__(kSecThreads) void k_dc_arrow_prep(const double* __restrict__ theta,
+                                                               const double* __restrict__ s, double a,
+                                                               int k, double* __restrict__ state) {
   extern __shared__ __align__(16) char lds_raw[];
   const SecLds L = carve_sec(lds_raw, k + 1);
   constexpr int NT = kSecThreads;
-  const int tid = threadIdx.x, N = k + 1;
+  const int tid = threadIdx.x;
   for (int i = tid; i < k; i += NT) {
     L.d[i] = theta[i];
     L.z[i] = s[i];
@@ -329,25 +428,28 @@ __global__ __launch_bounds__(kSecThreads) void k_dc_arrow(const double* __restri
   mx = wg_max<NT>(mx, L.red);
   s2 = wg_sum<NT>(s2, L.red);
   const double tol = 8.0 * kEps * fmax(fmax(mx, fabs(a)), sqrt(s2));
-  deflate<NT>(L, k, 1.0, tol);
+  deflate<NT>(L, k, 1.0, tol, false);
   const int n = L.misc[0];
-  // bounds for the outer roots: the spectrum lies within ||s|| of the diagonal
+  // the spectrum lies within ||s|| of the diagonal: bounds for the outer roots
   double R2 = 0.0;
   for (int j = tid; j < n; j += NT) R2 += L.z2[j];
   const double R = sqrt(wg_sum<NT>(R2, L.red));
   const double lo_b = (n ? fmin(L.Dk[0], a) : a) - R - kEps * (fabs(a) + mx);
   const double hi_b = (n ? fmax(L.Dk[n - 1], a) : a) + R + kEps * (fabs(a) + mx);
-  for (int i = tid; i <= n; i += NT) {
-    if (n == 0) {
-      L.org[0] = a;
-      L.tau[0] = 0.0;
-      continue;
-    }
-    const Root r = secular_root(a, -1.0, -1.0, L.Dk, L.z2, n, i - 1, i < n ? i : -1, lo_b, hi_b);
-    L.org[i] = r.org;
-    L.tau[i] = r.tau;
-  }
-  __syncthreads();
+  save_state<NT>(L, state_view(state, k + 1), k, 1.0, -1.0, a, -1.0, lo_b, hi_b);
+}
+
+__global__ __launch_bounds__(kSecThreads) void k_dc_arrow_fin(int k, const double* __restrict__ state,
+                                                              double* __restrict__ DA,
+                                                              double* __restrict__ QA,
+                                                              double* __restrict__ X) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const SecLds L = carve_sec(lds_raw, k + 1);
+  constexpr int NT = kSecThreads;
+  const int tid = threadIdx.x, N = k + 1;
+  const SecState S = state_view(const_cast<double*>(state), k + 1);
+  const int n = (int)S.hdr[0];
+  load_state<NT>(L, S, k, n + 1);
   // Rebuilt weights: s_j^2 = (d_j - lam_j)(lam_{j+1} - d_j) prod_{i != j}
   // (lam_{i or i+1} - d_j) / (d_i - d_j), from the interlacing.
   for (int j = tid; j < n; j += NT) {
@@ -416,6 +518,7 @@ struct MergeJob {
   double* Dout;       // N eigenvalues
   double* W;          // N x N (ld N): parent vectors in the children's bases
   double* X;          // N x N scratch
+  double* state;      // sec_state_doubles(N)
   double rho;
   int ld1, ld2, zrow1, zrow2, n1, n2;
 };
@@ -425,8 +528,9 @@ struct MergeJobs {
 };
 
 // eig(diag(D1, D2) + rho z z^T), z = [row zrow1 of Q1; row zrow2 of Q2]: the
-// merge of a tear.  One workgroup per job.
-__global__ __launch_bounds__(kSecThreads) void k_dc_merge(MergeJobs jobs) {
+// merge of a tear, prepared (gather, scale, sort, deflate) by one workgroup
+// per job.
+__global__ __launch_bounds__(kSecThreads) void k_dc_merge_prep(MergeJobs jobs) {
   extern __shared__ __align__(16) char lds_raw[];
   constexpr int NT = kSecThreads;
   const MergeJob& J = jobs.j[blockIdx.x];
@@ -446,13 +550,9 @@ __global__ __launch_bounds__(kSecThreads) void k_dc_merge(MergeJobs jobs) {
   for (int i = tid; i < N; i += NT) zz += L.z[i] * L.z[i];
   zz = wg_sum<NT>(zz, L.red);
   double r = J.rho * zz;
-  if (r == 0.0 || zz == 0.0) {   // no coupling: the children's pairs as they are
-    for (int i = tid; i < N; i += NT) J.Dout[i] = L.d[i];
-    for (int idx = tid; idx < N * N; idx += NT) J.W[idx] = (idx % N == idx / N) ? 1.0 : 0.0;
-    return;
-  }
-  const double sgn = r < 0.0 ? -1.0 : 1.0;   // solve for -D + |r| z z^T when r < 0
-  const double inv = 1.0 / sqrt(zz);
+  const bool uncoupled = (r == 0.0 || zz == 0.0);   // the children's pairs as they are
+  const double sgn = r < 0.0 ? -1.0 : 1.0;         // solve for -D + |r| z z^T when r < 0
+  const double inv = uncoupled ? 1.0 : 1.0 / sqrt(zz);
   for (int i = tid; i < N; i += NT) {
     L.d[i] *= sgn;
     L.z[i] *= inv;
@@ -464,19 +564,27 @@ __global__ __launch_bounds__(kSecThreads) void k_dc_merge(MergeJobs jobs) {
   for (int i = tid; i < N; i += NT) mx = fmax(mx, fabs(L.d[i]));
   mx = wg_max<NT>(mx, L.red);
   const double tol = 8.0 * kEps * fmax(mx, r);
-  deflate<NT>(L, N, r, tol);
+  deflate<NT>(L, N, r, tol, uncoupled);
   const int n = L.misc[0];
   double zs = 0.0;
   for (int j = tid; j < n; j += NT) zs += L.z2[j];
   zs = wg_sum<NT>(zs, L.red);
-  for (int i = tid; i < n; i += NT) {
-    const Root rt = i < n - 1
-                        ? secular_root(1.0, 0.0, r, L.Dk, L.z2, n, i, i + 1, 0.0, 0.0)
-                        : secular_root(1.0, 0.0, r, L.Dk, L.z2, n, i, -1, 0.0, L.Dk[n - 1] + r * zs);
-    L.org[i] = rt.org;
-    L.tau[i] = rt.tau;
-  }
-  __syncthreads();
+  const double hi_b = n ? L.Dk[n - 1] + r * zs : 0.0;
+  save_state<NT>(L, state_view(J.state, N), N, sgn, r, 1.0, 0.0, 0.0, hi_b);
+}
+
+// Finish of a merge: weights from the roots, the vectors, the deflation
+// rotations and the sort undone -> W and Dout.
+__global__ __launch_bounds__(kSecThreads) void k_dc_merge_fin(MergeJobs jobs) {
+  extern __shared__ __align__(16) char lds_raw[];
+  constexpr int NT = kSecThreads;
+  const MergeJob& J = jobs.j[blockIdx.x];
+  const int N = J.n1 + J.n2, tid = threadIdx.x;
+  const SecLds L = carve_sec(lds_raw, N);
+  const SecState S = state_view(J.state, N);
+  const int n = (int)S.hdr[0];
+  const double sgn = S.hdr[2], r = S.hdr[3];
+  load_state<NT>(L, S, N, n);
   // Rebuilt weights: z_j^2 = (lam_j - d_j) / r prod_{i != j} (lam_i - d_j) / (d_i - d_j).
   for (int j = tid; j < n; j += NT) {
     const double dj = L.Dk[j];
@@ -517,6 +625,43 @@ __global__ __launch_bounds__(kSecThreads) void k_dc_merge(MergeJobs jobs) {
   for (int idx = tid; idx < N * N; idx += NT) {
     const int rr = idx % N, c = idx / N;
     J.W[L.perm[rr] + (int64_t)c * N] = X[idx];
+  }
+}
+
+// ------------------------------------------------------------ secular roots
+// One wavefront per root; jobs list the problems of a launch with the first
+// wavefront of each (root0) and the upper bound of its roots (cap).
+struct RootJob {
+  double* state;
+  int cap, root0, arrow;
+};
+constexpr int kMaxRootJobs = 48;
+struct RootJobs {
+  RootJob j[kMaxRootJobs];
+  int njobs;
+};
+
+__global__ __launch_bounds__(256) void k_dc_roots(RootJobs jobs) {
+  const int gw = blockIdx.x * 4 + threadIdx.x / 64;
+  int jb = 0;
+  while (jb + 1 < jobs.njobs && gw >= jobs.j[jb + 1].root0) ++jb;
+  const RootJob& J = jobs.j[jb];
+  const int i = gw - J.root0;
+  const SecState S = state_view(J.state, J.cap);
+  const int n = (int)S.hdr[0];
+  const double w = S.hdr[3], c0 = S.hdr[4], c1 = S.hdr[5], lo_b = S.hdr[6], hi_b = S.hdr[7];
+  Root r;
+  if (J.arrow) {                      // n + 1 roots interlacing the n poles
+    if (i > n) return;
+    if (n == 0) r = Root{c0, 0.0};
+    else r = secular_root_wave(c0, c1, w, S.Dk, S.z2, n, i - 1, i < n ? i : -1, lo_b, hi_b);
+  } else {                            // n roots, root i above pole i
+    if (i >= n) return;
+    r = secular_root_wave(c0, c1, w, S.Dk, S.z2, n, i, i + 1 < n ? i + 1 : -1, lo_b, hi_b);
+  }
+  if (threadIdx.x % 64 == 0) {
+    S.org[i] = r.org;
+    S.tau[i] = r.tau;
   }
 }
 
@@ -614,18 +759,44 @@ hipError_t launch_gemm_jobs(const std::vector<GemmJob>& all, hipStream_t st) {
   return hipSuccess;
 }
 
+hipError_t launch_roots(const std::vector<RootJob>& all, hipStream_t st) {
+  for (size_t b = 0; b < all.size(); b += kMaxRootJobs) {
+    RootJobs J{};
+    J.njobs = (int)std::min(all.size() - b, (size_t)kMaxRootJobs);
+    int waves = 0;
+    for (int i = 0; i < J.njobs; ++i) {
+      J.j[i] = all[b + i];
+      J.j[i].root0 = waves;
+      waves += all[b + i].cap;
+    }
+    if (waves == 0) continue;
+    hipLaunchKernelGGL(k_dc_roots, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, J);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Each merge: prepare (one workgroup per job), roots (one wavefront per
+// possible root over the whole device), finish (one workgroup per job).
 hipError_t launch_merges(const std::vector<MergeJob>& all, hipStream_t st) {
   for (size_t b = 0; b < all.size(); b += kMaxMergeJobs) {
     MergeJobs J{};
     const int nj = (int)std::min(all.size() - b, (size_t)kMaxMergeJobs);
     int cap = 0;
+    std::vector<RootJob> rj;
     for (int i = 0; i < nj; ++i) {
       J.j[i] = all[b + i];
-      cap = std::max(cap, J.j[i].n1 + J.j[i].n2);
+      const int N = J.j[i].n1 + J.j[i].n2;
+      cap = std::max(cap, N);
+      rj.push_back(RootJob{J.j[i].state, N, 0, 0});
     }
-    hipLaunchKernelGGL(k_dc_merge, dim3(nj), dim3(kSecThreads), sec_lds_bytes(cap), st, J);
+    hipLaunchKernelGGL(k_dc_merge_prep, dim3(nj), dim3(kSecThreads), sec_lds_bytes(cap), st, J);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if ((e = launch_roots(rj, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dc_merge_fin, dim3(nj), dim3(kSecThreads), sec_lds_bytes(cap), st, J);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -634,6 +805,10 @@ hipError_t launch_merges(const std::vector<MergeJob>& all, hipStream_t st) {
 
 int dc_max_m() { return kDcMaxM; }
 
+namespace {
+size_t state_doubles(int m) { return 64 * 32 + 12 * (size_t)m; }   // >= 28 per node + 10.5 per pole
+}  // namespace
+
 size_t dc_work_doubles(int m) {
   int t = m, H = 0;
   while (t > kDcLeaf) {
@@ -641,8 +816,9 @@ size_t dc_work_doubles(int m) {
     ++H;
   }
   const size_t mm = (size_t)m * m;
-  // Q and D per tail height, then W, X, QA, Zfin (m x m) and DA, Droot (m)
-  return (size_t)(H + 1) * (mm + (size_t)m) + 4 * mm + 2 * (size_t)m + 64;
+  // Q and D per tail height, then W, X, QA, Zfin (m x m), DA, Droot (m) and
+  // the secular states of one level (at most 64 nodes)
+  return (size_t)(H + 1) * (mm + (size_t)m) + 4 * mm + 2 * (size_t)m + state_doubles(m) + 64;
 }
 
 // T_m from its packed structure: theta[k], s[k], alpha[m - k], beta[m - k - 1]
@@ -681,6 +857,7 @@ hipError_t ritz_dc(int m, int k, const double* hs, const double* ds, double* wor
   double* Zf = p; p += mm;
   double* DA = p; p += m;
   double* Dr = p; p += m;
+  double* SB = p;   // secular states, reused level by level
   hipError_t e;
   if (t > 0) {   // leaves of the tail
     std::vector<int> leaves;
@@ -700,14 +877,18 @@ hipError_t ritz_dc(int m, int k, const double* hs, const double* ds, double* wor
   }
   if (k > 0) {   // the arrowhead, corner torn from the tail
     const double a = h_alpha[0] - (t > 0 ? h_beta[0] : 0.0);
-    hipLaunchKernelGGL(k_dc_arrow, dim3(1), dim3(kSecThreads), sec_lds_bytes(k + 1), st, d_theta, d_s, a,
-                       k, DA, QA, X);
+    hipLaunchKernelGGL(k_dc_arrow_prep, dim3(1), dim3(kSecThreads), sec_lds_bytes(k + 1), st, d_theta,
+                       d_s, a, k, SB);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_roots(std::vector<RootJob>{RootJob{SB, k + 1, 0, 1}}, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dc_arrow_fin, dim3(1), dim3(kSecThreads), sec_lds_bytes(k + 1), st, k, SB, DA, QA,
+                       X);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   for (int h = 1; h <= H; ++h) {   // tail merges, one launch (plus its GEMMs) per height
     std::vector<MergeJob> mj;
     std::vector<GemmJob> gj;
-    size_t woff = 0;
+    size_t woff = 0, soff = 0;
     for (const Node& nd : nodes) {
       if (nd.h != h) continue;
       const Node& a = nodes[nd.c1];
@@ -728,7 +909,9 @@ hipError_t ritz_dc(int m, int k, const double* hs, const double* ds, double* wor
       J.Dout = Dh[h] + nd.lo;
       J.W = W + woff;
       J.X = X + woff;
+      J.state = SB + soff;
       woff += (size_t)N * N;
+      soff += (sec_state_doubles(N) + 7) & ~size_t(7);
       mj.push_back(J);
       gj.push_back(GemmJob{J.Q1, J.W, Qh[h] + nd.lo + (int64_t)nd.lo * t, t, N, t, a.n, N, a.n, 0});
       gj.push_back(GemmJob{J.Q2, J.W + a.n, Qh[h] + b.lo + (int64_t)nd.lo * t, t, N, t, b.n, N, b.n, 0});
@@ -764,6 +947,7 @@ hipError_t ritz_dc(int m, int k, const double* hs, const double* ds, double* wor
   J.Dout = Dr;
   J.W = W;
   J.X = X;
+  J.state = SB;
   if ((e = launch_merges(std::vector<MergeJob>{J}, st)) != hipSuccess) return e;
   std::vector<GemmJob> gj{GemmJob{QA, W, Zf, k + 1, m, m, k + 1, m, k + 1, 0},
                           GemmJob{Qh[H], W + (k + 1), Zf + (k + 1), t, m, m, t, m, t, 0}};
