@@ -18,7 +18,7 @@ namespace jl {
 namespace {
 
 constexpr int kReorthThreads = 256;   // 4 wavefronts
-constexpr int kPairsPerLane = 8;      // pairs of u each lane holds per chunk
+constexpr int kPairsPerLane = 4;      // pairs of u each lane holds per chunk (more resident waves than 8)
 constexpr int kMaxCols = 2048;        // LDS column accumulators
 
 // E = complex elements per 16-byte load (2 for FP32 with an even half
