@@ -34,6 +34,17 @@ with 0-based indices: V has columns v_0..v_m, the projected matrix Tbar is
 * The J-restriction uses w_i = J v_i^* (Alg. 2 builds W alongside V).  With
   jsym=False the W-projections are dropped, giving the standard TRLAN that the
   paper compares against (Sec. 3).
+* Invert mode (Alg. 1 and 2, invert branches): the Lanczos steps take
+  u = A^-1 v_j from the caller's solve(); the Ritz values theta of T are those
+  of A^-1, and the wanted end of A's spectrum is the opposite end of theta's
+  (the lowest eigenvalues of a positive definite A are the largest theta), so
+  the sort is reversed.  ev = 1/theta, res_est = c |t_{m+1,i} ev_i| with
+  c = ||A v_{m+1}||, and the true residual uses A itself.  Every solve counts
+  as one matvec in n_mv (Sec. 3); the application of A for c is counted in
+  n_resid_mv with the true-residual checks.  After a breakdown there is no
+  v_{m+1} and c = 0 (the couplings are zero anyway).  With tol_relative the
+  scale is the running maximum of c and of the wanted |ev_i|, both lower
+  bounds on ||A||_2 as max |theta| is in normal mode.
 """
 from __future__ import annotations
 
@@ -54,13 +65,14 @@ def lanczos_jsym(apply, V, T, k, m, stats, jsym=True, breakdown_tol_fn=None, tra
                  min_passes=1):
     """Algorithm 2: extend the decomposition from dimension k to m.
 
+    apply(v) is A v in normal mode and A^-1 v in invert mode.
     V: (n, m+1) complex128 with v_0..v_k valid; T: (m+1, m) real with rows
     0..k valid.  Returns the dimension actually reached (m, or less on
     breakdown) and the breakdown flag.
     """
     gamma = math.sqrt(2.0)                       # reorthogonalisation threshold
     for j in range(k, m):
-        u = apply(V[:, j])                       # normal mode: A v_j
+        u = apply(V[:, j])                       # A v_j, or A^-1 v_j (invert mode)
         stats["n_mv"] += 1
         t = np.vdot(V[:, j], u)                  # t_jj = v_j^H v_{j+1}
         T[j, j] = t.real
@@ -103,10 +115,12 @@ def _sym_T(T, m):
 def trlan_jsym(apply, n, nev, mwin, m, tol, which="lowest", v1=None,
                max_cycles=100000, jsym=True, unit_roundoff=2.0 ** -53,
                breakdown_factor=64.0, trace_cap=0, record_history=False,
-               time_limit=None, on_cycle=None, min_passes=1, tol_relative=False):
+               time_limit=None, on_cycle=None, min_passes=1, tol_relative=False,
+               mode="normal", solve=None):
     """Algorithm 1: thick-restart Lanczos for a Hermitian J-symmetric A.
 
-    apply(v) -> A v.  Returns a dict with ev (nev, desired order), X (n, nev),
+    apply(v) -> A v; in mode "invert" also solve(v) -> A^-1 v, which drives
+    the Lanczos steps.  Returns a dict with ev (nev, desired order), X (n, nev),
     res (true residual norms), and counters n_mv (Lanczos matvecs only, as in
     Sec. 3), n_conv (outer iterations), gs_passes, n_resid_mv, status
     ("ok", "not_converged", "breakdown", "time_limit").
@@ -115,6 +129,12 @@ def trlan_jsym(apply, n, nev, mwin, m, tol, which="lowest", v1=None,
     """
     if n % 2 or nev < 1 or not (nev <= mwin < m) or (jsym and m > n // 2) or m > n:
         raise ValueError("invalid parameters")
+    if mode not in ("normal", "invert") or (mode == "invert" and solve is None):
+        raise ValueError("mode must be 'normal' or 'invert' (the latter with solve)")
+    invert = mode == "invert"
+    step = solve if invert else apply
+    # sort key on theta: the wanted end of A's spectrum, reversed under inversion
+    descending = (which == "lowest") == invert
     stats = dict(n_mv=0, gs_passes=0, n_resid_mv=0, n_conv=0)
     trace = dict(alpha=[], beta=[], cap=trace_cap) if trace_cap else None
     history = []
@@ -134,7 +154,7 @@ def trlan_jsym(apply, n, nev, mwin, m, tol, which="lowest", v1=None,
     scale = 0.0                                  # running max |theta| (tol_relative)
     for cycle in range(max_cycles):
         stats["n_conv"] += 1
-        meff, broke = lanczos_jsym(apply, V, T, k, m, stats, jsym=jsym,
+        meff, broke = lanczos_jsym(step, V, T, k, m, stats, jsym=jsym,
                                    breakdown_tol_fn=btol, trace=trace, min_passes=min_passes)
         if meff < nev:                           # invariant subspace too small
             status = "breakdown"
@@ -144,16 +164,25 @@ def trlan_jsym(apply, n, nev, mwin, m, tol, which="lowest", v1=None,
             break
         Tm = _sym_T(T, meff)
         lam, Z = np.linalg.eigh(Tm)              # T_m = Z Lambda Z^T
-        order = np.argsort(lam if which == "lowest" else -lam, kind="stable")
+        order = np.argsort(-lam if descending else lam, kind="stable")
         lam = lam[order]
         Z = Z[:, order]
         V[:, :meff] = V[:, :meff] @ Z            # V_m := V_m Z_m
         s = T[meff, meff - 1] * Z[meff - 1, :]   # t_{m+1,i} = t_{m+1,m} z_{m,i}
-        ev = lam[:nev].copy()
-        res_est = np.abs(s[:nev])
+        if invert:
+            ev = 1.0 / lam[:nev]                 # ev(i) = 1/lambda_i
+            c = 0.0
+            if not broke:
+                c = np.linalg.norm(apply(V[:, meff]))   # c = ||A v_{m+1}||
+                stats["n_resid_mv"] += 1
+            res_est = c * np.abs(s[:nev] * ev)
+            scale = max(scale, c, np.abs(ev).max())
+        else:
+            ev = lam[:nev].copy()
+            res_est = np.abs(s[:nev])
+            scale = max(scale, np.abs(lam).max())
         res = np.full(nev, np.inf)
         is_convd = np.zeros(nev, dtype=bool)
-        scale = max(scale, np.abs(lam).max())
         tol_c = tol * scale if tol_relative else tol
         for i in range(nev):
             if res_est[i] < tol_c:               # check true residuals
@@ -167,9 +196,9 @@ def trlan_jsym(apply, n, nev, mwin, m, tol, which="lowest", v1=None,
         lam = lam[perm]
         s = s[perm]
         V[:, :meff] = V[:, perm]
-        ev = lam[:nev].copy()
+        ev = ev[perm[:nev]]
         res = res[perm[:nev]]
-        res_est = np.abs(s[:nev])
+        res_est = res_est[perm[:nev]]
         icnv = int(is_convd.sum())
         s[:icnv] = 0.0                           # decouple converged subspace
         if record_history:
