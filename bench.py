@@ -8,7 +8,8 @@ workload is solved in the mixed form (FP32 complex operator and basis, FP64
 reductions and Ritz problem) and in plain FP64; `value` is the mixed time to
 the nev converged pairs, the FP64 time is reported beside it.
 
-    python bench.py [--steps K] [--warmup W] [--workload stencil16|stencil32|dense4096]
+    python bench.py [--steps K] [--warmup W]
+                    [--workload stencil16|stencil32|dense4096|batched512|casea|invert16]
 
 Prints one JSON line.  Only one GPU is used; --gpus N > 1 exits with a message.
 """
@@ -43,10 +44,23 @@ WORKLOADS = {
     # replayed from a hipGraph; tolerance relative to max|theta| in both forms
     "batched512": dict(kind="batched", seed=3, count=512, nev=8, m=32, mwin=16, tol=1e-5,
                        tol_relative=True, tol_fp64=1e-10),
+    # invert mode (A^-1 v_j by conjugate gradients) on the 16^4 J-stencil,
+    # which is positive definite; the paper's small-eigenvalue parameters
+    # for TRLAN-JSYM (nev, mwin, m) = (8, 16, 48)
+    "invert16": dict(kind="stencil", L=(16, 16, 16, 16), seed=4, nev=8, m=48, mwin=16,
+                     tol=1e-5, tol_relative=False, invert=True, cg_tol=1e-7),
+    # Table 1 (Case A, Sec. 4.1): ten known-spectrum matrices of size 2000,
+    # largest eigenvalues, tol 1e-13, FP64; the J-restricted method against
+    # the standard one over the published (nev, mwin, m) grid
+    "casea": dict(kind="casea", n=2000, seeds=list(range(8, 18)), tol=1e-13),
 }
 
 
 def describe(w):
+    if w["kind"] == "casea":
+        return (f"Case A: {len(w['seeds'])} known-spectrum Hermitian J-symmetric matrices, n={w['n']}, "
+                f"largest eigenvalues, tol={w['tol']:g}, FP64, seeds {w['seeds'][0]}..{w['seeds'][-1]}; "
+                "TRLAN-JSYM and standard TRLAN over the Table 1 grid")
     if w["kind"] == "batched":
         return (f"batched: {w['count']} dense Hermitian J-symmetric problems, even n uniform in "
                 f"64..1024, {w['nev']} lowest pairs each, m={w['m']}, mwin={w['mwin']}, "
@@ -55,16 +69,29 @@ def describe(w):
     if w["kind"] == "stencil":
         L = w["L"]
         n = 2 * int(np.prod(L)) * 4
+        inv = (f", invert mode (CG to {w['cg_tol']:g})" if w.get("invert") else "")
         return (f"4D J-stencil {'x'.join(map(str, L))} d=4 (n={n}), {w['nev']} lowest pairs, "
-                f"m={w['m']}, mwin={w['mwin']}, tol={w['tol']:g} abs, seed {w['seed']}")
+                f"m={w['m']}, mwin={w['mwin']}, tol={w['tol']:g} abs, seed {w['seed']}{inv}")
     n = 2 * w["h"]
     return (f"dense Hermitian J-symmetric n={n}, {w['nev']} lowest pairs, m={w['m']}, "
             f"mwin={w['mwin']}, tol={w['tol']:g} rel (mixed) / {w['tol_fp64']:g} abs (fp64), "
             f"seed {w['seed']}")
 
 
+def _known_spectrum_blocks(seed, n):
+    from threadpoolctl import threadpool_limits
+    from paper_2001_07428_amd import inputs
+    with threadpool_limits(1):   # one BLAS thread per worker process
+        return inputs.known_spectrum(seed, n)[:3]
+
+
 def make_host_inputs(w):
     from paper_2001_07428_amd import inputs
+    if w["kind"] == "casea":   # ~17 s per matrix of size 2000: one process each
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(len(w["seeds"]), os.cpu_count() or 1, 16)) as ex:
+            mats = list(ex.map(_known_spectrum_blocks, w["seeds"], [w["n"]] * len(w["seeds"])))
+        return dict(mats=mats)
     if w["kind"] == "batched":
         n, probs = inputs.batched_dense(w["seed"], count=w["count"])
         return dict(n=n, probs=probs)
@@ -92,12 +119,13 @@ def run_precision(J, ctx, w, host, mixed, steps, warmup, verbose):
     op = make_op(J, ctx, w, host, dtype)
     tol = w["tol"] if mixed or "tol_fp64" not in w else w["tol_fp64"]
     rel = w["tol_relative"] if mixed else False
-    nb = J.jl_workspace_bytes(op, w["nev"], w["m"], w["mwin"], tol)
+    inv = bool(w.get("invert", False))
+    nb = J.jl_workspace_bytes(op, w["nev"], w["m"], w["mwin"], tol, invert=inv)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
 
     def solve(timing):
         return J.jl_solve(op, w["nev"], w["m"], w["mwin"], tol, tol_relative=rel, timing=timing,
-                          workspace=ws, verbose=verbose)
+                          workspace=ws, verbose=verbose, invert=inv, cg_tol=w.get("cg_tol", 0.0))
 
     for _ in range(warmup):
         solve(False)
@@ -177,6 +205,68 @@ def main_batched(args, J, ctx, w, host):
     print(json.dumps(line), flush=True)
 
 
+def main_casea(args, J, ctx, w, host):
+    """Table 1 on the GPU: every published (algorithm, nev, mwin, m) row on the
+    ten matrices; N_conv and N_MV as [min, avg, max], beside the paper's."""
+    import torch
+    rows = json.load(open(os.path.join(ROOT, "tests", "golden", "table1_caseA.json")))["rows"]
+    ops = []
+    for A11, A12, lam in host["mats"]:
+        ops.append((J.jl_op_create_dense(ctx, torch.from_numpy(A11).cuda(), torch.from_numpy(A12).cuda()),
+                    lam))
+    J.jl_solve(ops[0][0], 5, 50, 10, w["tol"], which="largest")   # warm-up
+    table, t_jsym, n_jsym = [], 0.0, 0
+    t_start = time.perf_counter()
+    for alg, nev, mwin, m, *paper in rows:
+        standard = alg == "TRLAN"
+        conv, mv, incomplete = [], [], 0
+        for op, lam in ops:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = J.jl_solve(op, nev, m, mwin, w["tol"], which="largest", standard=standard)
+            dt = time.perf_counter() - t0
+            if out.status != J.JL_OK:
+                raise RuntimeError(f"{alg} {nev}/{mwin}/{m} did not converge: {out.status}")
+            top = lam[::-1]
+            # every returned value is an eigenvalue of A (true residual below tol)
+            if np.abs(out.evals[:, None] - top[None, :]).min(axis=1).max() > 1e-12:
+                raise RuntimeError(f"{alg} {nev}/{mwin}/{m}: eigenvalues off the known spectrum")
+            if standard:
+                # the standard method may stop before the second copy of every
+                # pair has entered its Krylov space (a single-vector Krylov
+                # space holds one direction per eigenspace until rounding adds
+                # the other): count such solves instead of failing them
+                if np.abs(np.sort(out.evals)[::-1] - np.repeat(top[:nev // 2], 2)).max() > 1e-12:
+                    incomplete += 1
+            elif np.abs(out.evals - top[:nev]).max() > 1e-12:
+                raise RuntimeError(f"{alg} {nev}/{mwin}/{m}: not the {nev} largest eigenvalues")
+            conv.append(out.stats["cycles"])
+            mv.append(out.stats["n_mv"])
+            if not standard:
+                t_jsym += dt
+                n_jsym += 1
+        row = dict(algorithm=alg, nev=nev, mwin=mwin, m=m,
+                   n_conv=[min(conv), round(float(np.mean(conv)), 1), max(conv)],
+                   n_mv=[min(mv), round(float(np.mean(mv)), 1), max(mv)],
+                   paper_n_conv=paper[0:3], paper_n_mv=paper[3:6])
+        if standard:
+            row["incomplete_pairs_solves"] = incomplete
+        table.append(row)
+    total = time.perf_counter() - t_start
+    value = t_jsym / n_jsym
+    jsym_mv = np.mean([r["n_mv"][1] for r in table if r["algorithm"] == "TRLAN-JSYM" and r["nev"] == 10])
+    std_mv = np.mean([r["n_mv"][1] for r in table if r["algorithm"] == "TRLAN" and r["nev"] == 20])
+    line = dict(metric=METRIC, value=round(value, 5), unit="s", n_gpus=1, steps=len(rows) * len(ops),
+                warmup=1, ms_per_step=round(value * 1e3, 3), higher_is_better=False, scaling="weak",
+                vs_baseline=None, dtype="f64", data="synthetic",
+                config=dict(workload=describe(w), name=args.workload, n=w["n"], parallelism="1 GPU"),
+                note="value: mean time of one TRLAN-JSYM solve over the grid rows and matrices",
+                total_seconds=round(total, 2),
+                mv_ratio_standard_over_jsym=round(float(std_mv / jsym_mv), 3),
+                table1=table)
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline_batched(w, host, budget_s):
     """The FP64 oracle (Algorithms 1 and 2, literal MGS) solving the problems
     one after another for about budget_s seconds; the per-problem mean time
@@ -203,6 +293,12 @@ def kernel_rates(stats):
         t, nl, b = stats[f"t_{k}"], stats[f"n_{k}_launch"], stats[f"bytes_{k}"]
         if t > 0 and nl > 0:
             out[k] = dict(gbps=b / t / 1e9, avg_us=t / nl * 1e6, bytes_per_launch=b / nl, launches=nl)
+    if stats["t_cg"] > 0 and stats["cg_iters"] > 0:
+        out["cg"] = dict(gbps=stats["bytes_cg"] / stats["t_cg"] / 1e9,
+                         avg_us_per_iter=stats["t_cg"] / stats["cg_iters"] * 1e6,
+                         bytes_per_iter=stats["bytes_cg"] / stats["cg_iters"],
+                         iters=stats["cg_iters"], max_iters=stats["cg_max_iters"],
+                         seconds=stats["t_cg"])
     if stats["t_gemm"] > 0:
         out["gemm"] = dict(tflops=stats["flops_gemm"] / stats["t_gemm"] / 1e12,
                            seconds=stats["t_gemm"], launches=stats["n_gemm_launch"])
@@ -230,7 +326,7 @@ def cpu_baseline(w, host, gpu_stats, budget_s):
     """The FP64 oracle (literal Algorithm 2) on a bounded prefix of the same
     workload: per-step cost fit a + b*j over the first Lanczos steps, then
     extrapolated to the GPU run's N_MV and sum of basis widths."""
-    from oracle import jsym, trlan
+    from oracle import cg, jsym, trlan
     try:
         from threadpoolctl import threadpool_info
         blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
@@ -244,6 +340,9 @@ def cpu_baseline(w, host, gpu_stats, budget_s):
         A = jsym.dense_from_blocks(host["A11"], host["A12"])
         n = A.shape[0]
         apply = lambda v: A @ v
+    step = apply
+    if w.get("invert"):   # invert mode: every Lanczos step solves by the oracle's CG
+        step = lambda v: cg.cg(apply, v, w["cg_tol"], 100000)[0]
     smax = 64
     V = np.zeros((n, smax + 1), dtype=np.complex128)
     T = np.zeros((smax + 1, smax))
@@ -254,7 +353,7 @@ def cpu_baseline(w, host, gpu_stats, budget_s):
     j = 0
     while j < smax and time.perf_counter() - t_start < budget_s:
         t0 = time.perf_counter()
-        trlan.lanczos_jsym(apply, V, T, j, j + 1, stats)
+        trlan.lanczos_jsym(step, V, T, j, j + 1, stats)
         times.append((j, time.perf_counter() - t0))
         j += 1
     js = np.array([t[0] for t in times], float)
@@ -268,7 +367,8 @@ def cpu_baseline(w, host, gpu_stats, budget_s):
     sum_j = gpu_stats["sum_ncol"] - nmv
     est = a * nmv + b * sum_j
     return dict(value=est, unit="s", cores=blas_threads, kind="oracle",
-                sample=(f"first {len(js)} Lanczos steps (Alg. 2, literal MGS, FP64) of the same "
+                sample=(f"first {len(js)} Lanczos steps (Alg. 2, literal MGS, FP64"
+                        f"{', each with a CG solve' if w.get('invert') else ''}) of the same "
                         f"workload in {time.perf_counter() - t_start:.1f} s; per-step time fit "
                         f"{a:.3g} + {b:.3g}*j s extrapolated to the GPU run's N_MV={nmv} and "
                         f"sum j={sum_j} (extrapolated); os.cpu_count()={os.cpu_count()}"))
@@ -316,20 +416,25 @@ def main():
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the multi-GPU "
               "sharding of this solver is a design, not a build.", file=sys.stderr)
         sys.exit(2)
+    w = WORKLOADS[args.workload]
+    # host inputs first: the Case A recipe runs in worker processes, forked
+    # before anything in this process touches the GPU
+    host = None if args.probe else make_host_inputs(w)
     import torch
     from paper_2001_07428_amd import jlanczos as J
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     J.load_library()
-    w = WORKLOADS[args.workload]
     if args.probe:
         probe(w)
         return
-    host = make_host_inputs(w)
     ctx = J.Context(0)
     if w["kind"] == "batched":
         main_batched(args, J, ctx, w, host)
+        return
+    if w["kind"] == "casea":
+        main_casea(args, J, ctx, w, host)
         return
     print(f"[bench] {describe(w)}: mixed solves", file=sys.stderr, flush=True)
     mixed = run_precision(J, ctx, w, host, True, args.steps, args.warmup, args.verbose)
@@ -338,13 +443,22 @@ def main():
         print("[bench] fp64 solves", file=sys.stderr, flush=True)
         fp64 = run_precision(J, ctx, w, host, False, args.steps, args.warmup, args.verbose)
     rates = kernel_rates(mixed["stats"])
-    dom = max(("dots", "update"), key=lambda k: mixed["stats"][f"t_{k}"])
-    achieved = rates[dom]["gbps"]
-    roof = dict(bound="hbm", kernel=f"reorth_{dom}", achieved=round(achieved, 1),
-                peak=HBM_PEAK_GBPS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBPS, 4),
-                traffic=traffic_for(dom, rates[dom]["bytes_per_launch"]),
-                algorithmic_bytes_per_launch=rates[dom]["bytes_per_launch"],
-                avg_launch_us=round(rates[dom]["avg_us"], 2))
+    if "cg" in rates:   # invert mode: the CG loop dominates
+        achieved = rates["cg"]["gbps"]
+        roof = dict(bound="hbm", kernel="cg_iteration (apply + alpha/update/beta/direction)",
+                    achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None,
+                    algorithmic_bytes_per_launch=rates["cg"]["bytes_per_iter"],
+                    avg_launch_us=round(rates["cg"]["avg_us_per_iter"], 2),
+                    note="per CG iteration (five launches), launch gaps included")
+    else:
+        dom = max(("dots", "update"), key=lambda k: mixed["stats"][f"t_{k}"])
+        achieved = rates[dom]["gbps"]
+        roof = dict(bound="hbm", kernel=f"reorth_{dom}", achieved=round(achieved, 1),
+                    peak=HBM_PEAK_GBPS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBPS, 4),
+                    traffic=traffic_for(dom, rates[dom]["bytes_per_launch"]),
+                    algorithmic_bytes_per_launch=rates[dom]["bytes_per_launch"],
+                    avg_launch_us=round(rates[dom]["avg_us"], 2))
     line = dict(
         metric=METRIC, value=round(mixed["seconds"], 4), unit="s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=round(mixed["seconds"] * 1e3, 2), higher_is_better=False,
@@ -352,17 +466,20 @@ def main():
         config=dict(workload=describe(w), name=args.workload, n=mixed["n"], nev=w["nev"], m=w["m"],
                     mwin=w["mwin"], parallelism="1 GPU"),
         mixed=dict(seconds=mixed["seconds"], cycles=mixed["last"].stats["cycles"],
+                   cg_iters=mixed["last"].stats["cg_iters"],
                    n_mv=mixed["last"].stats["n_mv"], gs_passes=mixed["last"].stats["gs_passes"],
                    res_max=float(mixed["last"].res.max()), kernels=rates),
-        matvec_GBps=dict(mixed=round(rates["matvec"]["gbps"], 1)),
+        matvec_GBps=dict(mixed=round(rates["matvec"]["gbps"], 1)) if "matvec" in rates else {},
         roofline=roof,
     )
     if fp64 is not None:
         r64 = kernel_rates(fp64["stats"])
         line["fp64"] = dict(seconds=fp64["seconds"], cycles=fp64["last"].stats["cycles"],
+                            cg_iters=fp64["last"].stats["cg_iters"],
                             n_mv=fp64["last"].stats["n_mv"], gs_passes=fp64["last"].stats["gs_passes"],
                             res_max=float(fp64["last"].res.max()), kernels=r64)
-        line["matvec_GBps"]["fp64"] = round(r64["matvec"]["gbps"], 1)
+        if "matvec" in r64:
+            line["matvec_GBps"]["fp64"] = round(r64["matvec"]["gbps"], 1)
         line["speedup_mixed_vs_fp64"] = round(fp64["seconds"] / mixed["seconds"], 3)
         e32, e64 = mixed["last"].evals, fp64["last"].evals
         line["mixed_vs_fp64_max_rel_eig_diff"] = float(np.abs(e32 - e64).max() / np.abs(e64).max())

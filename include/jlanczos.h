@@ -110,7 +110,8 @@ jl_status jl_op_apply(jl_op op, const void* x, void* y, int32_t nrhs);
 
 typedef struct {
   int32_t nev;          /* number of desired pairs (1 <= nev <= mwin)          */
-  int32_t m;            /* maximum Krylov dimension (mwin < m <= n/2)          */
+  int32_t m;            /* maximum Krylov dimension (mwin < m <= n/2; with
+                           standard, m <= n)                                   */
   int32_t mwin;         /* restart window: k = min(icnv + mwin, m - 1)         */
   int32_t which;        /* jl_which                                            */
   double tol;           /* residual tolerance: ||A x - lambda x|| < tol          */
@@ -125,6 +126,24 @@ typedef struct {
   int32_t trace_cap;    /* record alpha_j, beta_j of the first trace_cap steps */
   double* trace_ab;     /* host [2 * trace_cap]: alpha then beta (may be NULL) */
   int32_t verbose;      /* nonzero: one progress line per cycle on stderr      */
+  int32_t standard;     /* nonzero: the standard thick-restart Lanczos the
+                           paper compares against (Sec. 3): no projection on
+                           J V^*, so each pair is found twice; zero (the
+                           default): the J-restricted method of Alg. 1/2     */
+  int32_t invert;       /* nonzero: invert mode (Alg. 1 and 2, invert
+                           branches; Sec. 4.2): every Lanczos step takes
+                           u = A^-1 v_j by conjugate gradients, so A must be
+                           Hermitian positive definite; the Ritz values theta
+                           are those of A^-1, the pairs returned have
+                           ev = 1/theta, the residual estimate is
+                           ||A v_{m+1}|| |t_{m+1,i} ev_i| and the true residual
+                           ||A x - ev x||.  which names the end of A's
+                           spectrum (JL_LOWEST: the smallest eigenvalues).
+                           With tol_relative the scale is the running max of
+                           ||A v_{m+1}|| and the wanted |ev|.                */
+  int32_t cg_maxit;     /* CG iterations per solve cap (<= 0: 10000)            */
+  double cg_tol;        /* CG stops once ||v_j - A u|| <= cg_tol ||v_j|| on the
+                           recursively updated residual (<= 0: tol)           */
 } jl_params;
 
 typedef struct {
@@ -141,6 +160,16 @@ typedef struct {
   double t_matvec, t_dots, t_update, t_gemm, t_ritz, t_resid;
   int64_t n_matvec_launch, n_dots_launch, n_update_launch, n_gemm_launch;
   double bytes_matvec, bytes_dots, bytes_update, flops_gemm;
+  /* Invert mode: CG iterations over all solves (each one operator apply),
+   * the most in one solve, solves stopped by cg_maxit, (with timing) the GPU
+   * time of the CG solves [s], and their algorithmic bytes (per iteration
+   * one operator apply plus nine vector passes: x, r, p, q read and x, r
+   * written by the update, r, p read and p written by the direction step). */
+  int64_t cg_iters;
+  int32_t cg_max_iters;
+  int32_t cg_unconverged;
+  double t_cg;
+  double bytes_cg;
 } jl_stats;
 
 /* Workspace bytes jl_solve needs for `op` and `p`. */
@@ -164,7 +193,10 @@ jl_status jl_workspace_bytes(jl_op op, const jl_params* p, size_t* bytes);
  * max_cycles (the first stats.icnv entries are converged), JL_BREAKDOWN when
  * the Krylov space became invariant before nev pairs converged (converged
  * entries first).  Errors: JL_EINVAL for parameters outside the ranges
- * above, JL_ENOMEM for a short workspace, JL_EHIP for runtime failures. */
+ * above or, in invert mode, when CG meets p^H A p <= 0 (A not positive
+ * definite), JL_ENOMEM for a short workspace, JL_EHIP for runtime failures.
+ * In invert mode "matvec" in n_mv means one solve A^-1 v_j (as Sec. 3 counts
+ * it); the applications of A for ||A v_{m+1}|| count in n_resid. */
 jl_status jl_solve(jl_op op, const jl_params* p, const void* v1, void* ws, size_t ws_bytes,
                    double* evals, void* X, int64_t ldx, double* res, jl_stats* stats);
 
@@ -183,7 +215,9 @@ jl_status jl_pair_vectors(jl_ctx ctx, int64_t n, int32_t k, jl_dtype dtype, cons
  * the queue reset and the result copies are captured once in a hipGraph at
  * jl_batch_create and replayed by every jl_batch_run.
  *
- * Limits: m + (m mod 2) <= 60, 2 <= n_i, m <= n_i / 2, nev <= mwin < m.
+ * Limits: m + (m mod 2) <= 60, 2 <= n_i, m <= n_i / 2, nev <= mwin < m;
+ * normal mode, J-restricted only (p->standard and p->invert must be 0, else
+ * JL_EUNSUPPORTED).
  * threads: workgroup size (128, 256 or 512; 0 = 256); blocks: persistent
  * workgroups (0 = min(count, 2 x compute units)); both are tuning knobs.
  * X[i] (device, n_i x nev column-major, leading dimension n_i) receives the

@@ -44,6 +44,8 @@ jl_status batch_layout(jl_ctx ctx, int count, const int64_t* n, jl_dtype dtype, 
   if (p->m + (p->m & 1) > 60) return set_err(ctx, JL_EINVAL, "batched solver supports m <= 59 (got %d)", p->m);
   if (!(p->tol > 0.0)) return set_err(ctx, JL_EINVAL, "tol must be positive");
   if (p->which != JL_LOWEST && p->which != JL_LARGEST) return set_err(ctx, JL_EINVAL, "invalid which");
+  if (p->standard) return set_err(ctx, JL_EUNSUPPORTED, "the batched solver is J-restricted only");
+  if (p->invert) return set_err(ctx, JL_EUNSUPPORTED, "the batched solver has no invert mode");
   int64_t hmax = 0;
   for (int i = 0; i < count; ++i) {
     if (n[i] < 2 || n[i] % 2) return set_err(ctx, JL_EINVAL, "n[%d] = %lld must be even and >= 2", i, (long long)n[i]);

@@ -24,7 +24,6 @@ constexpr int kWave = 64;
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `st` and returns the launch error (if any).
 
-// Stencil operator data (d = 4).  U: [4][V][4][4], B: [4][4][4] or [4][V][4][4].
 // Stencil operator data.  U: links in site-fastest order, entry e of U_mu(s)
 // at U[(mu * 16 + e) * V + s]; B: the 4 direction matrices [mu][16], or with
 // b_per_site the layout of U.
@@ -36,6 +35,10 @@ template <typename S> struct StencilArgs {
   int b_per_site;
   double diag;
   double scale;
+  // When non-null, the apply kernels return at once while *skip != 0 (a
+  // device flag: the conjugate-gradient loop sets it on convergence, so
+  // launches queued past that point do no work).  Null for plain applies.
+  const double* skip;
 };
 
 // y = A x for nrhs columns (ld = n), compute type = S.  With apart !=
@@ -44,7 +47,7 @@ template <typename S> struct StencilArgs {
 template <typename S>
 hipError_t launch_stencil_apply(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
                                 int nrhs, double* apart, hipStream_t st);
-int stencil_apply_blocks(int64_t V);
+int stencil_apply_blocks(int64_t V, int es);   // es: bytes per complex element
 // Per-block partial sums of ||A x_c - lam_c x_c||^2 (FP64 compute) for ncols
 // columns x_c = X + cols[c]*ldx (cols, lam on the device); partial layout
 // [blk][c]; *nblk = blocks per column.
@@ -64,6 +67,7 @@ template <typename S> struct DenseArgs {
   const cplx<S>* A12;
   int64_t h;
   int64_t ld;
+  const double* skip;   // as StencilArgs::skip
 };
 template <typename S>
 hipError_t launch_dense_apply(const DenseArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ldv,
@@ -93,8 +97,10 @@ hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* 
 // update: u -= V c_v + W c_w (W = J V^*), coef = [4*ncol] FP64 (Re cv, Im cv,
 // Re cw, Im cw per column); partial[blk] = ||u_new||^2 per block.
 template <typename S>
+// jsym = false leaves out the W projection (standard Gram-Schmidt against V).
 hipError_t launch_reorth_update(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
-                                const double* coef, double* partial, int nblk, hipStream_t st);
+                                const double* coef, double* partial, int nblk, hipStream_t st,
+                                bool jsym = true);
 // out[c] = sum_b partial[b * stride + c] for c < ncols (deterministic order).
 hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int ncols, double* out,
                               hipStream_t st);
@@ -112,6 +118,33 @@ hipError_t launch_pair(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t ldy, i
 template <typename S>
 hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t ldy, int64_t n,
                             int k, hipStream_t st);
+
+// ------------------------------------------------- conjugate gradients (invert)
+// Device scalars of one CG solve (doubles at cs[slot]).
+enum CgSlot {
+  CG_RR = 0, CG_ALPHA, CG_BETA, CG_THR, CG_DONE, CG_ITERS, CG_MAXIT, CG_BB, CG_CNT, CG_NSLOTS
+};
+// CG_DONE: 0 running, 1 stopped (converged or maxit), 2 p^H A p <= 0.
+// CG_CNT: the fused step's finished-block counter (an unsigned in the slot).
+int cg_blocks(int64_t n);   // partial sums written by the CG vector kernels
+// x = 0, r = p = b; starts the solve of A x = b (stop at ||r|| <= tol ||b||).
+template <typename S>
+hipError_t launch_cg_init(const cplx<S>* b, cplx<S>* x, cplx<S>* r, cplx<S>* p, int64_t n,
+                          double* part, double* cs, double tol, int maxit, hipStream_t st);
+// The rest of one iteration after q = A p (apart: the apply's napply
+// partials of p^H q): alpha, x and r, beta and the stop test (one launch),
+// then p (a second).
+template <typename S>
+hipError_t launch_cg_step(cplx<S>* x, cplx<S>* r, cplx<S>* p, const cplx<S>* q, int64_t n,
+                          const double* apart, int napply, double* part, double* cs,
+                          hipStream_t st);
+// u = x and the partials of v^H u (2 per block, cg_blocks(n) blocks).
+template <typename S>
+hipError_t launch_cg_finish(const cplx<S>* x, cplx<S>* u, const cplx<S>* v, int64_t n,
+                            double* part, hipStream_t st);
+// Partials of x^H x (cg_blocks(n) blocks).
+template <typename S>
+hipError_t launch_norm2(const cplx<S>* x, int64_t n, double* part, hipStream_t st);
 
 // ------------------------------------------------------------ restart GEMM
 // C (M x N, ldc) = A (M x K, lda) * B (K x N, ldb), real, column-major; A

@@ -183,6 +183,21 @@ hipError_t op_apply(const jl_op_s* op, const cplx<S>* x, cplx<S>* y, int64_t ld,
   return launch_dense_apply<S>(OpView<S>::de(op), x, y, ld, nrhs, apart, st);
 }
 
+// y = A x (one column) returning at once while *skip != 0 (CG launches
+// queued past convergence).
+template <typename S>
+hipError_t op_apply_skip(const jl_op_s* op, const double* skip, const cplx<S>* x, cplx<S>* y,
+                         double* apart, hipStream_t st) {
+  if (op->kind == OP_STENCIL) {
+    StencilArgs<S> a = OpView<S>::st(op);
+    a.skip = skip;
+    return launch_stencil_apply<S>(a, x, y, op->n, 1, apart, st);
+  }
+  DenseArgs<S> a = OpView<S>::de(op);
+  a.skip = skip;
+  return launch_dense_apply<S>(a, x, y, op->n, 1, apart, st);
+}
+
 template <typename S>
 hipError_t op_resid(const jl_op_s* op, const cplx<S>* X, int64_t ldx, const int* cols,
                     const double* lam, int ncols, double* partial, int* nblk, hipStream_t st) {
@@ -192,7 +207,8 @@ hipError_t op_resid(const jl_op_s* op, const cplx<S>* X, int64_t ldx, const int*
 }
 
 int op_apply_blocks(const jl_op_s* op) {
-  return op->kind == OP_STENCIL ? stencil_apply_blocks(op->n / 8) : dense_apply_blocks(op->n / 2);
+  return op->kind == OP_STENCIL ? stencil_apply_blocks(op->n / 8, op->dtype == JL_C64 ? 8 : 16)
+                                 : dense_apply_blocks(op->n / 2);
 }
 
 int op_resid_blocks(const jl_op_s* op) {
@@ -213,7 +229,7 @@ double op_bytes(const jl_op_s* op, int es) {
 // ----------------------------------------------------------- workspace layout
 struct Layout {
   size_t V[2], apart, dots_part, upd_part, coef, scal, Tdev, ritz, lam_s, Zs, zlast, res_part,
-      res_out, res_lam, res_cols, total;
+      res_out, res_lam, res_cols, cg_vec[4], cg_part, cg_s, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -245,6 +261,11 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   L.res_out = take(sizeof(double) * p->nev);
   L.res_lam = take(sizeof(double) * p->nev);
   L.res_cols = take(sizeof(int) * p->nev);
+  if (p->invert) {   // CG: x, r, p, q; partial sums; device scalars
+    for (int i = 0; i < 4; ++i) L.cg_vec[i] = take((size_t)n * es);
+    L.cg_part = take(sizeof(double) * 2 * (size_t)cg_blocks(n));
+    L.cg_s = take(sizeof(double) * CG_NSLOTS);
+  }
   L.total = off;
   return L;
 }
@@ -256,9 +277,11 @@ jl_status check_params(jl_ctx ctx, const jl_op_s* op, const jl_params* p) {
   if (p->mwin < p->nev)
     return set_err(ctx, JL_EINVAL, "mwin (%d) must be >= nev (%d)", p->mwin, p->nev);
   if (p->m <= p->mwin) return set_err(ctx, JL_EINVAL, "m (%d) must exceed mwin (%d)", p->m, p->mwin);
-  if ((int64_t)p->m > n / 2)
+  if (!p->standard && (int64_t)p->m > n / 2)
     return set_err(ctx, JL_EINVAL, "m (%d) exceeds n/2 (%lld): the J-half Krylov space is exhausted",
                    p->m, (long long)(n / 2));
+  if (p->standard && (int64_t)p->m > n)
+    return set_err(ctx, JL_EINVAL, "m (%d) exceeds n (%lld)", p->m, (long long)n);
   if (p->m + 1 > kReorthMaxCols)
     return set_err(ctx, JL_EINVAL, "m (%d) exceeds the supported maximum %d", p->m,
                    kReorthMaxCols - 1);
@@ -267,13 +290,15 @@ jl_status check_params(jl_ctx ctx, const jl_op_s* op, const jl_params* p) {
     return set_err(ctx, JL_EINVAL, "which must be JL_LOWEST or JL_LARGEST");
   if (p->trace_cap < 0 || (p->trace_cap > 0 && !p->trace_ab))
     return set_err(ctx, JL_EINVAL, "trace_cap > 0 needs trace_ab");
+  if (p->invert && !(p->cg_tol < 1.0))
+    return set_err(ctx, JL_EINVAL, "cg_tol must be below 1");
   return JL_OK;
 }
 
 // Accumulates GPU time of kernel classes from HIP event pairs; pairs are
 // resolved at the driver's synchronisation points.
 struct Timer {
-  enum { MATVEC, DOTS, UPDATE, GEMM, RITZ, RESID, NCLS };
+  enum { MATVEC, DOTS, UPDATE, GEMM, RITZ, RESID, CG, NCLS };
   bool on = false;
   hipStream_t st = nullptr;
   std::vector<hipEvent_t> pool;
@@ -350,6 +375,13 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   const int es = (int)sizeof(cplx<S>);
   const double uround = sizeof(S) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
   const double bd_factor = 64.0;
+  const bool jsym = prm->standard == 0;   // J-restricted (Alg. 2) or standard Gram-Schmidt
+  const bool invert = prm->invert != 0;   // Lanczos on A^-1 (Alg. 1 and 2, invert mode)
+  // sort order of theta: the wanted end of A's spectrum, reversed under inversion
+  const int descending = ((prm->which == JL_LOWEST) == invert) ? 1 : 0;
+  const int cg_maxit = prm->cg_maxit > 0 ? prm->cg_maxit : 10000;
+  const double cg_tol = prm->cg_tol > 0.0 ? prm->cg_tol : prm->tol;
+  constexpr int kCgChunk = 8;   // CG iterations queued between two looks at the done flag
 
   const Layout L = make_layout(op, prm);
   if (!ws || ws_bytes < L.total)
@@ -375,6 +407,15 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   double* res_dev = reinterpret_cast<double*>(base + L.res_out);
   double* res_lam = reinterpret_cast<double*>(base + L.res_lam);
   int* res_cols = reinterpret_cast<int*>(base + L.res_cols);
+  cplx<S>* cgv[4] = {nullptr, nullptr, nullptr, nullptr};   // x, r, p, q
+  double* cg_part = nullptr;
+  double* cgs = nullptr;
+  if (invert) {
+    for (int i = 0; i < 4; ++i) cgv[i] = reinterpret_cast<cplx<S>*>(base + L.cg_vec[i]);
+    cg_part = reinterpret_cast<double*>(base + L.cg_part);
+    cgs = reinterpret_cast<double*>(base + L.cg_s);
+  }
+  const int ncgb = cg_blocks(n);
 
   const int ndots = reorth_dots_blocks(h);
   const int napply = op_apply_blocks(op);
@@ -382,10 +423,11 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   const int64_t ldv = n;
 
   Pinned pin;
-  const size_t pin_doubles = 16 + 3 * (size_t)m + 3 * (size_t)nev;
+  const size_t pin_doubles = 16 + CG_NSLOTS + 3 * (size_t)m + 3 * (size_t)nev;
   JL_HIP(ctx, hipHostMalloc((void**)&pin.p, sizeof(double) * pin_doubles, hipHostMallocDefault));
   double* hs = pin.p;                    // [16] scalars
-  double* h_lam = pin.p + 16;            // [m]
+  double* h_cg = pin.p + 16;             // [CG_NSLOTS] CG scalars
+  double* h_lam = h_cg + CG_NSLOTS;      // [m]
   double* h_zl = h_lam + m;              // [m]
   double* h_res = h_zl + m;              // [nev]
   double* h_rlam = h_res + nev;          // [nev]
@@ -415,7 +457,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   auto Tat = [&](int i, int j) -> double& { return T[(size_t)i + (size_t)j * (m + 1)]; };
   double maxT = 0.0;
   std::vector<double> Tm((size_t)m * m);
-  std::vector<double> lam_sorted(m), svec(m);
+  std::vector<double> lam_sorted(m), svec(m), evv(m), est(m);   // theta, t_{m+1,i}, ev, res_est
   double tol_scale = 0.0;   // running max |theta| for tol_relative
   std::vector<char> conv(nev);
   std::vector<double> resv(nev);
@@ -425,6 +467,48 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   jl_status status = JL_NOT_CONVERGED;
   int icnv = 0;
   std::vector<int> out_order;
+
+  // Invert mode: u = A^-1 b by CG on the device, then t_jj = b^H u into
+  // scal[0..1] (where the normal mode's apply leaves it).
+  int cg_prev = 0;   // iterations of the previous solve: queued before the first look
+  auto cg_solve = [&](const cplx<S>* b, cplx<S>* u) -> jl_status {
+    cplx<S>* const x = cgv[0];
+    cplx<S>* const r = cgv[1];
+    cplx<S>* const p = cgv[2];
+    cplx<S>* const q = cgv[3];
+    tm.start(Timer::CG);
+    JL_HIP(ctx, launch_cg_init<S>(b, x, r, p, n, cg_part, cgs, cg_tol, cg_maxit, st));
+    int issued = 0;
+    int batch = std::max(kCgChunk, cg_prev - cg_prev % kCgChunk);
+    for (;;) {
+      for (int c = 0; c < batch; ++c) {
+        JL_HIP(ctx, op_apply_skip<S>(op, cgs + CG_DONE, p, q, apart, st));
+        JL_HIP(ctx, launch_cg_step<S>(x, r, p, q, n, apart, napply, cg_part, cgs, st));
+      }
+      issued += batch;
+      JL_HIP(ctx, hipMemcpyAsync(h_cg, cgs, sizeof(double) * CG_NSLOTS, hipMemcpyDeviceToHost, st));
+      JL_HIP(ctx, hipStreamSynchronize(st));
+      if (h_cg[CG_DONE] != 0.0) break;
+      if (issued > cg_maxit + kCgChunk)   // the stop test fires at cg_maxit at the latest
+        return set_err(ctx, JL_EHIP, "CG did not report its stop after %d iterations", issued);
+      batch = kCgChunk;
+    }
+    if (h_cg[CG_DONE] == 2.0)
+      return set_err(ctx, JL_EINVAL,
+                     "invert mode: CG met p^H A p <= 0 (the operator is not positive definite)");
+    const int it = (int)h_cg[CG_ITERS];
+    S_.cg_iters += it;
+    S_.cg_max_iters = std::max(S_.cg_max_iters, it);
+    if (!(h_cg[CG_RR] <= h_cg[CG_THR])) S_.cg_unconverged++;
+    S_.n_matvec_launch += it;
+    S_.bytes_matvec += it * op_bytes(op, es);
+    S_.bytes_cg += it * (op_bytes(op, es) + 9.0 * (double)n * es);
+    cg_prev = it;
+    JL_HIP(ctx, launch_cg_finish<S>(x, u, b, n, cg_part, st));
+    JL_HIP(ctx, launch_reduce_cols(cg_part, ncgb, 2, 2, scal, st));
+    tm.stop();
+    return JL_OK;
+  };
 
   for (int cycle = 0; cycle < max_cycles; ++cycle) {
     S_.cycles++;
@@ -438,15 +522,19 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       cplx<S>* u = V + (int64_t)(j + 1) * ldv;
       const int ncol = j + 1;
       const int stride = 4 * ncol + 1;
-      // u = A v_j, with the block partial sums of t_jj = v_j^H u
-      tm.start(Timer::MATVEC);
-      JL_HIP(ctx, op_apply<S>(op, vj, u, ldv, 1, apart, st));
-      tm.stop();
-      JL_HIP(ctx, launch_reduce_cols(apart, napply, 2, 2, scal, st));
+      if (invert) {   // u = A^-1 v_j by CG, t_jj = v_j^H u into scal
+        const jl_status cs = cg_solve(vj, u);
+        if (cs != JL_OK) return cs;
+      } else {        // u = A v_j, with the block partial sums of t_jj = v_j^H u
+        tm.start(Timer::MATVEC);
+        JL_HIP(ctx, op_apply<S>(op, vj, u, ldv, 1, apart, st));
+        tm.stop();
+        JL_HIP(ctx, launch_reduce_cols(apart, napply, 2, 2, scal, st));
+        S_.n_matvec_launch++;
+        S_.bytes_matvec += op_bytes(op, es);
+      }
       S_.n_mv++;
       S_.sum_ncol += ncol;
-      S_.n_matvec_launch++;
-      S_.bytes_matvec += op_bytes(op, es);
       // local three-term step u -= t_jj v_j + beta_{j-1} v_{j-1} fused into the
       // first inner products against [V_j, W_j]; then the first update pass
       const double beta_prev = (j > k) ? Tat(j, j - 1) : 0.0;
@@ -457,7 +545,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       S_.n_dots_launch++;
       S_.bytes_dots += (double)(ncol + 1) * n * es;
       tm.start(Timer::UPDATE);
-      JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st));
+      JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st, jsym));
       tm.stop();
       JL_HIP(ctx, launch_reduce_cols(upd_part, nupd, 1, 1, scal + 2, st));
       S_.n_update_launch++;
@@ -483,7 +571,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
         S_.n_dots_launch++;
         S_.bytes_dots += (double)(ncol + 1) * n * es;
         tm.start(Timer::UPDATE);
-        JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st));
+        JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st, jsym));
         tm.stop();
         JL_HIP(ctx, launch_reduce_cols(upd_part, nupd, 1, 1, scal + 2, st));
         S_.n_update_launch++;
@@ -534,7 +622,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       }
       for (int j = k; j < meff; ++j) Tm[2 * k + (j - k)] = Tat(j, j);
       for (int j = k; j + 1 < meff; ++j) Tm[2 * k + (meff - k) + (j - k)] = Tat(j + 1, j);
-      JL_HIP(ctx, ritz_arrow_device<S>(meff, k, Tm.data(), prm->which == JL_LARGEST, 0, ritz_scr, lam_s,
+      JL_HIP(ctx, ritz_arrow_device<S>(meff, k, Tm.data(), descending, 0, ritz_scr, lam_s,
                                        Zs, nullptr, zlast, st));
     } else {
       for (int jj = 0; jj < meff; ++jj)
@@ -546,7 +634,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       for (int i = 0; i < meff * meff; ++i) fro2 += Tm[i] * Tm[i];
       JL_HIP(ctx, hipMemcpyAsync(Tdev, Tm.data(), sizeof(double) * (size_t)meff * meff,
                                  hipMemcpyHostToDevice, st));
-      JL_HIP(ctx, ritz_device<S>(meff, Tdev, fro2, prm->which == JL_LARGEST, 0, ritz_scr, lam_s, Zs,
+      JL_HIP(ctx, ritz_device<S>(meff, Tdev, fro2, descending, 0, ritz_scr, lam_s, Zs,
                                  nullptr, zlast, hs, st));
     }
     JL_HIP(ctx, hipMemcpyAsync(h_lam, lam_s, sizeof(double) * meff, hipMemcpyDeviceToHost, st));
@@ -566,16 +654,44 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       lam_sorted[i] = h_lam[i];
       svec[i] = beta_m * h_zl[i];   // t_{m+1,i} = t_{m+1,m} z_{m,i}
     }
+    // ================= estimated residuals (Alg. 1): |t_{m+1,i}|, or in
+    // invert mode c |t_{m+1,i} ev_i| with ev_i = 1/theta_i, c = ||A v_{m+1}||
+    if (invert) {
+      double c = 0.0;
+      if (!broke) {   // after a breakdown there is no v_{m+1} (the couplings are zero)
+        tm.start(Timer::RESID);
+        JL_HIP(ctx, op_apply<S>(op, V + (int64_t)meff * ldv, cgv[3], ldv, 1, nullptr, st));
+        JL_HIP(ctx, launch_norm2<S>(cgv[3], n, cg_part, st));
+        JL_HIP(ctx, launch_reduce_cols(cg_part, ncgb, 1, 1, scal + 4, st));
+        JL_HIP(ctx, hipMemcpyAsync(hs + 4, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+        tm.stop();
+        JL_HIP(ctx, hipStreamSynchronize(st));
+        tm.resolve();
+        S_.n_resid++;
+        c = std::sqrt(hs[4]);
+      }
+      tol_scale = std::max(tol_scale, c);
+      for (int i = 0; i < meff; ++i) {
+        evv[i] = 1.0 / lam_sorted[i];
+        est[i] = c * std::fabs(svec[i] * evv[i]);
+      }
+      for (int i = 0; i < nev; ++i) tol_scale = std::max(tol_scale, std::fabs(evv[i]));
+    } else {
+      for (int i = 0; i < meff; ++i) {
+        evv[i] = lam_sorted[i];
+        est[i] = std::fabs(svec[i]);
+      }
+      tol_scale = std::max(tol_scale, std::max(std::fabs(lam_sorted[0]), std::fabs(lam_sorted[meff - 1])));
+    }
     // ================= convergence check on the true residuals (Alg. 1)
-    tol_scale = std::max(tol_scale, std::max(std::fabs(lam_sorted[0]), std::fabs(lam_sorted[meff - 1])));
     const double tol_abs = prm->tol_relative ? prm->tol * tol_scale : prm->tol;
     int ncand = 0;
     for (int i = 0; i < nev; ++i) {
       conv[i] = 0;
       resv[i] = INFINITY;
-      if (std::fabs(svec[i]) < tol_abs) {
+      if (est[i] < tol_abs) {
         h_rcols[ncand] = i;
-        h_rlam[ncand] = lam_sorted[i];
+        h_rlam[ncand] = evv[i];
         ncand++;
       }
     }
@@ -605,8 +721,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       if (!conv[i]) out_order.push_back(i);
     if (prm->verbose) {
       double worst = 0.0;
-      for (int i = 0; i < nev; ++i) worst = std::max(worst, std::fabs(svec[i]));
-      fprintf(stderr, "[jlanczos] cycle %d k %d m %d icnv %d/%d max|s| %.2e n_mv %d t %.2fs\n",
+      for (int i = 0; i < nev; ++i) worst = std::max(worst, est[i]);
+      fprintf(stderr, "[jlanczos] cycle %d k %d m %d icnv %d/%d max res_est %.2e n_mv %d t %.2fs\n",
               cycle + 1, k, meff, icnv, nev, worst, S_.n_mv,
               std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count());
       fflush(stderr);
@@ -638,7 +754,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     cplx<S>* X = static_cast<cplx<S>*>(Xout);
     for (int c = 0; c < nev; ++c) {
       const int i = out_order[c];
-      evals[c] = lam_sorted[i];
+      evals[c] = evv[i];
       res_out[c] = resv[i];
       JL_HIP(ctx, launch_copy_cols<S>(Vf + (int64_t)i * ldv, ldv, X + (int64_t)c * ldx, ldx, n, 1,
                                       st));
@@ -654,6 +770,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   S_.t_gemm = tm.t[Timer::GEMM];
   S_.t_ritz = tm.t[Timer::RITZ];
   S_.t_resid = tm.t[Timer::RESID];
+  S_.t_cg = tm.t[Timer::CG];
   S_.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count();
   if (stats) *stats = S_;
   return status;

@@ -11,7 +11,7 @@
 // above the mixed-precision tolerance.
 //
 // Block tile 128 x 128, 4 wavefronts in 2 x 2, each 64 x 64 = 4 x 4 MFMA
-// tiles; K staged through LDS (as FP64) in steps of 8 with a
+// tiles (computed transposed so that stores run down the columns of C); K staged through LDS (as FP64) in steps of 8 with a
 // register prefetch of the next step and two LDS buffers (one barrier per
 // step).  Consecutive tiles of one row panel are placed on the same XCD so
 // the A panel is shared through that XCD's L2.
@@ -131,27 +131,29 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nn(const S* __restrict__ A, i
       for (int i = 0; i < 4; ++i) a[i] = As[buf][kr][wm * 64 + i * 16 + lane % 16];
 #pragma unroll
       for (int j = 0; j < 4; ++j) bb[j] = Bs[buf][kr][wn * 64 + j * 16 + lane % 16];
+      // the transposed tile product (B^T A^T): the MFMA output then runs
+      // along the rows of C in consecutive lanes
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = MF::op(a[i], bb[j], acc[i][j]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = MF::op(bb[j], a[i], acc[i][j]);
     }
   }
 
   // Output layout of v_mfma_f64_16x16x4f64: lane l holds column l % 16 of the
-  // 16 x 16 tile, register r holds row 4*r + l/16.
+  // 16 x 16 tile, register r holds row 4*r + l/16.  The tile here is C^T, so
+  // lane l holds row l % 16 of C and register r column 4*r + l/16: each store
+  // writes 16 consecutive rows of 4 columns.
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int col = n0 + wn * 64 + j * 16 + lane % 16;
-    if (col >= N) continue;
-    S* pc = C + (int64_t)col * ldc;
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = m0 + wm * 64 + i * 16 + lane % 16;
+    if (row >= M) continue;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t tile_row = m0 + wm * 64 + i * 16;
+    for (int j = 0; j < 4; ++j) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = tile_row + 4 * r + lane / 16;
-        if (row < M) pc[row] = (S)acc[i][j][r];
+        const int col = n0 + wn * 64 + j * 16 + 4 * r + lane / 16;
+        if (col < N) C[(int64_t)col * ldc + row] = (S)acc[i][j][r];
       }
     }
   }

@@ -167,6 +167,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply(StencilArgs<S
                                                                    cplx<S>* __restrict__ y,
                                                                    int64_t ld,
                                                                    double* __restrict__ apart) {
+  if (a.skip && *a.skip != 0.0) return;   // uniform over the grid
   __shared__ double sh[kStencilThreads / 64];
   const int64_t s = (int64_t)blockIdx.x * kStencilThreads + threadIdx.x;
   const int64_t h = a.V * 4;
@@ -215,6 +216,139 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {   // result 
   }
   __syncthreads();
   return r;
+}
+
+// y = A x with four threads per site: thread q of a site handles direction
+// mu = q (both hops); the partial outputs are summed over the site's four
+// lanes with cross-lane exchanges, after which lane q holds row q of both
+// halves and stores it (the four lanes write the site's components
+// contiguously).  Four times the wavefronts of the one-thread-per-site form,
+// for lattices too small to fill the device with one thread per site.
+template <typename S, bool BSITE>
+__global__ __launch_bounds__(kStencilThreads) void k_stencil_apply4(StencilArgs<S> a,
+                                                                    const cplx<S>* __restrict__ x,
+                                                                    cplx<S>* __restrict__ y,
+                                                                    int64_t ld,
+                                                                    double* __restrict__ apart) {
+  if (a.skip && *a.skip != 0.0) return;   // uniform over the grid
+  __shared__ double sh[kStencilThreads / 64];
+  const int64_t gt = (int64_t)blockIdx.x * kStencilThreads + threadIdx.x;
+  const int64_t s = gt >> 2;
+  const int mu = (int)(gt & 3);
+  const int64_t h = a.V * 4;
+  const cplx<S>* xt = x + (int64_t)blockIdx.y * ld;
+  const cplx<S>* xb = xt + h;
+  cplx<S>* yc = y + (int64_t)blockIdx.y * ld;
+  const bool active = s < a.V;          // whole quads are active or not (4 | blockDim)
+  const int64_t sc = active ? s : 0;    // inactive quads compute a harmless site
+  cx<S> top[4], bot[4];
+  {
+    const int Ls[4] = {a.L[0], a.L[1], a.L[2], a.L[3]};
+    const int64_t st[4] = {(int64_t)Ls[1] * Ls[2] * Ls[3], (int64_t)Ls[2] * Ls[3], (int64_t)Ls[3], 1};
+    int64_t r = sc;
+    int xm = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int xd = (int)(r / st[d]);
+      r -= (int64_t)xd * st[d];
+      if (d == mu) xm = xd;
+    }
+    const int Lm = Ls[mu];
+    const int64_t stm = st[mu];
+    const int64_t sf = (xm == Lm - 1) ? sc - (int64_t)(Lm - 1) * stm : sc + stm;
+    const int64_t sb = (xm == 0) ? sc + (int64_t)(Lm - 1) * stm : sc - stm;
+    const S sca = (S)a.scale;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) top[q] = bot[q] = cx<S>{0, 0};
+    if (mu == 0) {   // the diagonal term, once per site
+      const S dg = (S)a.diag;
+      S ar[4], ai[4], br[4], bi[4];
+      load_site<S, S>(xt + sc * 4, ar, ai);
+      load_site<S, S>(xb + sc * 4, br, bi);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        top[q].re = dg * ar[q]; top[q].im = dg * ai[q];
+        bot[q].re = dg * br[q]; bot[q].im = dg * bi[q];
+      }
+    }
+    const int64_t V = a.V;
+    const cplx<S>* Um = a.U + (int64_t)mu * 16 * V;
+    const cplx<S>* Bm = BSITE ? a.B + (int64_t)mu * 16 * V : a.B + mu * 16;
+    {   // forward hop: U(x) a(x+mu), conj(U(x)) b(x+mu), B(x) b(x+mu), conj(B(x)) a(x+mu)
+      S ar[4], ai[4], br[4], bi[4];
+      load_site<S, S>(xt + sf * 4, ar, ai);
+      load_site<S, S>(xb + sf * 4, br, bi);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cx<S> t = {0, 0}, u = {0, 0}, tb = {0, 0}, ub = {0, 0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const cplx<S> l = Um[(int64_t)(4 * q + c) * V + sc];
+          const cplx<S> w = BSITE ? Bm[(int64_t)(4 * q + c) * V + sc] : Bm[4 * q + c];
+          mac(t, l.x, l.y, ar[c], ai[c]);
+          mac_conj_a(u, l.x, l.y, br[c], bi[c]);
+          mac(tb, w.x, w.y, br[c], bi[c]);
+          mac_conj_a(ub, w.x, w.y, ar[c], ai[c]);
+        }
+        top[q].re += sca * tb.re - t.re; top[q].im += sca * tb.im - t.im;
+        bot[q].re -= u.re + sca * ub.re; bot[q].im -= u.im + sca * ub.im;
+      }
+    }
+    {   // backward hop: U(x-mu)^H a, U(x-mu)^T b, B(x-mu)^T b, B(x-mu)^H a at x-mu
+      S ar[4], ai[4], br[4], bi[4];
+      load_site<S, S>(xt + sb * 4, ar, ai);
+      load_site<S, S>(xb + sb * 4, br, bi);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cx<S> t = {0, 0}, u = {0, 0}, tb = {0, 0}, ub = {0, 0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const cplx<S> l = Um[(int64_t)(4 * c + q) * V + sb];
+          const cplx<S> w = BSITE ? Bm[(int64_t)(4 * c + q) * V + sb] : Bm[4 * c + q];
+          mac_conj_a(t, l.x, l.y, ar[c], ai[c]);
+          mac(u, l.x, l.y, br[c], bi[c]);
+          mac(tb, w.x, w.y, br[c], bi[c]);
+          mac_conj_a(ub, w.x, w.y, ar[c], ai[c]);
+        }
+        top[q].re -= t.re + sca * tb.re; top[q].im -= t.im + sca * tb.im;
+        bot[q].re += sca * ub.re - u.re; bot[q].im += sca * ub.im - u.im;
+      }
+    }
+  }
+  // sum over the site's four lanes (adjacent lanes of one quad)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int o = 1; o <= 2; o <<= 1) {
+      top[q].re += __shfl_xor(top[q].re, o); top[q].im += __shfl_xor(top[q].im, o);
+      bot[q].re += __shfl_xor(bot[q].re, o); bot[q].im += __shfl_xor(bot[q].im, o);
+    }
+  }
+  cx<S> ot = top[0], ob = bot[0];   // row mu of this site
+#pragma unroll
+  for (int q = 1; q < 4; ++q)
+    if (mu == q) { ot = top[q]; ob = bot[q]; }
+  double are = 0.0, aim = 0.0;
+  if (active) {
+    cplx<S> t, b;
+    t.x = ot.re; t.y = ot.im;
+    b.x = ob.re; b.y = ob.im;
+    yc[s * 4 + mu] = t;
+    yc[h + s * 4 + mu] = b;
+    if (apart) {
+      const cplx<S> x0 = xt[s * 4 + mu], x1 = xb[s * 4 + mu];
+      are = (double)x0.x * t.x + (double)x0.y * t.y + (double)x1.x * b.x + (double)x1.y * b.y;
+      aim = (double)x0.x * t.y - (double)x0.y * t.x + (double)x1.x * b.y - (double)x1.y * b.x;
+    }
+  }
+  if (apart) {   // uniform over the grid
+    are = block_sum<kStencilThreads>(are, sh);
+    aim = block_sum<kStencilThreads>(aim, sh);
+    if (threadIdx.x == 0) {
+      apart[2 * blockIdx.x] = are;
+      apart[2 * blockIdx.x + 1] = aim;
+    }
+  }
 }
 
 // ||A x_c - lam_c x_c||^2 per block in FP64 (x stored as S).
@@ -297,6 +431,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(DenseArgs<S> a,
                                                                const cplx<S>* __restrict__ x,
                                                                cplx<S>* __restrict__ y, int64_t ld,
                                                                double* __restrict__ apart) {
+  if (a.skip && *a.skip != 0.0) return;   // uniform over the grid
   __shared__ double sh[kDenseThreads / 64];
   const int64_t r = (int64_t)blockIdx.x * (kDenseThreads / 64) + threadIdx.x / 64;
   const cplx<S>* xc = x + (int64_t)blockIdx.y * ld;
@@ -358,8 +493,19 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_resid(DenseArgs<S> a,
 
 }  // namespace
 
+// The apply runs four threads per site (k_stencil_apply4).
+// Four threads per site pay only where one thread per site leaves the device
+// short of wavefronts: measured faster for FP32 at 16^4 (23.7 us against
+// 31.8 us), slower for FP64 at 16^4 (44.1 against 33.5 us) and for both at
+// 32^4 (339 / 584 us against 282 / 490 us), where the longer per-thread work
+// already hides the latency.  es: bytes per complex element.
+static bool stencil_quad(int64_t V, int es) { return es == 8 && V <= (int64_t)1 << 17; }
+
 int stencil_resid_blocks(int64_t V) { return (int)((V + kStencilThreads - 1) / kStencilThreads); }
-int stencil_apply_blocks(int64_t V) { return stencil_resid_blocks(V); }
+int stencil_apply_blocks(int64_t V, int es) {
+  return stencil_quad(V, es) ? (int)((4 * V + kStencilThreads - 1) / kStencilThreads)
+                             : stencil_resid_blocks(V);
+}
 int dense_apply_blocks(int64_t h) { return (int)((h + kDenseThreads / 64 - 1) / (kDenseThreads / 64)); }
 int dense_resid_blocks(int64_t h) { return (int)((h + kDenseThreads / 64 - 1) / (kDenseThreads / 64)); }
 
@@ -367,6 +513,15 @@ template <typename S>
 hipError_t launch_stencil_apply(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
                                 int nrhs, double* apart, hipStream_t st) {
   if (apart && nrhs != 1) return hipErrorInvalidValue;
+  constexpr int es = (int)sizeof(cplx<S>);
+  if (stencil_quad(a.V, es)) {
+    dim3 grid4((unsigned)stencil_apply_blocks(a.V, es), (unsigned)nrhs);
+    if (a.b_per_site)
+      hipLaunchKernelGGL((k_stencil_apply4<S, true>), grid4, dim3(kStencilThreads), 0, st, a, x, y, ld, apart);
+    else
+      hipLaunchKernelGGL((k_stencil_apply4<S, false>), grid4, dim3(kStencilThreads), 0, st, a, x, y, ld, apart);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((a.V + kStencilThreads - 1) / kStencilThreads), (unsigned)nrhs);
   if (a.b_per_site)
     hipLaunchKernelGGL((k_stencil_apply<S, true>), grid, dim3(kStencilThreads), 0, st, a, x, y, ld, apart);

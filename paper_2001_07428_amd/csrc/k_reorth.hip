@@ -188,10 +188,11 @@ __global__ __launch_bounds__(kReorthThreads) void k_dots(const cplx<S>* __restri
   for (int i = threadIdx.x; i < 4 * ncol + 1; i += kReorthThreads) out[i] = acc[i];
 }
 
-// u -= sum_c v_c cv_c + w_c cw_c; each lane keeps the corrections of its
-// E*Q pairs in registers across the column loop (Q loads of 16 bytes per half
-// per column).  partial[blk] = ||u_new||^2.
-template <typename S, int E, int Q>
+// u -= sum_c v_c cv_c + w_c cw_c (JSYM; without it the W projection is
+// left out: standard Gram-Schmidt against V alone); each lane keeps the
+// corrections of its E*Q pairs in registers across the column loop (Q loads
+// of 16 bytes per half per column).  partial[blk] = ||u_new||^2.
+template <typename S, int E, int Q, bool JSYM>
 __global__ __launch_bounds__(kReorthThreads) void k_update(const cplx<S>* __restrict__ V,
                                                            int64_t ldv, int ncol,
                                                            cplx<S>* __restrict__ u, int64_t h,
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(kReorthThreads) void k_update(const cplx<S>* __rest
 #pragma unroll 4
   for (int c = 0; c < ncol; ++c) {
     const S cvr = (S)coef[4 * c + 0], cvi = (S)coef[4 * c + 1];
-    const S cwr = (S)coef[4 * c + 2], cwi = (S)coef[4 * c + 3];
+    const S cwr = JSYM ? (S)coef[4 * c + 2] : (S)0, cwi = JSYM ? (S)coef[4 * c + 3] : (S)0;
     const cplx<S>* vt = V + (int64_t)c * ldv;
     const cplx<S>* vb = vt + h;
 #pragma unroll
@@ -400,29 +401,35 @@ int reorth_dots_blocks(int64_t h) {
 
 template <typename S, int E, int Q>
 static void launch_update_q(unsigned grid, const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u,
-                            int64_t h, const double* coef, double* partial, hipStream_t st) {
-  hipLaunchKernelGGL((k_update<S, E, Q>), dim3(grid), dim3(kReorthThreads), 0, st, V, ldv, ncol, u,
-                     h, coef, partial);
+                            int64_t h, const double* coef, double* partial, hipStream_t st,
+                            bool jsym) {
+  if (jsym)
+    hipLaunchKernelGGL((k_update<S, E, Q, true>), dim3(grid), dim3(kReorthThreads), 0, st, V, ldv, ncol,
+                       u, h, coef, partial);
+  else
+    hipLaunchKernelGGL((k_update<S, E, Q, false>), dim3(grid), dim3(kReorthThreads), 0, st, V, ldv,
+                       ncol, u, h, coef, partial);
 }
 
 template <typename S>
 hipError_t launch_reorth_update(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
-                                const double* coef, double* partial, int nblk, hipStream_t st) {
+                                const double* coef, double* partial, int nblk, hipStream_t st,
+                                bool jsym) {
   const int E = elems_per_load(h, (int)sizeof(cplx<S>));
   const int ppl = update_ppl(h, E);
   const unsigned grid = (unsigned)((h + 256 * (int64_t)ppl - 1) / (256 * (int64_t)ppl));
   if ((int)grid != nblk) return hipErrorInvalidValue;
   if (E == 2) {
     if constexpr (sizeof(S) == 4) {
-      if (ppl == 8) launch_update_q<S, 2, 4>(grid, V, ldv, ncol, u, h, coef, partial, st);
-      else if (ppl == 4) launch_update_q<S, 2, 2>(grid, V, ldv, ncol, u, h, coef, partial, st);
-      else launch_update_q<S, 2, 1>(grid, V, ldv, ncol, u, h, coef, partial, st);
+      if (ppl == 8) launch_update_q<S, 2, 4>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
+      else if (ppl == 4) launch_update_q<S, 2, 2>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
+      else launch_update_q<S, 2, 1>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
     }
   } else {
-    if (ppl == 8) launch_update_q<S, 1, 8>(grid, V, ldv, ncol, u, h, coef, partial, st);
-    else if (ppl == 4) launch_update_q<S, 1, 4>(grid, V, ldv, ncol, u, h, coef, partial, st);
-    else if (ppl == 2) launch_update_q<S, 1, 2>(grid, V, ldv, ncol, u, h, coef, partial, st);
-    else launch_update_q<S, 1, 1>(grid, V, ldv, ncol, u, h, coef, partial, st);
+    if (ppl == 8) launch_update_q<S, 1, 8>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
+    else if (ppl == 4) launch_update_q<S, 1, 4>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
+    else if (ppl == 2) launch_update_q<S, 1, 2>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
+    else launch_update_q<S, 1, 1>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
   }
   return hipGetLastError();
 }
@@ -474,7 +481,7 @@ hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t l
                                             double*, int, hipStream_t, const double*, double,     \
                                             int);                                                 \
   template hipError_t launch_reorth_update<S>(const cplx<S>*, int64_t, int, cplx<S>*, int64_t,    \
-                                              const double*, double*, int, hipStream_t);          \
+                                              const double*, double*, int, hipStream_t, bool);    \
   template hipError_t launch_scale<S>(cplx<S>*, int64_t, double, hipStream_t);                    \
   template hipError_t launch_fill<S>(cplx<S>*, int64_t, double, hipStream_t);                     \
   template hipError_t launch_pair<S>(const cplx<S>*, int64_t, cplx<S>*, int64_t, int64_t, int,    \

@@ -15,6 +15,8 @@ eq. (blockform)):
   A12 = scale * sum_mu (B_mu T_mu - (B_mu T_mu)^T),
   with Haar-random unitary links U_mu(x) and complex normal B_mu.
   (T_mu a)(x) = a(x + mu_hat) with periodic wrap.
+* known spectrum (Case A, Sec. 4.1): A = U diag(Lambda, Lambda) U^H from a
+  J-orthonormal U = [X, J X^*] and Lambda uniform on (0, 1).
 
 Complex normal CN(0,1): real and imaginary parts i.i.d. N(0, 1/2), the real
 part drawn first as a whole array.
@@ -29,7 +31,7 @@ import numpy as np
 
 __all__ = [
     "cn", "dense_jsym", "batched_sizes", "batched_dense", "haar_unitary",
-    "stencil_links", "constant_links", "random_start", "STENCIL_DIAG",
+    "stencil_links", "constant_links", "random_start", "known_spectrum", "STENCIL_DIAG",
     "STENCIL_A12_SCALE",
 ]
 
@@ -130,3 +132,43 @@ def constant_links(seed: int, L, d: int = 4):
 def random_start(seed: int, n: int) -> np.ndarray:
     """CN(0,1) start vector of length n (not normalised)."""
     return cn(np.random.default_rng(seed), (n,))
+
+
+def known_spectrum(seed: int, n: int, lam=None):
+    """Known-spectrum Hermitian J-symmetric matrix (the Case A recipe, Sec. 4.1).
+
+    A = U diag(Lambda, Lambda) U^H with U = [X, J X^*] (eq. diagblockform),
+    Lambda uniform on (0, 1), the entries of X uniform on the square
+    (-1, 1) x (-1, 1) i, then made orthonormal column by column against the
+    previous columns and their partners J x^* (two Gram-Schmidt passes).
+    Returns (A11, A12, Lambda ascending, X)."""
+    assert n % 2 == 0
+    h = n // 2
+    rng = np.random.default_rng(seed)
+    if lam is None:
+        lam = rng.uniform(0.0, 1.0, h)
+    lam = np.asarray(lam, dtype=np.float64)
+
+    def partner(Y):   # J Y^* = [-conj(Y_bot); conj(Y_top)] for the columns of Y
+        return np.concatenate([-Y[h:].conj(), Y[:h].conj()], axis=0)
+
+    X = rng.uniform(-1.0, 1.0, (n, h)) + 1j * rng.uniform(-1.0, 1.0, (n, h))
+    Q = np.zeros((n, h), dtype=np.complex128)
+    Wq = np.zeros((n, h), dtype=np.complex128)   # partners of the columns of Q, kept alongside
+    for l in range(h):
+        x = X[:, l].copy()
+        for _ in range(2):
+            if l:
+                P = Q[:, :l]
+                W = Wq[:, :l]
+                x = x - P @ (P.conj().T @ x)
+                x = x - W @ (W.conj().T @ x)
+        Q[:, l] = x / np.linalg.norm(x)
+        Wq[:, l] = partner(Q[:, l:l + 1])[:, 0]
+    U = np.concatenate([Q, partner(Q)], axis=1)
+    A = (U * np.concatenate([lam, lam])[None, :]) @ U.conj().T
+    A = (A + A.conj().T) / 2.0
+    A11 = A[:h, :h].copy()
+    A12 = A[:h, h:].copy()
+    A12 = (A12 - A12.T) / 2.0
+    return A11, A12, np.sort(lam), Q

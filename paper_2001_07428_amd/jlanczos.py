@@ -47,6 +47,8 @@ class JlParams(ctypes.Structure):
         ("max_passes", ctypes.c_int32), ("min_passes", ctypes.c_int32), ("timing", ctypes.c_int32),
         ("trace_cap", ctypes.c_int32),
         ("trace_ab", ctypes.POINTER(ctypes.c_double)), ("verbose", ctypes.c_int32),
+        ("standard", ctypes.c_int32), ("invert", ctypes.c_int32), ("cg_maxit", ctypes.c_int32),
+        ("cg_tol", ctypes.c_double),
     ]
 
 
@@ -61,6 +63,9 @@ class JlStats(ctypes.Structure):
         ("n_update_launch", ctypes.c_int64), ("n_gemm_launch", ctypes.c_int64),
         ("bytes_matvec", ctypes.c_double), ("bytes_dots", ctypes.c_double),
         ("bytes_update", ctypes.c_double), ("flops_gemm", ctypes.c_double),
+        ("cg_iters", ctypes.c_int64), ("cg_max_iters", ctypes.c_int32),
+        ("cg_unconverged", ctypes.c_int32), ("t_cg", ctypes.c_double),
+        ("bytes_cg", ctypes.c_double),
     ]
 
     def to_dict(self):
@@ -261,8 +266,13 @@ class SolveResult:
 
 
 def _params(nev, m, mwin, tol, which, max_cycles, max_passes, timing, trace_buf, min_passes=0,
-            tol_relative=False, verbose=False):
+            tol_relative=False, verbose=False, standard=False, invert=False, cg_tol=0.0,
+            cg_maxit=0):
     p = JlParams()
+    p.standard = int(bool(standard))
+    p.invert = int(bool(invert))
+    p.cg_tol = float(cg_tol)
+    p.cg_maxit = int(cg_maxit)
     p.nev, p.m, p.mwin = nev, m, mwin
     p.which = JL_LARGEST if which in ("largest", JL_LARGEST) else JL_LOWEST
     p.tol = float(tol)
@@ -281,9 +291,10 @@ def _params(nev, m, mwin, tol, which, max_cycles, max_passes, timing, trace_buf,
     return p
 
 
-def jl_workspace_bytes(op: Operator, nev, m, mwin, tol=1e-10, which="lowest") -> int:
+def jl_workspace_bytes(op: Operator, nev, m, mwin, tol=1e-10, which="lowest", standard=False,
+                       invert=False) -> int:
     lib = load_library()
-    p = _params(nev, m, mwin, tol, which, 0, 0, 0, None)
+    p = _params(nev, m, mwin, tol, which, 0, 0, 0, None, standard=standard, invert=invert)
     nb = ctypes.c_size_t()
     _check(lib.jl_workspace_bytes(op.handle, ctypes.byref(p), ctypes.byref(nb)), op.ctx.handle)
     return nb.value
@@ -291,13 +302,17 @@ def jl_workspace_bytes(op: Operator, nev, m, mwin, tol=1e-10, which="lowest") ->
 
 def jl_solve(op: Operator, nev, m, mwin, tol, which="lowest", v1=None, max_cycles=0,
              max_passes=0, min_passes=0, timing=False, trace_cap=0, workspace=None,
-             tol_relative=False, verbose=False) -> SolveResult:
-    """Thick-restart J-Lanczos for the nev lowest (or largest) pairs."""
+             tol_relative=False, verbose=False, standard=False, invert=False, cg_tol=0.0,
+             cg_maxit=0) -> SolveResult:
+    """Thick-restart J-Lanczos for the nev lowest (or largest) pairs
+    (standard=True: the standard thick-restart Lanczos without the
+    J-restriction, which finds every pair twice; invert=True: the Lanczos
+    steps take A^-1 v_j by conjugate gradients, for positive definite A)."""
     torch = _torch()
     lib = load_library()
     trace_buf = np.zeros(2 * trace_cap) if trace_cap else None
     p = _params(nev, m, mwin, tol, which, max_cycles, max_passes, timing, trace_buf, min_passes,
-                tol_relative, verbose)
+                tol_relative, verbose, standard, invert, cg_tol, cg_maxit)
     nb = ctypes.c_size_t()
     _check(lib.jl_workspace_bytes(op.handle, ctypes.byref(p), ctypes.byref(nb)), op.ctx.handle)
     if workspace is None or workspace.numel() < nb.value:
@@ -423,7 +438,8 @@ class Batch:
     dtype); eigenvectors land in self.X[i] (nev, n_i)."""
 
     def __init__(self, ctx: Context, A11s, A12s, nev, m, mwin, tol, which="lowest",
-                 tol_relative=False, max_cycles=0, threads=0, blocks=0):
+                 tol_relative=False, max_cycles=0, threads=0, blocks=0, standard=False,
+                 invert=False):
         torch = _torch()
         lib = load_library()
         count = len(A11s)
@@ -442,7 +458,8 @@ class Batch:
             if hit is not None:
                 threads, blocks = hit
         self.threads, self.blocks = threads, blocks
-        self.p = _params(nev, m, mwin, tol, which, max_cycles, 0, 0, None, 0, tol_relative, False)
+        self.p = _params(nev, m, mwin, tol, which, max_cycles, 0, 0, None, 0, tol_relative, False,
+                         standard, invert)
         code = _dtype_code(A11s[0])
         nb = ctypes.c_size_t()
         n_c = self.n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))

@@ -41,6 +41,22 @@ def test_stencil_apply(ctx, L, mixed, b_per_site):
         assert _rel(Y[r], ref) < (2e-6 if mixed else 1e-14)
 
 
+@pytest.mark.parametrize("L", [(16, 16, 16, 16), (24, 24, 16, 16)])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_stencil_apply_large(ctx, L, mixed):
+    """The benchmark's 16^4 shape and one past the size where FP32 switches
+    from four threads per site to one (V = 147456 > 2^17), every output."""
+    from paper_2001_07428_amd import jlanczos as J
+    say("stencil_apply large", L, mixed)
+    U, B = inputs.stencil_links(4, L)
+    n = 2 * int(np.prod(L)) * 4
+    x = inputs.cn(np.random.default_rng(3), (1, n))
+    dt = cdt(mixed)
+    op = J.jl_op_create_stencil(ctx, L, to_dev(U, dt), to_dev(B, dt))
+    y = to_np(J.jl_op_apply(op, to_dev(x, dt)))[0]
+    assert _rel(y, jsym.stencil_apply(U, B, L, x[0])) < (2e-6 if mixed else 1e-14)
+
+
 @pytest.mark.parametrize("h", [100, 33, 1])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_dense_apply(ctx, h, mixed):

@@ -307,3 +307,19 @@ def test_table1_caseA_counts_in_published_range():
         assert np.abs(out["ev"] - lam[::-1][:10]).max() < 1e-12
         assert row[4] <= out["n_conv"] <= row[6]
         assert row[7] <= out["n_mv"] <= row[9]
+
+
+def test_standard_trlan_can_miss_partners():
+    """Case A, n=2000, seed 12, the ten largest: the standard method converges
+    before the second copy of any pair has entered its Krylov space (one
+    direction per eigenspace for a single start vector, up to rounding), and
+    returns ten distinct eigenvalues; the J-restricted method returns the five
+    largest pairs once each, which is what it is built to do (Sec. 3)."""
+    A11, A12, lam, _ = casea.known_spectrum(12, 2000)
+    A = jsym.dense_from_blocks(A11, A12)
+    std = trlan.trlan_jsym(lambda v: A @ v, 2000, 10, 20, 200, 1e-13, which="largest", jsym=False)
+    top = lam[::-1]
+    assert std["status"] == "ok"
+    assert np.abs(np.sort(std["ev"])[::-1] - top[:10]).max() < 1e-12
+    js = trlan.trlan_jsym(lambda v: A @ v, 2000, 5, 10, 100, 1e-13, which="largest")
+    assert js["status"] == "ok" and np.abs(js["ev"] - top[:5]).max() < 1e-12
