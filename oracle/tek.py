@@ -1,0 +1,172 @@
+"""The Case B operator of Sec. 4.2 (twisted Eguchi-Kawai Wilson-Dirac, A = D D^H
+with J = C gamma_5) written from its definition, FP64 NumPy.
+
+Test infrastructure only (see the package docstring).
+
+* gamma_1..gamma_4 are the explicit matrices of the appendix, gamma_5 =
+  gamma_4 gamma_1 gamma_2 gamma_3, C = gamma_4 gamma_2, J = C gamma_5.
+* The colour index a runs over the N^2 - 1 generators T_a of su(N) in the
+  generalised Gell-Mann basis, normalised to tr(T_a T_b) = delta_ab / 2, in
+  this order: the symmetric (E_jk + E_kj)/2 for j < k (row-major over the
+  strict upper triangle), then the antisymmetric (-i E_jk + i E_kj)/2 in the
+  same order, then the diagonal diag(1, ..., 1, -l, 0, ...)/sqrt(2 l (l+1))
+  for l = 1..N-1.
+* V_mu(a, b) = 2 tr(T_a U_mu T_b U_mu^H), the adjoint representation of
+  U_mu in SU(N): real and orthogonal, the properties Sec. 4.2 asks of V_mu.
+  The paper's V_mu come from a Monte Carlo ensemble that is not available;
+  Haar-random U_mu stand in for them.
+* D (eq. TEKWDmatrix) = I - kappa sum_mu [(I - gamma_mu) (x) V_mu +
+  (I + gamma_mu) (x) V_mu^T], index i = (alpha, a) with the spin alpha
+  slowest (Kronecker order spin (x) colour), and A = D D^H (eq. TEKmatrix).
+* dense_* build the matrices element by element from these definitions;
+  apply_* compute the same products through the identity (V psi)_a T_a =
+  U (psi_b T_b) U^H, which the tests pin to the dense form.
+* J = C gamma_5 is a signed permutation of the spins.  canonical_pairing
+  finds the reordering (with signs) of the index set that turns J (x) I into
+  the canonical [[0, -I], [I, 0]], the form the eigensolver works in.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# --------------------------------------------------------------- appendix
+G1 = np.array([[0, 0, 0, -1j], [0, 0, -1j, 0], [0, 1j, 0, 0], [1j, 0, 0, 0]])
+G2 = np.array([[0, 0, 0, -1], [0, 0, 1, 0], [0, 1, 0, 0], [-1, 0, 0, 0]], dtype=complex)
+G3 = np.array([[0, 0, -1j, 0], [0, 0, 0, 1j], [1j, 0, 0, 0], [0, -1j, 0, 0]])
+G4 = np.diag([1, 1, -1, -1]).astype(complex)
+GAMMA = [G1, G2, G3, G4]
+G5 = G4 @ G1 @ G2 @ G3
+C = G4 @ G2
+J4 = C @ G5
+
+
+def su_generators(N: int) -> np.ndarray:
+    """(N^2 - 1, N, N) complex: the generalised Gell-Mann basis in the order
+    of the module docstring."""
+    Ts = []
+    pairs = [(j, k) for j in range(N) for k in range(j + 1, N)]
+    for j, k in pairs:
+        T = np.zeros((N, N), dtype=complex)
+        T[j, k] = T[k, j] = 0.5
+        Ts.append(T)
+    for j, k in pairs:
+        T = np.zeros((N, N), dtype=complex)
+        T[j, k] = -0.5j
+        T[k, j] = 0.5j
+        Ts.append(T)
+    for l in range(1, N):
+        d = np.zeros(N)
+        d[:l] = 1.0
+        d[l] = -l
+        Ts.append(np.diag(d / np.sqrt(2.0 * l * (l + 1))).astype(complex))
+    return np.array(Ts)
+
+
+def haar_su(rng: np.random.Generator, N: int, count: int) -> np.ndarray:
+    """count Haar-random SU(N) matrices: the unitary factor of a complex
+    Gaussian matrix (QR with a positive real diagonal of R, Mezzadri 2007),
+    divided by an N-th root of its determinant."""
+    out = np.empty((count, N, N), dtype=complex)
+    for c in range(count):
+        Z = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) / np.sqrt(2.0)
+        Q, R = np.linalg.qr(Z)
+        d = np.diag(R)
+        Q = Q * (d / np.abs(d))[None, :]
+        det = np.linalg.det(Q)
+        out[c] = Q / det ** (1.0 / N)
+    return out
+
+
+def adjoint(U: np.ndarray, Ts: np.ndarray) -> np.ndarray:
+    """V(a, b) = 2 tr(T_a U T_b U^H), real (n_a x n_a)."""
+    W = np.einsum("ij,bjk,lk->bil", U, Ts, U.conj())       # U T_b U^H for every b
+    V = 2.0 * np.einsum("aji,bij->ab", Ts, W)               # 2 tr(T_a W_b)
+    return V.real
+
+
+def dense_D(Us: np.ndarray, kappa: float) -> np.ndarray:
+    """eq. (TEKWDmatrix) as a dense matrix, spin slowest."""
+    N = Us.shape[1]
+    Ts = su_generators(N)
+    na = N * N - 1
+    I4 = np.eye(4)
+    D = np.eye(4 * na, dtype=complex)
+    for mu in range(4):
+        V = adjoint(Us[mu], Ts)
+        D -= kappa * (np.kron(I4 - GAMMA[mu], V) + np.kron(I4 + GAMMA[mu], V.T))
+    return D
+
+
+def dense_A(Us: np.ndarray, kappa: float) -> np.ndarray:
+    """eq. (TEKmatrix): A = D D^H."""
+    D = dense_D(Us, kappa)
+    return D @ D.conj().T
+
+
+# ------------------------------------------------------- matrix-free form
+def coef_to_mat(psi: np.ndarray, N: int, Ts: np.ndarray | None = None) -> np.ndarray:
+    """X = sum_a psi_a T_a for psi of shape (..., N^2 - 1)."""
+    Ts = su_generators(N) if Ts is None else Ts
+    return np.einsum("...a,aij->...ij", psi, Ts)
+
+
+def mat_to_coef(X: np.ndarray, N: int, Ts: np.ndarray | None = None) -> np.ndarray:
+    """psi_a = 2 tr(T_a X) (the inverse of coef_to_mat on traceless X)."""
+    Ts = su_generators(N) if Ts is None else Ts
+    return 2.0 * np.einsum("aji,...ij->...a", Ts, X)
+
+
+def apply_D(Us: np.ndarray, kappa: float, psi: np.ndarray, Ts=None, dagger=False) -> np.ndarray:
+    """D psi (or D^H psi) for psi of length 4 (N^2 - 1), spin slowest, via
+    (V psi)_a T_a = U X U^H and (V^T psi)_a T_a = U^H X U."""
+    N = Us.shape[1]
+    Ts = su_generators(N) if Ts is None else Ts
+    na = N * N - 1
+    X = coef_to_mat(psi.reshape(4, na), N, Ts)               # X_beta
+    Y = X.copy()
+    for mu in range(4):
+        U = Us[mu]
+        F = U @ X @ U.conj().T                                # V_mu X_beta
+        B = U.conj().T @ X @ U                                # V_mu^T X_beta
+        Gm, Gp = np.eye(4) - GAMMA[mu], np.eye(4) + GAMMA[mu]
+        if dagger:   # D^H = I - kappa sum [(I - g)^H V^T + (I + g)^H V], g Hermitian
+            Y -= kappa * (np.einsum("ab,bij->aij", Gm, B) + np.einsum("ab,bij->aij", Gp, F))
+        else:
+            Y -= kappa * (np.einsum("ab,bij->aij", Gm, F) + np.einsum("ab,bij->aij", Gp, B))
+    return mat_to_coef(Y, N, Ts).reshape(-1)
+
+
+def apply_A(Us: np.ndarray, kappa: float, psi: np.ndarray, Ts=None) -> np.ndarray:
+    """A psi = D (D^H psi)."""
+    return apply_D(Us, kappa, apply_D(Us, kappa, psi, Ts, dagger=True), Ts)
+
+
+# --------------------------------------------------------- canonical form
+def canonical_pairing(Jm: np.ndarray):
+    """For a real signed permutation J with J^T = -J: (top, bottom, sign)
+    index arrays such that, with P e_top[k] = e_{top[k]} and P e_bot[k] =
+    sign[k] e_{bottom[k]}, P^T J P = [[0, -I], [I, 0]]."""
+    n = Jm.shape[0]
+    seen = np.zeros(n, bool)
+    top, bot, sgn = [], [], []
+    for i in range(n):
+        if seen[i]:
+            continue
+        j = int(np.flatnonzero(Jm[:, i])[0])      # J e_i = s e_j
+        s = Jm[j, i]
+        top.append(i)
+        bot.append(j)
+        sgn.append(s)
+        seen[i] = seen[j] = True
+    return np.array(top), np.array(bot), np.array(sgn, dtype=float)
+
+
+def canonical_matrix(Jm: np.ndarray) -> np.ndarray:
+    """The signed permutation P of canonical_pairing as a dense matrix."""
+    top, bot, sgn = canonical_pairing(Jm)
+    n = Jm.shape[0]
+    h = n // 2
+    P = np.zeros((n, n))
+    P[top, np.arange(h)] = 1.0
+    P[bot, h + np.arange(h)] = sgn
+    return P
