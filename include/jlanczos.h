@@ -99,6 +99,29 @@ jl_status jl_op_create_dense(jl_ctx ctx, int64_t n, const void* A11, const void*
 jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double diag,
                                double a12_scale, const void* U, const void* B,
                                int32_t b_per_site, jl_dtype dtype, jl_op* out);
+/* The Case B operator of Sec. 4.2: A = D D^H (eq. TEKmatrix) with the
+ * twisted Eguchi-Kawai Wilson-Dirac matrix of eq. (TEKWDmatrix),
+ *   D = I - kappa sum_mu [(I - gamma_mu) (x) V_mu + (I + gamma_mu) (x) V_mu^T],
+ * gamma_mu as in the appendix and V_mu the adjoint representation of U_mu:
+ * V_mu(a, b) = 2 tr(T_a U_mu T_b U_mu^H) over the generalised Gell-Mann
+ * basis T_a of su(N) (tr(T_a T_b) = delta_ab / 2; per spin N^2 - 1
+ * coefficients: the symmetric (E_jk + E_kj)/2 for j < k in row-major order
+ * of the strict upper triangle, the antisymmetric (-i E_jk + i E_kj)/2 in the
+ * same order, the diagonal diag(1, ..., 1, -l, 0, ...)/sqrt(2 l (l+1)) for
+ * l = 1..N-1).  n = 4 (N^2 - 1).  J = C gamma_5 pairs the spins (0, 1) and
+ * (2, 3), so vectors are laid out as [psi_0; psi_2; psi_1; psi_3] (spin
+ * blocks of N^2 - 1 coefficients), in which J is the canonical
+ * [[0, -I], [I, 0]] of every other call here.
+ *  U: device [4][N][N] row-major complex of the dtype (U_mu in SU(N); not
+ *     checked), copied at creation (not referenced afterwards).
+ * The operator owns 72 Np^2 complex elements of device scratch (Np = N
+ * rounded up to 64), so two applies of one operator must not run at the
+ * same time.  D is applied through (V_mu psi)_a T_a = U_mu X U_mu^H with
+ * X = psi_b T_b: 128 N x N complex products per apply of A, on the matrix
+ * cores in the storage precision.  Errors: JL_EINVAL for N outside 2..1024
+ * or NULL pointers, JL_ENOMEM when the scratch cannot be allocated. */
+jl_status jl_op_create_tek(jl_ctx ctx, int32_t N, double kappa, const void* U, jl_dtype dtype,
+                           jl_op* out);
 jl_status jl_op_destroy(jl_op op);
 /* Dimension n of the operator. */
 jl_status jl_op_dim(jl_op op, int64_t* n);
@@ -163,8 +186,9 @@ typedef struct {
   /* Invert mode: CG iterations over all solves (each one operator apply),
    * the most in one solve, solves stopped by cg_maxit, (with timing) the GPU
    * time of the CG solves [s], and their algorithmic bytes (per iteration
-   * one operator apply plus nine vector passes: x, r, p, q read and x, r
-   * written by the update, r, p read and p written by the direction step). */
+   * one operator apply, plus r read and p written by the direction step
+   * fused into it, plus x, r, p, q read and x, r written by the update:
+   * eight vector passes). */
   int64_t cg_iters;
   int32_t cg_max_iters;
   int32_t cg_unconverged;

@@ -29,6 +29,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from paper_2001_07428_amd.inputs import haar_su  # noqa: F401  (the links are an input)
+
 # --------------------------------------------------------------- appendix
 G1 = np.array([[0, 0, 0, -1j], [0, 0, -1j, 0], [0, 1j, 0, 0], [1j, 0, 0, 0]])
 G2 = np.array([[0, 0, 0, -1], [0, 0, 1, 0], [0, 1, 0, 0], [-1, 0, 0, 0]], dtype=complex)
@@ -60,21 +62,6 @@ def su_generators(N: int) -> np.ndarray:
         d[l] = -l
         Ts.append(np.diag(d / np.sqrt(2.0 * l * (l + 1))).astype(complex))
     return np.array(Ts)
-
-
-def haar_su(rng: np.random.Generator, N: int, count: int) -> np.ndarray:
-    """count Haar-random SU(N) matrices: the unitary factor of a complex
-    Gaussian matrix (QR with a positive real diagonal of R, Mezzadri 2007),
-    divided by an N-th root of its determinant."""
-    out = np.empty((count, N, N), dtype=complex)
-    for c in range(count):
-        Z = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) / np.sqrt(2.0)
-        Q, R = np.linalg.qr(Z)
-        d = np.diag(R)
-        Q = Q * (d / np.abs(d))[None, :]
-        det = np.linalg.det(Q)
-        out[c] = Q / det ** (1.0 / N)
-    return out
 
 
 def adjoint(U: np.ndarray, Ts: np.ndarray) -> np.ndarray:
@@ -116,13 +103,49 @@ def mat_to_coef(X: np.ndarray, N: int, Ts: np.ndarray | None = None) -> np.ndarr
     return 2.0 * np.einsum("aji,...ij->...a", Ts, X)
 
 
-def apply_D(Us: np.ndarray, kappa: float, psi: np.ndarray, Ts=None, dagger=False) -> np.ndarray:
+def coef_to_mat_entries(psi: np.ndarray, N: int) -> np.ndarray:
+    """coef_to_mat written out entry by entry, O(N^2) per vector: X_jk =
+    (s - i a)/2 and X_kj = (s + i a)/2 for the pair j < k, and the diagonal
+    X_jj = sum_{l > j} c_l - j c_j with c_l = d_l / sqrt(2 l (l + 1))."""
+    P = N * (N - 1) // 2
+    jj, kk = np.triu_indices(N, 1)
+    s, a, d = psi[..., :P], psi[..., P:2 * P], psi[..., 2 * P:]
+    X = np.zeros(psi.shape[:-1] + (N, N), dtype=complex)
+    X[..., jj, kk] = (s - 1j * a) / 2.0
+    X[..., kk, jj] = (s + 1j * a) / 2.0
+    l = np.arange(1, N)
+    c = d / np.sqrt(2.0 * l * (l + 1))
+    for j in range(N):
+        X[..., j, j] = c[..., j:].sum(axis=-1) - (j * c[..., j - 1] if j >= 1 else 0.0)
+    return X
+
+
+def mat_to_coef_entries(X: np.ndarray, N: int) -> np.ndarray:
+    """mat_to_coef written out entry by entry: s = X_jk + X_kj,
+    a = i (X_jk - X_kj), d_l = 2 (sum_{j < l} X_jj - l X_ll) / sqrt(2 l (l + 1))."""
+    jj, kk = np.triu_indices(N, 1)
+    s = X[..., jj, kk] + X[..., kk, jj]
+    a = 1j * (X[..., jj, kk] - X[..., kk, jj])
+    dg = np.diagonal(X, axis1=-2, axis2=-1)
+    l = np.arange(1, N)
+    csum = np.cumsum(dg, axis=-1)[..., :-1]                  # sum_{j < l} X_jj
+    d = 2.0 * (csum - l * dg[..., 1:]) / np.sqrt(2.0 * l * (l + 1))
+    return np.concatenate([s, a, d], axis=-1)
+
+
+def apply_D(Us: np.ndarray, kappa: float, psi: np.ndarray, Ts=None, dagger=False,
+            entries=False) -> np.ndarray:
     """D psi (or D^H psi) for psi of length 4 (N^2 - 1), spin slowest, via
-    (V psi)_a T_a = U X U^H and (V^T psi)_a T_a = U^H X U."""
+    (V psi)_a T_a = U X U^H and (V^T psi)_a T_a = U^H X U.  entries=True
+    converts with the O(N^2) entry formulas instead of the generator sums
+    (for large N, where the (N^2 - 1) N^2 generator array does not fit)."""
     N = Us.shape[1]
-    Ts = su_generators(N) if Ts is None else Ts
+    if not entries:
+        Ts = su_generators(N) if Ts is None else Ts
     na = N * N - 1
-    X = coef_to_mat(psi.reshape(4, na), N, Ts)               # X_beta
+    to_mat = (lambda p: coef_to_mat_entries(p, N)) if entries else (lambda p: coef_to_mat(p, N, Ts))
+    to_coef = (lambda x: mat_to_coef_entries(x, N)) if entries else (lambda x: mat_to_coef(x, N, Ts))
+    X = to_mat(psi.reshape(4, na))                            # X_beta
     Y = X.copy()
     for mu in range(4):
         U = Us[mu]
@@ -133,12 +156,33 @@ def apply_D(Us: np.ndarray, kappa: float, psi: np.ndarray, Ts=None, dagger=False
             Y -= kappa * (np.einsum("ab,bij->aij", Gm, B) + np.einsum("ab,bij->aij", Gp, F))
         else:
             Y -= kappa * (np.einsum("ab,bij->aij", Gm, F) + np.einsum("ab,bij->aij", Gp, B))
-    return mat_to_coef(Y, N, Ts).reshape(-1)
+    return to_coef(Y).reshape(-1)
 
 
-def apply_A(Us: np.ndarray, kappa: float, psi: np.ndarray, Ts=None) -> np.ndarray:
+def apply_A(Us: np.ndarray, kappa: float, psi: np.ndarray, Ts=None, entries=False) -> np.ndarray:
     """A psi = D (D^H psi)."""
-    return apply_D(Us, kappa, apply_D(Us, kappa, psi, Ts, dagger=True), Ts)
+    return apply_D(Us, kappa, apply_D(Us, kappa, psi, Ts, dagger=True, entries=entries), Ts,
+                   entries=entries)
+
+
+# spin block of the canonical layout holding physical spin alpha (and back):
+# J = C gamma_5 pairs spins (0, 1) and (2, 3) with sign +1, so the canonical
+# vector is [psi_0; psi_2 | psi_1; psi_3] (canonical_pairing of J (x) I)
+CANON_BLOCK = (0, 2, 1, 3)
+
+
+def to_canonical(psi: np.ndarray, na: int) -> np.ndarray:
+    """Physical (spin slowest) -> canonical [top; bottom] layout."""
+    blocks = psi.reshape(4, na)
+    out = np.empty_like(blocks)
+    for alpha in range(4):
+        out[CANON_BLOCK[alpha]] = blocks[alpha]
+    return out.reshape(-1)
+
+
+def from_canonical(v: np.ndarray, na: int) -> np.ndarray:
+    blocks = v.reshape(4, na)
+    return np.stack([blocks[CANON_BLOCK[alpha]] for alpha in range(4)]).reshape(-1)
 
 
 # --------------------------------------------------------- canonical form

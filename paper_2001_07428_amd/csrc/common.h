@@ -48,6 +48,13 @@ template <typename S>
 hipError_t launch_stencil_apply(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
                                 int nrhs, double* apart, hipStream_t st);
 int stencil_apply_blocks(int64_t V, int es);   // es: bytes per complex element
+// One CG direction step fused into the apply (single column): the operand is
+// p = r + beta p_old (beta = *beta on the device), y = A p, p is stored to
+// pnew, and apart receives the partials of p^H y as above.
+template <typename S>
+hipError_t launch_stencil_apply_dir(const StencilArgs<S>& a, const cplx<S>* r, const cplx<S>* pold,
+                                    const double* beta, cplx<S>* pnew, cplx<S>* y, double* apart,
+                                    hipStream_t st);
 // Per-block partial sums of ||A x_c - lam_c x_c||^2 (FP64 compute) for ncols
 // columns x_c = X + cols[c]*ldx (cols, lam on the device); partial layout
 // [blk][c]; *nblk = blocks per column.
@@ -73,11 +80,56 @@ template <typename S>
 hipError_t launch_dense_apply(const DenseArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ldv,
                               int nrhs, double* apart, hipStream_t st);
 int dense_apply_blocks(int64_t h);
+template <typename S>   // as launch_stencil_apply_dir
+hipError_t launch_dense_apply_dir(const DenseArgs<S>& a, const cplx<S>* r, const cplx<S>* pold,
+                                  const double* beta, cplx<S>* pnew, cplx<S>* y, double* apart,
+                                  hipStream_t st);
 template <typename S>
 hipError_t launch_dense_resid(const DenseArgs<S>& a, const cplx<S>* X, int64_t ldx,
                               const int* cols, const double* lam, int ncols, double* partial,
                               int* nblk, hipStream_t st);
 int dense_resid_blocks(int64_t h);
+
+// Case B operator (A = D D^H, twisted Eguchi-Kawai Wilson-Dirac, Sec. 4.2)
+// in the canonical layout [psi_0; psi_2 | psi_1; psi_3] of su(N)
+// coefficients.  All matrices Np x Np row-major (Np = N rounded up to 64),
+// zero outside N x N.
+template <typename S> struct ZJob {   // C = op(A) op(B); op 0 = as is, 1 = conjugate transpose
+  const cplx<S>* A;
+  const cplx<S>* B;
+  cplx<S>* C;
+  int opA, opB;
+};
+template <typename S> struct TekArgs {
+  int N, Np;
+  int64_t na;                 // N^2 - 1 coefficients per spin
+  double kappa;
+  cplx<S>* X;                 // [4][Np][Np] spin matrices (scratch)
+  cplx<S>* FB;                // [32][Np][Np]: U X_b U^H for (mu, b), then U^H X_b U
+  double* zd;                 // [4][N] complex diagonal scratch (FP64)
+  const ZJob<S>* jobs1;       // 32 first products: U X_b, U^H X_b
+  const ZJob<S>* jobs2;       // 32 second products: (U X_b) U^H, (U^H X_b) U
+  const double* skip;         // as StencilArgs::skip
+};
+template <typename S> struct TekSrc {   // operand x, or p = r + beta x stored to pnew
+  const cplx<S>* x;
+  const cplx<S>* r;
+  const double* beta;
+  cplx<S>* pnew;
+};
+int tek_apply_blocks(int N);   // partial-sum blocks of one apply (apart / residual)
+template <typename S>
+hipError_t launch_tek_apply(const TekArgs<S>& a, const cplx<S>* x, cplx<S>* y, double* apart,
+                            hipStream_t st);
+template <typename S>   // as launch_stencil_apply_dir
+hipError_t launch_tek_apply_dir(const TekArgs<S>& a, const cplx<S>* r, const cplx<S>* pold,
+                                const double* beta, cplx<S>* pnew, cplx<S>* y, double* apart,
+                                hipStream_t st);
+// As launch_stencil_resid, with the column indices on the host (hcols).
+template <typename S>
+hipError_t launch_tek_resid(const TekArgs<S>& a, const cplx<S>* X, int64_t ldx, const int* hcols,
+                            const double* lam, int ncols, double* partial, int* nblk,
+                            hipStream_t st);
 
 // ------------------------------------------------------- reorthogonalisation
 // Basis V: ncol columns of length n = 2h, column stride ldv.
@@ -127,13 +179,14 @@ enum CgSlot {
 // CG_DONE: 0 running, 1 stopped (converged or maxit), 2 p^H A p <= 0.
 // CG_CNT: the fused step's finished-block counter (an unsigned in the slot).
 int cg_blocks(int64_t n);   // partial sums written by the CG vector kernels
-// x = 0, r = p = b; starts the solve of A x = b (stop at ||r|| <= tol ||b||).
+// x = 0, r = b, p = 0, beta = 0 (so the first fused apply forms p = b);
+// starts the solve of A x = b (stop at ||r|| <= tol ||b||).
 template <typename S>
 hipError_t launch_cg_init(const cplx<S>* b, cplx<S>* x, cplx<S>* r, cplx<S>* p, int64_t n,
                           double* part, double* cs, double tol, int maxit, hipStream_t st);
 // The rest of one iteration after q = A p (apart: the apply's napply
-// partials of p^H q): alpha, x and r, beta and the stop test (one launch),
-// then p (a second).
+// partials of p^H q): alpha, x and r, beta and the stop test, in one launch.
+// The next direction p = r + beta p is formed by the next apply.
 template <typename S>
 hipError_t launch_cg_step(cplx<S>* x, cplx<S>* r, cplx<S>* p, const cplx<S>* q, int64_t n,
                           const double* apart, int napply, double* part, double* cs,

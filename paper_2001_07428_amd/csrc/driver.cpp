@@ -30,7 +30,7 @@ namespace {
 
 thread_local std::string g_thread_err;
 
-enum OpKind { OP_DENSE = 1, OP_STENCIL = 2 };
+enum OpKind { OP_DENSE = 1, OP_STENCIL = 2, OP_TEK = 3 };
 
 }  // namespace
 
@@ -43,7 +43,9 @@ struct jl_op_s {
   StencilArgs<double> sd{};
   DenseArgs<float> df{};
   DenseArgs<double> dd{};
-  void* links = nullptr;   // stencil: owned site-fastest copy of U (and per-site B)
+  TekArgs<float> tf{};
+  TekArgs<double> td{};
+  void* links = nullptr;   // owned device memory: stencil links, or the TEK links and scratch
   ~jl_op_s() {
     if (links) (void)hipFree(links);
   }
@@ -169,10 +171,12 @@ template <typename S> struct OpView;
 template <> struct OpView<float> {
   static const StencilArgs<float>& st(const jl_op_s* o) { return o->sf; }
   static const DenseArgs<float>& de(const jl_op_s* o) { return o->df; }
+  static const TekArgs<float>& tk(const jl_op_s* o) { return o->tf; }
 };
 template <> struct OpView<double> {
   static const StencilArgs<double>& st(const jl_op_s* o) { return o->sd; }
   static const DenseArgs<double>& de(const jl_op_s* o) { return o->dd; }
+  static const TekArgs<double>& tk(const jl_op_s* o) { return o->td; }
 };
 
 template <typename S>
@@ -180,43 +184,66 @@ hipError_t op_apply(const jl_op_s* op, const cplx<S>* x, cplx<S>* y, int64_t ld,
                     double* apart, hipStream_t st) {
   if (op->kind == OP_STENCIL)
     return launch_stencil_apply<S>(OpView<S>::st(op), x, y, ld, nrhs, apart, st);
+  if (op->kind == OP_TEK) {   // one column at a time (the products are batched inside)
+    if (apart && nrhs != 1) return hipErrorInvalidValue;
+    for (int r = 0; r < nrhs; ++r) {
+      const hipError_t e = launch_tek_apply<S>(OpView<S>::tk(op), x + (int64_t)r * ld,
+                                               y + (int64_t)r * ld, apart, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   return launch_dense_apply<S>(OpView<S>::de(op), x, y, ld, nrhs, apart, st);
 }
 
-// y = A x (one column) returning at once while *skip != 0 (CG launches
-// queued past convergence).
+// One CG apply: p = r + beta p_old formed on the fly and stored to pnew,
+// q = A p with the partials of p^H q; returns at once while *skip != 0 (CG
+// launches queued past convergence).
 template <typename S>
-hipError_t op_apply_skip(const jl_op_s* op, const double* skip, const cplx<S>* x, cplx<S>* y,
-                         double* apart, hipStream_t st) {
+hipError_t op_apply_cg(const jl_op_s* op, const double* skip, const cplx<S>* r,
+                       const cplx<S>* pold, const double* beta, cplx<S>* pnew, cplx<S>* q,
+                       double* apart, hipStream_t st) {
   if (op->kind == OP_STENCIL) {
     StencilArgs<S> a = OpView<S>::st(op);
     a.skip = skip;
-    return launch_stencil_apply<S>(a, x, y, op->n, 1, apart, st);
+    return launch_stencil_apply_dir<S>(a, r, pold, beta, pnew, q, apart, st);
+  }
+  if (op->kind == OP_TEK) {
+    TekArgs<S> a = OpView<S>::tk(op);
+    a.skip = skip;
+    return launch_tek_apply_dir<S>(a, r, pold, beta, pnew, q, apart, st);
   }
   DenseArgs<S> a = OpView<S>::de(op);
   a.skip = skip;
-  return launch_dense_apply<S>(a, x, y, op->n, 1, apart, st);
+  return launch_dense_apply_dir<S>(a, r, pold, beta, pnew, q, apart, st);
 }
 
 template <typename S>
 hipError_t op_resid(const jl_op_s* op, const cplx<S>* X, int64_t ldx, const int* cols,
-                    const double* lam, int ncols, double* partial, int* nblk, hipStream_t st) {
+                    const int* hcols, const double* lam, int ncols, double* partial, int* nblk,
+                    hipStream_t st) {
+  if (op->kind == OP_TEK)
+    return launch_tek_resid<S>(OpView<S>::tk(op), X, ldx, hcols, lam, ncols, partial, nblk, st);
   if (op->kind == OP_STENCIL)
     return launch_stencil_resid<S>(OpView<S>::st(op), X, ldx, cols, lam, ncols, partial, nblk, st);
   return launch_dense_resid<S>(OpView<S>::de(op), X, ldx, cols, lam, ncols, partial, nblk, st);
 }
 
 int op_apply_blocks(const jl_op_s* op) {
+  if (op->kind == OP_TEK) return tek_apply_blocks(op->tf.N);
   return op->kind == OP_STENCIL ? stencil_apply_blocks(op->n / 8, op->dtype == JL_C64 ? 8 : 16)
                                  : dense_apply_blocks(op->n / 2);
 }
 
 int op_resid_blocks(const jl_op_s* op) {
+  if (op->kind == OP_TEK) return tek_apply_blocks(op->tf.N);
   return op->kind == OP_STENCIL ? stencil_resid_blocks(op->n / 8) : dense_resid_blocks(op->n / 2);
 }
 
-// Algorithmic bytes of one operator apply (storage element size es).
+// Algorithmic bytes of one operator apply (storage element size es); for
+// the TEK operator (bound by its matrix products) the vectors and links only.
 double op_bytes(const jl_op_s* op, int es) {
+  if (op->kind == OP_TEK) return es * (2.0 * (double)op->n + 4.0 * op->tf.N * (double)op->tf.N);
   if (op->kind == OP_STENCIL) {
     const double V = (double)(op->n / 8);
     const int bps = op->dtype == JL_C64 ? op->sf.b_per_site : op->sd.b_per_site;
@@ -229,7 +256,7 @@ double op_bytes(const jl_op_s* op, int es) {
 // ----------------------------------------------------------- workspace layout
 struct Layout {
   size_t V[2], apart, dots_part, upd_part, coef, scal, Tdev, ritz, lam_s, Zs, zlast, res_part,
-      res_out, res_lam, res_cols, cg_vec[4], cg_part, cg_s, total;
+      res_out, res_lam, res_cols, cg_vec[5], cg_part, cg_s, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -261,8 +288,8 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   L.res_out = take(sizeof(double) * p->nev);
   L.res_lam = take(sizeof(double) * p->nev);
   L.res_cols = take(sizeof(int) * p->nev);
-  if (p->invert) {   // CG: x, r, p, q; partial sums; device scalars
-    for (int i = 0; i < 4; ++i) L.cg_vec[i] = take((size_t)n * es);
+  if (p->invert) {   // CG: x, r, q, two directions; partial sums; device scalars
+    for (int i = 0; i < 5; ++i) L.cg_vec[i] = take((size_t)n * es);
     L.cg_part = take(sizeof(double) * 2 * (size_t)cg_blocks(n));
     L.cg_s = take(sizeof(double) * CG_NSLOTS);
   }
@@ -407,11 +434,11 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   double* res_dev = reinterpret_cast<double*>(base + L.res_out);
   double* res_lam = reinterpret_cast<double*>(base + L.res_lam);
   int* res_cols = reinterpret_cast<int*>(base + L.res_cols);
-  cplx<S>* cgv[4] = {nullptr, nullptr, nullptr, nullptr};   // x, r, p, q
+  cplx<S>* cgv[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // x, r, q, p (two)
   double* cg_part = nullptr;
   double* cgs = nullptr;
   if (invert) {
-    for (int i = 0; i < 4; ++i) cgv[i] = reinterpret_cast<cplx<S>*>(base + L.cg_vec[i]);
+    for (int i = 0; i < 5; ++i) cgv[i] = reinterpret_cast<cplx<S>*>(base + L.cg_vec[i]);
     cg_part = reinterpret_cast<double*>(base + L.cg_part);
     cgs = reinterpret_cast<double*>(base + L.cg_s);
   }
@@ -474,16 +501,20 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   auto cg_solve = [&](const cplx<S>* b, cplx<S>* u) -> jl_status {
     cplx<S>* const x = cgv[0];
     cplx<S>* const r = cgv[1];
-    cplx<S>* const p = cgv[2];
-    cplx<S>* const q = cgv[3];
+    cplx<S>* const q = cgv[2];
+    cplx<S>* const pb[2] = {cgv[3], cgv[4]};   // iteration c reads pb[c % 2], writes the other
     tm.start(Timer::CG);
-    JL_HIP(ctx, launch_cg_init<S>(b, x, r, p, n, cg_part, cgs, cg_tol, cg_maxit, st));
+    JL_HIP(ctx, launch_cg_init<S>(b, x, r, pb[0], n, cg_part, cgs, cg_tol, cg_maxit, st));
     int issued = 0;
+    // batches are multiples of kCgChunk (even), so iteration c of a batch
+    // has the parity of its global index
     int batch = std::max(kCgChunk, cg_prev - cg_prev % kCgChunk);
     for (;;) {
       for (int c = 0; c < batch; ++c) {
-        JL_HIP(ctx, op_apply_skip<S>(op, cgs + CG_DONE, p, q, apart, st));
-        JL_HIP(ctx, launch_cg_step<S>(x, r, p, q, n, apart, napply, cg_part, cgs, st));
+        cplx<S>* const pold = pb[c & 1];
+        cplx<S>* const pnew = pb[(c + 1) & 1];
+        JL_HIP(ctx, op_apply_cg<S>(op, cgs + CG_DONE, r, pold, cgs + CG_BETA, pnew, q, apart, st));
+        JL_HIP(ctx, launch_cg_step<S>(x, r, pnew, q, n, apart, napply, cg_part, cgs, st));
       }
       issued += batch;
       JL_HIP(ctx, hipMemcpyAsync(h_cg, cgs, sizeof(double) * CG_NSLOTS, hipMemcpyDeviceToHost, st));
@@ -502,7 +533,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     if (!(h_cg[CG_RR] <= h_cg[CG_THR])) S_.cg_unconverged++;
     S_.n_matvec_launch += it;
     S_.bytes_matvec += it * op_bytes(op, es);
-    S_.bytes_cg += it * (op_bytes(op, es) + 9.0 * (double)n * es);
+    S_.bytes_cg += it * (op_bytes(op, es) + 8.0 * (double)n * es);
     cg_prev = it;
     JL_HIP(ctx, launch_cg_finish<S>(x, u, b, n, cg_part, st));
     JL_HIP(ctx, launch_reduce_cols(cg_part, ncgb, 2, 2, scal, st));
@@ -660,8 +691,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       double c = 0.0;
       if (!broke) {   // after a breakdown there is no v_{m+1} (the couplings are zero)
         tm.start(Timer::RESID);
-        JL_HIP(ctx, op_apply<S>(op, V + (int64_t)meff * ldv, cgv[3], ldv, 1, nullptr, st));
-        JL_HIP(ctx, launch_norm2<S>(cgv[3], n, cg_part, st));
+        JL_HIP(ctx, op_apply<S>(op, V + (int64_t)meff * ldv, cgv[2], ldv, 1, nullptr, st));
+        JL_HIP(ctx, launch_norm2<S>(cgv[2], n, cg_part, st));
         JL_HIP(ctx, launch_reduce_cols(cg_part, ncgb, 1, 1, scal + 4, st));
         JL_HIP(ctx, hipMemcpyAsync(hs + 4, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
         tm.stop();
@@ -700,7 +731,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       JL_HIP(ctx, hipMemcpyAsync(res_cols, h_rcols, sizeof(int) * ncand, hipMemcpyHostToDevice, st));
       JL_HIP(ctx, hipMemcpyAsync(res_lam, h_rlam, sizeof(double) * ncand, hipMemcpyHostToDevice, st));
       int nrb = 0;
-      JL_HIP(ctx, op_resid<S>(op, Vn, ldv, res_cols, res_lam, ncand, res_part, &nrb, st));
+      JL_HIP(ctx, op_resid<S>(op, Vn, ldv, res_cols, h_rcols, res_lam, ncand, res_part, &nrb, st));
       JL_HIP(ctx, launch_reduce_cols(res_part, nrb, ncand, ncand, res_dev, st));
       JL_HIP(ctx, hipMemcpyAsync(h_res, res_dev, sizeof(double) * ncand, hipMemcpyDeviceToHost, st));
       tm.stop();
@@ -774,6 +805,51 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   S_.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count();
   if (stats) *stats = S_;
   return status;
+}
+
+}  // namespace
+
+namespace {
+
+template <typename S>
+TekArgs<S> tek_layout(char* base, int N, int Np, double kappa, size_t* total) {
+  // [U 4 | X 4 | P 32 | FB 32] matrices, then the diagonal scratch, then the job tables
+  const size_t M = (size_t)Np * Np * sizeof(cplx<S>);
+  TekArgs<S> a{};
+  a.N = N;
+  a.Np = Np;
+  a.na = (int64_t)N * N - 1;
+  a.kappa = kappa;
+  cplx<S>* U = reinterpret_cast<cplx<S>*>(base);
+  a.X = reinterpret_cast<cplx<S>*>(base + 4 * M);
+  a.FB = reinterpret_cast<cplx<S>*>(base + 40 * M);
+  a.zd = reinterpret_cast<double*>(base + 72 * M);
+  const size_t jobs_off = 72 * M + ((8 * (size_t)N * sizeof(double) + 255) & ~size_t(255));
+  a.jobs1 = reinterpret_cast<const ZJob<S>*>(base + jobs_off);
+  a.jobs2 = a.jobs1 + 32;
+  *total = jobs_off + 64 * sizeof(ZJob<S>);
+  (void)U;
+  return a;
+}
+
+// Host copies of the 64 product jobs (pointers into the device block).
+template <typename S>
+std::vector<ZJob<S>> tek_jobs(char* base, int Np) {
+  const size_t M = (size_t)Np * Np;
+  cplx<S>* U = reinterpret_cast<cplx<S>*>(base);
+  cplx<S>* X = U + 4 * M;
+  cplx<S>* P = U + 8 * M;
+  cplx<S>* FB = U + 40 * M;
+  std::vector<ZJob<S>> j(64);
+  for (int mu = 0; mu < 4; ++mu)
+    for (int b = 0; b < 4; ++b) {
+      const int q = mu * 4 + b;
+      j[q] = ZJob<S>{U + mu * M, X + b * M, P + q * M, 0, 0};                    // U X_b
+      j[16 + q] = ZJob<S>{U + mu * M, X + b * M, P + (16 + q) * M, 1, 0};        // U^H X_b
+      j[32 + q] = ZJob<S>{P + q * M, U + mu * M, FB + q * M, 0, 1};              // (U X_b) U^H
+      j[48 + q] = ZJob<S>{P + (16 + q) * M, U + mu * M, FB + (16 + q) * M, 0, 0};  // (U^H X_b) U
+    }
+  return j;
 }
 
 }  // namespace
@@ -895,6 +971,60 @@ jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double
   sd.B = reinterpret_cast<const double2*>(bb);
   o->sf = sf;
   o->sd = sd;
+  *out = o;
+  return JL_OK;
+}
+
+jl_status jl_op_create_tek(jl_ctx ctx, int32_t N, double kappa, const void* U, jl_dtype dtype,
+                           jl_op* out) {
+  if (!ctx || !out) return set_err(ctx, JL_EINVAL, "ctx and out are required");
+  if (N < 2 || N > 1024) return set_err(ctx, JL_EINVAL, "N must be in 2..1024 (got %d)", N);
+  if (!U) return set_err(ctx, JL_EINVAL, "U is required");
+  if (dtype != JL_C64 && dtype != JL_C128) return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
+  const int Np = (N + 63) / 64 * 64;
+  const size_t es = dtype == JL_C64 ? sizeof(float2) : sizeof(double2);
+  size_t total = 0;
+  if (dtype == JL_C64) (void)tek_layout<float>(nullptr, N, Np, kappa, &total);
+  else (void)tek_layout<double>(nullptr, N, Np, kappa, &total);
+  DeviceGuard g(ctx->device);
+  void* mem = nullptr;
+  hipError_t e = hipMalloc(&mem, total);
+  if (e != hipSuccess)
+    return set_err(ctx, JL_ENOMEM, "TEK operator memory (%zu bytes): %s", total, hipGetErrorString(e));
+  char* base = static_cast<char*>(mem);
+  // zero everything (the padding must stay zero), then the links into the padded rows
+  e = hipMemsetAsync(mem, 0, total, ctx->stream);
+  for (int mu = 0; mu < 4 && e == hipSuccess; ++mu)
+    e = hipMemcpy2DAsync(base + (size_t)mu * Np * Np * es, (size_t)Np * es,
+                         static_cast<const char*>(U) + (size_t)mu * N * N * es, (size_t)N * es,
+                         (size_t)N * es, (size_t)N, hipMemcpyDeviceToDevice, ctx->stream);
+  jl_op o = new jl_op_s();
+  o->tf = tek_layout<float>(base, N, Np, kappa, &total);
+  o->td = tek_layout<double>(base, N, Np, kappa, &total);
+  const size_t jobs_bytes = 64 * (dtype == JL_C64 ? sizeof(ZJob<float>) : sizeof(ZJob<double>));
+  std::vector<ZJob<float>> jf;
+  std::vector<ZJob<double>> jd;
+  const void* jobs_host = nullptr;
+  if (dtype == JL_C64) {
+    jf = tek_jobs<float>(base, Np);
+    jobs_host = jf.data();
+  } else {
+    jd = tek_jobs<double>(base, Np);
+    jobs_host = jd.data();
+  }
+  void* jobs_dev = dtype == JL_C64 ? (void*)o->tf.jobs1 : (void*)o->td.jobs1;
+  if (e == hipSuccess) e = hipMemcpyAsync(jobs_dev, jobs_host, jobs_bytes, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    delete o;
+    (void)hipFree(mem);
+    return set_err(ctx, JL_EHIP, "TEK operator set-up: %s", hipGetErrorString(e));
+  }
+  o->ctx = ctx;
+  o->kind = OP_TEK;
+  o->dtype = dtype;
+  o->n = 4 * ((int64_t)N * N - 1);
+  o->links = mem;
   *out = o;
   return JL_OK;
 }

@@ -6,11 +6,12 @@
 // stopping when r^H r <= cg_tol^2 b^H b or after maxit iterations.
 //
 // Every scalar lives on the device (CgSlot), so a whole run of iterations
-// is queued without host round trips.  One iteration is three launches: the
-// operator apply (which leaves the block partials of p^H A p), the fused
-// alpha / x, r update / beta step, and the direction update.  The fused step
-// sets the done flag on convergence, after which every queued kernel (the
-// operator applies too, through their skip pointer) returns at once.
+// is queued without host round trips.  One iteration is two launches: the
+// operator apply, which forms the direction p = r + beta p_old on the fly,
+// stores it (into the other of two direction buffers) and leaves the block
+// partials of p^H A p; and the fused alpha / x, r update / beta step.  That
+// step sets the done flag on convergence, after which every queued kernel
+// (the operator applies too, through their skip pointer) returns at once.
 //
 // Vectors are n complex elements of storage type S, interleaved (re, im),
 // 16-byte aligned; the vector kernels move 16 bytes per thread and step
@@ -68,7 +69,7 @@ __device__ __forceinline__ double cg_reduce(const double* __restrict__ part, int
 
 __device__ __forceinline__ bool cg_done(const double* cs) { return cs[CG_DONE] != 0.0; }
 
-// x = 0, r = b, p = b; part[blk] = block partial of b^H b.
+// x = 0, r = b, p = 0; part[blk] = block partial of b^H b.
 template <typename S>
 __global__ __launch_bounds__(kCgThreads) void k_cg_init(const S* __restrict__ b, S* __restrict__ x,
                                                         S* __restrict__ r, S* __restrict__ p,
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_init(const S* __restrict__ b,
     }
     st16<S>(x + c * K, z);
     st16<S>(r + c * K, v);
-    st16<S>(p + c * K, v);
+    st16<S>(p + c * K, z);
   }
   acc = cg_block_sum(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
@@ -105,6 +106,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_start(const double* __restric
     cs[CG_BB] = bb;
     cs[CG_THR] = tol2 * bb;
     cs[CG_ITERS] = 0.0;
+    cs[CG_BETA] = 0.0;   // the first direction is r itself
     cs[CG_MAXIT] = (double)maxit;
     cs[CG_DONE] = (bb <= tol2 * bb || maxit <= 0) ? 1.0 : 0.0;   // b = 0 needs no iteration
   }
@@ -114,7 +116,8 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_start(const double* __restric
 // launch: every block sums the apply partials of p^H q itself (the same
 // order everywhere, so all blocks hold the same alpha), and the last block to
 // finish (counted on cnt) sums the r^H r partials and updates the scalars.
-// The partials are read with device-scope loads, past any stale L1 line.
+// The partials are written and read with agent-scope accesses, which go past
+// the caches that are not coherent across the chip.
 template <typename S>
 __global__ __launch_bounds__(kCgThreads) void k_cg_update_fused(
     S* __restrict__ x, S* __restrict__ r, const S* __restrict__ p, const S* __restrict__ q,
@@ -153,14 +156,18 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_update_fused(
   }
   acc = cg_block_sum(acc, sh);
   if (threadIdx.x == 0) {
+    // The partial is an agent-scope store, which bypasses the per-XCD L2
+    // (not coherent across XCDs); waiting for it to complete before the
+    // counter moves is all the last block needs to see it.  A release fence
+    // here would write back every dirty line of this XCD's L2 (measured: the
+    // kernel took 43 us instead of a few).
     __hip_atomic_store(&part[blockIdx.x], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     const unsigned done_blocks = atomicAdd(cnt, 1u);
     last = done_blocks == gridDim.x - 1;
   }
   __syncthreads();
   if (!last) return;   // uniform within the block
-  __threadfence();
   double s = 0.0;
   for (int b = threadIdx.x; b < (int)gridDim.x; b += kCgThreads)
     s += __hip_atomic_load(&part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -173,24 +180,6 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_update_fused(
     cs[CG_ITERS] = it;
     if (rr <= cs[CG_THR] || it >= cs[CG_MAXIT] || !(rr == rr)) cs[CG_DONE] = 1.0;
     *cnt = 0u;   // ready for the next iteration's launch
-  }
-}
-
-// p = r + beta p.
-template <typename S>
-__global__ __launch_bounds__(kCgThreads) void k_cg_dir(const S* __restrict__ r, S* __restrict__ p,
-                                                       int64_t nchunk, const double* __restrict__ cs) {
-  if (cg_done(cs)) return;   // uniform
-  constexpr int K = kPerChunk<S>;
-  const double be = cs[CG_BETA];
-  for (int64_t c = (int64_t)blockIdx.x * kCgThreads + threadIdx.x; c < nchunk;
-       c += (int64_t)gridDim.x * kCgThreads) {
-    S rv[K], pv[K];
-    ld16<S>(r + c * K, rv);
-    ld16<S>(p + c * K, pv);
-#pragma unroll
-    for (int e = 0; e < K; ++e) pv[e] = (S)((double)rv[e] + be * (double)pv[e]);
-    st16<S>(p + c * K, pv);
   }
 }
 
@@ -274,8 +263,6 @@ hipError_t launch_cg_step(cplx<S>* x, cplx<S>* r, cplx<S>* p, const cplx<S>* q, 
                      reinterpret_cast<S*>(x), reinterpret_cast<S*>(r),
                      reinterpret_cast<const S*>(p), reinterpret_cast<const S*>(q), chunks<S>(n),
                      apart, napply, cs, part, reinterpret_cast<unsigned*>(cs + CG_CNT));
-  hipLaunchKernelGGL(k_cg_dir<S>, dim3(nb), dim3(kCgThreads), 0, st,
-                     reinterpret_cast<const S*>(r), reinterpret_cast<S*>(p), chunks<S>(n), cs);
   return hipGetLastError();
 }
 

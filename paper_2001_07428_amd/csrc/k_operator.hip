@@ -68,16 +68,58 @@ __device__ __forceinline__ void store_site(cplx<S>* __restrict__ p, const cx<C> 
   }
 }
 
+// The operand of an apply: a plain vector x, or (in the conjugate-gradient
+// loop) the new search direction p = r + beta p_old, formed on the fly from
+// r and the previous direction so that the direction update needs no pass of
+// its own.  Every element of p is formed by the same expression (an explicit
+// fma) wherever it is used, so the copy of p that the kernel stores for the
+// other CG kernels is bit-identical to the operand it applied A to.
+template <typename S>
+__device__ __forceinline__ S cg_dir(S r, S p, double beta) {
+  return (S)fma(beta, (double)p, (double)r);
+}
+template <typename S, bool DIR> struct Operand;
+template <typename S> struct Operand<S, false> {
+  const cplx<S>* __restrict__ x;
+  template <typename C>
+  __device__ __forceinline__ void site(int64_t off, C re[4], C im[4]) const {
+    load_site<S, C>(x + off, re, im);
+  }
+  __device__ __forceinline__ cplx<S> elem(int64_t off) const { return x[off]; }
+};
+template <typename S> struct Operand<S, true> {
+  const cplx<S>* __restrict__ r;
+  const cplx<S>* __restrict__ p;
+  double beta;
+  template <typename C>
+  __device__ __forceinline__ void site(int64_t off, C re[4], C im[4]) const {
+    S rr[4], ri[4], pr[4], pi[4];
+    load_site<S, S>(r + off, rr, ri);
+    load_site<S, S>(p + off, pr, pi);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      re[k] = (C)cg_dir<S>(rr[k], pr[k], beta);
+      im[k] = (C)cg_dir<S>(ri[k], pi[k], beta);
+    }
+  }
+  __device__ __forceinline__ cplx<S> elem(int64_t off) const {
+    const cplx<S> a = r[off], b = p[off];
+    cplx<S> o;
+    o.x = cg_dir<S>(a.x, b.x, beta);
+    o.y = cg_dir<S>(a.y, b.y, beta);
+    return o;
+  }
+};
+
 // Computes (A v)(s) for one site: top[4], bot[4] in compute type C.  Links are site-fastest: entry e (row-major
 // index in the 4x4 link) of U_mu(s) is U[(mu * 16 + e) * V + s], so the 64
 // lanes of a wavefront read 64 consecutive elements per entry.  Without
 // BSITE, B holds the 4 direction matrices B_mu (16 entries each), read at
 // wavefront-uniform addresses (scalar loads); with BSITE it has the layout of
 // U.  One direction and one hop are live at a time.
-template <typename S, typename C, bool BSITE>
-__device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx<S>* __restrict__ xt,
-                                             const cplx<S>* __restrict__ xb, int64_t s,
-                                             cx<C> top[4], cx<C> bot[4]) {
+template <typename S, typename C, bool BSITE, typename X>
+__device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const X& xo, int64_t h,
+                                             int64_t s, cx<C> top[4], cx<C> bot[4]) {
   const int Ls[4] = {a.L[0], a.L[1], a.L[2], a.L[3]};
   const int64_t st[4] = {(int64_t)Ls[1] * Ls[2] * Ls[3], (int64_t)Ls[2] * Ls[3], (int64_t)Ls[3], 1};
   int x[4];
@@ -92,8 +134,8 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx
   const C sc = (C)a.scale;
   {
     C ar[4], ai[4], br[4], bi[4];
-    load_site<S, C>(xt + s * 4, ar, ai);
-    load_site<S, C>(xb + s * 4, br, bi);
+    xo.template site<C>(s * 4, ar, ai);
+    xo.template site<C>(h + s * 4, br, bi);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       top[r].re = dg * ar[r]; top[r].im = dg * ai[r];
@@ -110,8 +152,8 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx
     // ---- forward hop: U(x) a(x+mu), conj(U(x)) b(x+mu), B(x) b(x+mu), conj(B(x)) a(x+mu)
     {
       C ar[4], ai[4], br[4], bi[4];
-      load_site<S, C>(xt + sf * 4, ar, ai);
-      load_site<S, C>(xb + sf * 4, br, bi);
+      xo.template site<C>(sf * 4, ar, ai);
+      xo.template site<C>(h + sf * 4, br, bi);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         cx<C> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
@@ -132,8 +174,8 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const cplx
     // ---- backward hop: U(x-mu)^H a, U(x-mu)^T b, B(x-mu)^T b, B(x-mu)^H a at x-mu
     {
       C ar[4], ai[4], br[4], bi[4];
-      load_site<S, C>(xt + sb * 4, ar, ai);
-      load_site<S, C>(xb + sb * 4, br, bi);
+      xo.template site<C>(sb * 4, ar, ai);
+      xo.template site<C>(h + sb * 4, br, bi);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         cx<C> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
@@ -161,34 +203,53 @@ __device__ __forceinline__ double block_sum(double v, double* sh);
 
 // y = A x per site; with apart != nullptr (single column) the block also
 // writes its FP64 partial of x^H y (the alpha_j of Alg. 2) to apart[2*blk].
-template <typename S, bool BSITE>
+// With DIR (single column, CG) the operand is p = r + beta p_old with
+// p_old = x, and p is stored to pnew as well.
+template <typename S, bool BSITE, bool DIR>
 __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply(StencilArgs<S> a,
                                                                    const cplx<S>* __restrict__ x,
                                                                    cplx<S>* __restrict__ y,
                                                                    int64_t ld,
-                                                                   double* __restrict__ apart) {
+                                                                   double* __restrict__ apart,
+                                                                   const cplx<S>* __restrict__ dr,
+                                                                   const double* __restrict__ dbeta,
+                                                                   cplx<S>* __restrict__ pnew) {
   if (a.skip && *a.skip != 0.0) return;   // uniform over the grid
   __shared__ double sh[kStencilThreads / 64];
   const int64_t s = (int64_t)blockIdx.x * kStencilThreads + threadIdx.x;
   const int64_t h = a.V * 4;
-  const cplx<S>* xc = x + (int64_t)blockIdx.y * ld;
+  Operand<S, DIR> xo;
+  if constexpr (DIR) xo = Operand<S, true>{dr, x, *dbeta};
+  else xo = Operand<S, false>{x + (int64_t)blockIdx.y * ld};
   cplx<S>* yc = y + (int64_t)blockIdx.y * ld;
   double are = 0.0, aim = 0.0;
   if (s < a.V) {
     cx<S> top[4], bot[4];
-    stencil_site<S, S, BSITE>(a, xc, xc + h, s, top, bot);
+    stencil_site<S, S, BSITE>(a, xo, h, s, top, bot);
     store_site<S, S>(yc + s * 4, top);
     store_site<S, S>(yc + h + s * 4, bot);
-    if (apart) {   // the site's own components again (cache hit)
+    if (apart || DIR) {   // the site's own operand components again (cache hit)
       S a0r[4], a0i[4], b0r[4], b0i[4];
-      load_site<S, S>(xc + s * 4, a0r, a0i);
-      load_site<S, S>(xc + h + s * 4, b0r, b0i);
+      xo.template site<S>(s * 4, a0r, a0i);
+      xo.template site<S>(h + s * 4, b0r, b0i);
+      if constexpr (DIR) {
+        cx<S> pt[4], pb[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        are += (double)a0r[r] * top[r].re + (double)a0i[r] * top[r].im +
-               (double)b0r[r] * bot[r].re + (double)b0i[r] * bot[r].im;
-        aim += (double)a0r[r] * top[r].im - (double)a0i[r] * top[r].re +
-               (double)b0r[r] * bot[r].im - (double)b0i[r] * bot[r].re;
+        for (int r = 0; r < 4; ++r) {
+          pt[r] = cx<S>{a0r[r], a0i[r]};
+          pb[r] = cx<S>{b0r[r], b0i[r]};
+        }
+        store_site<S, S>(pnew + s * 4, pt);
+        store_site<S, S>(pnew + h + s * 4, pb);
+      }
+      if (apart) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          are += (double)a0r[r] * top[r].re + (double)a0i[r] * top[r].im +
+                 (double)b0r[r] * bot[r].re + (double)b0i[r] * bot[r].im;
+          aim += (double)a0r[r] * top[r].im - (double)a0i[r] * top[r].re +
+                 (double)b0r[r] * bot[r].im - (double)b0i[r] * bot[r].re;
+        }
       }
     }
   }
@@ -224,20 +285,24 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {   // result 
 // halves and stores it (the four lanes write the site's components
 // contiguously).  Four times the wavefronts of the one-thread-per-site form,
 // for lattices too small to fill the device with one thread per site.
-template <typename S, bool BSITE>
+template <typename S, bool BSITE, bool DIR>
 __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply4(StencilArgs<S> a,
                                                                     const cplx<S>* __restrict__ x,
                                                                     cplx<S>* __restrict__ y,
                                                                     int64_t ld,
-                                                                    double* __restrict__ apart) {
+                                                                    double* __restrict__ apart,
+                                                                    const cplx<S>* __restrict__ dr,
+                                                                    const double* __restrict__ dbeta,
+                                                                    cplx<S>* __restrict__ pnew) {
   if (a.skip && *a.skip != 0.0) return;   // uniform over the grid
   __shared__ double sh[kStencilThreads / 64];
   const int64_t gt = (int64_t)blockIdx.x * kStencilThreads + threadIdx.x;
   const int64_t s = gt >> 2;
   const int mu = (int)(gt & 3);
   const int64_t h = a.V * 4;
-  const cplx<S>* xt = x + (int64_t)blockIdx.y * ld;
-  const cplx<S>* xb = xt + h;
+  Operand<S, DIR> xo;
+  if constexpr (DIR) xo = Operand<S, true>{dr, x, *dbeta};
+  else xo = Operand<S, false>{x + (int64_t)blockIdx.y * ld};
   cplx<S>* yc = y + (int64_t)blockIdx.y * ld;
   const bool active = s < a.V;          // whole quads are active or not (4 | blockDim)
   const int64_t sc = active ? s : 0;    // inactive quads compute a harmless site
@@ -263,8 +328,8 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply4(StencilArgs<
     if (mu == 0) {   // the diagonal term, once per site
       const S dg = (S)a.diag;
       S ar[4], ai[4], br[4], bi[4];
-      load_site<S, S>(xt + sc * 4, ar, ai);
-      load_site<S, S>(xb + sc * 4, br, bi);
+      xo.template site<S>(sc * 4, ar, ai);
+      xo.template site<S>(h + sc * 4, br, bi);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         top[q].re = dg * ar[q]; top[q].im = dg * ai[q];
@@ -276,8 +341,8 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply4(StencilArgs<
     const cplx<S>* Bm = BSITE ? a.B + (int64_t)mu * 16 * V : a.B + mu * 16;
     {   // forward hop: U(x) a(x+mu), conj(U(x)) b(x+mu), B(x) b(x+mu), conj(B(x)) a(x+mu)
       S ar[4], ai[4], br[4], bi[4];
-      load_site<S, S>(xt + sf * 4, ar, ai);
-      load_site<S, S>(xb + sf * 4, br, bi);
+      xo.template site<S>(sf * 4, ar, ai);
+      xo.template site<S>(h + sf * 4, br, bi);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         cx<S> t = {0, 0}, u = {0, 0}, tb = {0, 0}, ub = {0, 0};
@@ -296,8 +361,8 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply4(StencilArgs<
     }
     {   // backward hop: U(x-mu)^H a, U(x-mu)^T b, B(x-mu)^T b, B(x-mu)^H a at x-mu
       S ar[4], ai[4], br[4], bi[4];
-      load_site<S, S>(xt + sb * 4, ar, ai);
-      load_site<S, S>(xb + sb * 4, br, bi);
+      xo.template site<S>(sb * 4, ar, ai);
+      xo.template site<S>(h + sb * 4, br, bi);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         cx<S> t = {0, 0}, u = {0, 0}, tb = {0, 0}, ub = {0, 0};
@@ -335,8 +400,12 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply4(StencilArgs<
     b.x = ob.re; b.y = ob.im;
     yc[s * 4 + mu] = t;
     yc[h + s * 4 + mu] = b;
-    if (apart) {
-      const cplx<S> x0 = xt[s * 4 + mu], x1 = xb[s * 4 + mu];
+    if (apart || DIR) {
+      const cplx<S> x0 = xo.elem(s * 4 + mu), x1 = xo.elem(h + s * 4 + mu);
+      if constexpr (DIR) {
+        pnew[s * 4 + mu] = x0;
+        pnew[h + s * 4 + mu] = x1;
+      }
       are = (double)x0.x * t.x + (double)x0.y * t.y + (double)x1.x * b.x + (double)x1.y * b.y;
       aim = (double)x0.x * t.y - (double)x0.y * t.x + (double)x1.x * b.y - (double)x1.y * b.x;
     }
@@ -367,7 +436,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S
   if (s < a.V) {
     const cplx<S>* xc = X + (int64_t)cols[c] * ldx;
     cx<double> top[4], bot[4];
-    stencil_site<S, double, BSITE>(a, xc, xc + h, s, top, bot);
+    stencil_site<S, double, BSITE>(a, Operand<S, false>{xc}, h, s, top, bot);
     double a0r[4], a0i[4], b0r[4], b0i[4];
     load_site<S, double>(xc + s * 4, a0r, a0i);
     load_site<S, double>(xc + h + s * 4, b0r, b0i);
@@ -397,9 +466,8 @@ __global__ void k_links_site_fastest(const cplx<S>* __restrict__ src, cplx<S>* _
 // ------------------------------------------------------------------ dense
 constexpr int kDenseThreads = 256;   // 4 rows per block, one wavefront per row
 
-template <typename S, typename C>
-__device__ __forceinline__ void dense_row(const DenseArgs<S>& a, const cplx<S>* __restrict__ xt,
-                                          const cplx<S>* __restrict__ xb, int64_t r, cx<C>& s1,
+template <typename S, typename C, typename X>
+__device__ __forceinline__ void dense_row(const DenseArgs<S>& a, const X& xo, int64_t r, cx<C>& s1,
                                           cx<C>& s2) {
   const int lane = threadIdx.x % 64;
   const cplx<S>* r11 = a.A11 + r * a.ld;
@@ -407,7 +475,7 @@ __device__ __forceinline__ void dense_row(const DenseArgs<S>& a, const cplx<S>* 
   cx<C> p = {0, 0}, q = {0, 0};
   for (int64_t c = lane; c < a.h; c += 64) {
     const cplx<S> m11 = r11[c], m12 = r12[c];
-    const cplx<S> va = xt[c], vb = xb[c];
+    const cplx<S> va = xo.elem(c), vb = xo.elem(a.h + c);
     // s1 += A11 a + A12 b
     mac(p, (C)m11.x, (C)m11.y, (C)va.x, (C)va.y);
     mac(p, (C)m12.x, (C)m12.y, (C)vb.x, (C)vb.y);
@@ -426,28 +494,39 @@ __device__ __forceinline__ void dense_row(const DenseArgs<S>& a, const cplx<S>* 
   s2 = q;
 }
 
-template <typename S>
+// As k_stencil_apply: with DIR the operand is p = r + beta p_old (p_old = x)
+// and p is stored to pnew.
+template <typename S, bool DIR>
 __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(DenseArgs<S> a,
                                                                const cplx<S>* __restrict__ x,
                                                                cplx<S>* __restrict__ y, int64_t ld,
-                                                               double* __restrict__ apart) {
+                                                               double* __restrict__ apart,
+                                                               const cplx<S>* __restrict__ dr,
+                                                               const double* __restrict__ dbeta,
+                                                               cplx<S>* __restrict__ pnew) {
   if (a.skip && *a.skip != 0.0) return;   // uniform over the grid
   __shared__ double sh[kDenseThreads / 64];
   const int64_t r = (int64_t)blockIdx.x * (kDenseThreads / 64) + threadIdx.x / 64;
-  const cplx<S>* xc = x + (int64_t)blockIdx.y * ld;
+  Operand<S, DIR> xo;
+  if constexpr (DIR) xo = Operand<S, true>{dr, x, *dbeta};
+  else xo = Operand<S, false>{x + (int64_t)blockIdx.y * ld};
   cplx<S>* yc = y + (int64_t)blockIdx.y * ld;
   double are = 0.0, aim = 0.0;
   if (r < a.h) {
     cx<S> s1, s2;
-    dense_row<S, S>(a, xc, xc + a.h, r, s1, s2);
+    dense_row<S, S>(a, xo, r, s1, s2);
     if (threadIdx.x % 64 == 0) {
       cplx<S> t, b;
       t.x = s1.re; t.y = s1.im;
       b.x = s2.re; b.y = -s2.im;   // u_bot = conj(s2)
       yc[r] = t;
       yc[a.h + r] = b;
-      if (apart) {
-        const cplx<S> xt = xc[r], xb = xc[a.h + r];
+      if (apart || DIR) {
+        const cplx<S> xt = xo.elem(r), xb = xo.elem(a.h + r);
+        if constexpr (DIR) {
+          pnew[r] = xt;
+          pnew[a.h + r] = xb;
+        }
         are = (double)xt.x * t.x + (double)xt.y * t.y + (double)xb.x * b.x + (double)xb.y * b.y;
         aim = (double)xt.x * t.y - (double)xt.y * t.x + (double)xb.x * b.y - (double)xb.y * b.x;
       }
@@ -477,7 +556,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_resid(DenseArgs<S> a,
   if (r < a.h) {
     const cplx<S>* xc = X + (int64_t)cols[c] * ldx;
     cx<double> s1, s2;
-    dense_row<S, double>(a, xc, xc + a.h, r, s1, s2);
+    dense_row<S, double>(a, Operand<S, false>{xc}, r, s1, s2);
     if (threadIdx.x % 64 == 0) {
       const double l = lam[c];
       const cplx<S> xt = xc[r], xb = xc[a.h + r];
@@ -509,25 +588,43 @@ int stencil_apply_blocks(int64_t V, int es) {
 int dense_apply_blocks(int64_t h) { return (int)((h + kDenseThreads / 64 - 1) / (kDenseThreads / 64)); }
 int dense_resid_blocks(int64_t h) { return (int)((h + kDenseThreads / 64 - 1) / (kDenseThreads / 64)); }
 
-template <typename S>
-hipError_t launch_stencil_apply(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
-                                int nrhs, double* apart, hipStream_t st) {
-  if (apart && nrhs != 1) return hipErrorInvalidValue;
+template <typename S, bool DIR>
+hipError_t stencil_apply_impl(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
+                              int nrhs, double* apart, const cplx<S>* dr, const double* dbeta,
+                              cplx<S>* pnew, hipStream_t st) {
   constexpr int es = (int)sizeof(cplx<S>);
   if (stencil_quad(a.V, es)) {
     dim3 grid4((unsigned)stencil_apply_blocks(a.V, es), (unsigned)nrhs);
     if (a.b_per_site)
-      hipLaunchKernelGGL((k_stencil_apply4<S, true>), grid4, dim3(kStencilThreads), 0, st, a, x, y, ld, apart);
+      hipLaunchKernelGGL((k_stencil_apply4<S, true, DIR>), grid4, dim3(kStencilThreads), 0, st, a, x,
+                         y, ld, apart, dr, dbeta, pnew);
     else
-      hipLaunchKernelGGL((k_stencil_apply4<S, false>), grid4, dim3(kStencilThreads), 0, st, a, x, y, ld, apart);
+      hipLaunchKernelGGL((k_stencil_apply4<S, false, DIR>), grid4, dim3(kStencilThreads), 0, st, a,
+                         x, y, ld, apart, dr, dbeta, pnew);
     return hipGetLastError();
   }
   dim3 grid((unsigned)((a.V + kStencilThreads - 1) / kStencilThreads), (unsigned)nrhs);
   if (a.b_per_site)
-    hipLaunchKernelGGL((k_stencil_apply<S, true>), grid, dim3(kStencilThreads), 0, st, a, x, y, ld, apart);
+    hipLaunchKernelGGL((k_stencil_apply<S, true, DIR>), grid, dim3(kStencilThreads), 0, st, a, x, y,
+                       ld, apart, dr, dbeta, pnew);
   else
-    hipLaunchKernelGGL((k_stencil_apply<S, false>), grid, dim3(kStencilThreads), 0, st, a, x, y, ld, apart);
+    hipLaunchKernelGGL((k_stencil_apply<S, false, DIR>), grid, dim3(kStencilThreads), 0, st, a, x,
+                       y, ld, apart, dr, dbeta, pnew);
   return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_stencil_apply(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
+                                int nrhs, double* apart, hipStream_t st) {
+  if (apart && nrhs != 1) return hipErrorInvalidValue;
+  return stencil_apply_impl<S, false>(a, x, y, ld, nrhs, apart, nullptr, nullptr, nullptr, st);
+}
+
+template <typename S>
+hipError_t launch_stencil_apply_dir(const StencilArgs<S>& a, const cplx<S>* r, const cplx<S>* pold,
+                                    const double* beta, cplx<S>* pnew, cplx<S>* y, double* apart,
+                                    hipStream_t st) {
+  return stencil_apply_impl<S, true>(a, pold, y, a.V * 8, 1, apart, r, beta, pnew, st);
 }
 
 template <typename S>
@@ -558,7 +655,18 @@ hipError_t launch_dense_apply(const DenseArgs<S>& a, const cplx<S>* x, cplx<S>* 
                               int nrhs, double* apart, hipStream_t st) {
   if (apart && nrhs != 1) return hipErrorInvalidValue;
   dim3 grid((unsigned)dense_resid_blocks(a.h), (unsigned)nrhs);
-  hipLaunchKernelGGL(k_dense_apply<S>, grid, dim3(kDenseThreads), 0, st, a, x, y, ldv, apart);
+  hipLaunchKernelGGL((k_dense_apply<S, false>), grid, dim3(kDenseThreads), 0, st, a, x, y, ldv,
+                     apart, nullptr, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_dense_apply_dir(const DenseArgs<S>& a, const cplx<S>* r, const cplx<S>* pold,
+                                  const double* beta, cplx<S>* pnew, cplx<S>* y, double* apart,
+                                  hipStream_t st) {
+  dim3 grid((unsigned)dense_resid_blocks(a.h), 1u);
+  hipLaunchKernelGGL((k_dense_apply<S, true>), grid, dim3(kDenseThreads), 0, st, a, pold, y,
+                     2 * a.h, apart, r, beta, pnew);
   return hipGetLastError();
 }
 
@@ -584,7 +692,13 @@ hipError_t launch_dense_resid(const DenseArgs<S>& a, const cplx<S>* X, int64_t l
                                             int64_t, int, double*, hipStream_t);                 \
   template hipError_t launch_dense_resid<S>(const DenseArgs<S>&, const cplx<S>*, int64_t,        \
                                             const int*, const double*, int, double*, int*,       \
-                                            hipStream_t);
+                                            hipStream_t);                                        \
+  template hipError_t launch_stencil_apply_dir<S>(const StencilArgs<S>&, const cplx<S>*,         \
+                                                  const cplx<S>*, const double*, cplx<S>*,       \
+                                                  cplx<S>*, double*, hipStream_t);               \
+  template hipError_t launch_dense_apply_dir<S>(const DenseArgs<S>&, const cplx<S>*,             \
+                                                const cplx<S>*, const double*, cplx<S>*,         \
+                                                cplx<S>*, double*, hipStream_t);
 JL_INST(float)
 JL_INST(double)
 #undef JL_INST

@@ -17,6 +17,7 @@ eq. (blockform)):
   (T_mu a)(x) = a(x + mu_hat) with periodic wrap.
 * known spectrum (Case A, Sec. 4.1): A = U diag(Lambda, Lambda) U^H from a
   J-orthonormal U = [X, J X^*] and Lambda uniform on (0, 1).
+* Case B links (Sec. 4.2): Haar-random SU(N) matrices U_mu, mu = 1..4.
 
 Complex normal CN(0,1): real and imaginary parts i.i.d. N(0, 1/2), the real
 part drawn first as a whole array.
@@ -31,7 +32,7 @@ import numpy as np
 
 __all__ = [
     "cn", "dense_jsym", "batched_sizes", "batched_dense", "haar_unitary",
-    "stencil_links", "constant_links", "random_start", "known_spectrum", "STENCIL_DIAG",
+    "stencil_links", "constant_links", "random_start", "known_spectrum", "haar_su", "STENCIL_DIAG",
     "STENCIL_A12_SCALE",
 ]
 
@@ -127,6 +128,24 @@ def constant_links(seed: int, L, d: int = 4):
     B = cn(rng, (4, d, d))
     U = np.ascontiguousarray(np.broadcast_to(Uc[:, None], (4, V, d, d)))
     return Uc, B, U
+
+
+def haar_su(seed_or_rng, N: int, count: int) -> np.ndarray:
+    """count Haar-random SU(N) matrices (count, N, N): the unitary factor of a
+    complex Gaussian matrix (QR with a positive real diagonal of R, Mezzadri
+    2007), divided by an N-th root of its determinant.  They stand in for the
+    Monte Carlo links of the Case B operator (Sec. 4.2)."""
+    rng = (seed_or_rng if isinstance(seed_or_rng, np.random.Generator)
+           else np.random.default_rng(seed_or_rng))
+    out = np.empty((count, N, N), dtype=complex)
+    for c in range(count):
+        Z = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) / np.sqrt(2.0)
+        Q, R = np.linalg.qr(Z)
+        d = np.diag(R)
+        Q = Q * (d / np.abs(d))[None, :]
+        det = np.linalg.det(Q)
+        out[c] = Q / det ** (1.0 / N)
+    return out
 
 
 def random_start(seed: int, n: int) -> np.ndarray:

@@ -30,7 +30,7 @@ JL_LOWEST, JL_LARGEST = 0, 1
 
 EXPORTS = (
     "jl_ctx_create", "jl_ctx_destroy", "jl_last_error", "jl_status_string",
-    "jl_op_create_dense", "jl_op_create_stencil", "jl_op_destroy", "jl_op_dim",
+    "jl_op_create_dense", "jl_op_create_stencil", "jl_op_create_tek", "jl_op_destroy", "jl_op_dim",
     "jl_op_apply", "jl_workspace_bytes", "jl_solve", "jl_pair_vectors",
     "jl_reorth_pass_workspace_bytes", "jl_reorth_pass", "jl_ritz_workspace_bytes", "jl_ritz",
     "jl_ritz_restart_workspace_bytes", "jl_ritz_restart",
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH):
         "jl_op_create_dense": (i32, [vp, i64, vp, vp, i64, i32, ctypes.POINTER(vp)]),
         "jl_op_create_stencil": (i32, [vp, ctypes.POINTER(i32), i32, dbl, dbl, vp, vp, i32, i32,
                                        ctypes.POINTER(vp)]),
+        "jl_op_create_tek": (i32, [vp, i32, dbl, vp, i32, ctypes.POINTER(vp)]),
         "jl_op_destroy": (i32, [vp]),
         "jl_op_dim": (i32, [vp, ctypes.POINTER(i64)]),
         "jl_op_apply": (i32, [vp, vp, vp, i32]),
@@ -237,6 +238,20 @@ def jl_op_create_stencil(ctx: Context, L, U, B, diag=8.1, a12_scale=0.3) -> Oper
                                     ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(B.data_ptr()),
                                     int(per_site), _dtype_code(U), ctypes.byref(op)), ctx.handle)
     return Operator(ctx, op, (U, B), 2 * V * 4, U.dtype)
+
+
+def jl_op_create_tek(ctx: Context, U, kappa) -> Operator:
+    """Case B operator A = D D^H (twisted Eguchi-Kawai Wilson-Dirac, J = C gamma_5)
+    from device links U of shape (4, N, N); vectors in the layout
+    [psi_0; psi_2; psi_1; psi_3] of su(N) coefficients (n = 4 (N^2 - 1))."""
+    lib = load_library()
+    if U.dim() != 3 or U.shape[0] != 4 or U.shape[1] != U.shape[2] or not U.is_contiguous():
+        raise ValueError("U must be contiguous (4, N, N)")
+    N = int(U.shape[1])
+    op = ctypes.c_void_p()
+    _check(lib.jl_op_create_tek(ctx.handle, N, float(kappa), ctypes.c_void_p(U.data_ptr()),
+                                _dtype_code(U), ctypes.byref(op)), ctx.handle)
+    return Operator(ctx, op, (U,), 4 * (N * N - 1), U.dtype)
 
 
 def jl_op_apply(op: Operator, x, y=None):

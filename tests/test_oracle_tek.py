@@ -126,3 +126,28 @@ def test_trlan_on_canonical_tek_vs_brute():
     out = trlan.trlan_jsym(lambda v: Ac @ v, Ac.shape[0], 6, 12, 28, 1e-10)
     assert out["status"] == "ok"
     assert np.abs(out["ev"] - ref[:6]).max() < 1e-10 * ref[-1]
+
+
+@pytest.mark.parametrize("N", [2, 3, 6])
+def test_entry_formulas_match_generator_sums(N):
+    rng = np.random.default_rng(N)
+    na = N * N - 1
+    psi = rng.standard_normal((3, na)) + 1j * rng.standard_normal((3, na))
+    X = tek.coef_to_mat(psi, N)
+    assert np.allclose(tek.coef_to_mat_entries(psi, N), X)
+    Y = rng.standard_normal((2, N, N)) + 1j * rng.standard_normal((2, N, N))
+    Y -= np.trace(Y, axis1=1, axis2=2)[:, None, None] * np.eye(N) / N     # traceless
+    assert np.allclose(tek.mat_to_coef_entries(Y, N), tek.mat_to_coef(Y, N))
+    Us = _us(7, N)
+    v = rng.standard_normal(4 * na) + 1j * rng.standard_normal(4 * na)
+    assert np.allclose(tek.apply_A(Us, KAPPA, v, entries=True), tek.apply_A(Us, KAPPA, v))
+
+
+def test_canonical_layout_helpers():
+    N = 3
+    na = N * N - 1
+    Jf = np.kron(tek.J4.real, np.eye(na))
+    P = tek.canonical_matrix(Jf)
+    v = np.arange(4 * na) + 0j
+    assert np.allclose(tek.from_canonical(v, na), P @ v)
+    assert np.allclose(tek.to_canonical(P @ v, na), v)
