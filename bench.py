@@ -9,7 +9,8 @@ reductions and Ritz problem) and in plain FP64; `value` is the mixed time to
 the nev converged pairs, the FP64 time is reported beside it.
 
     python bench.py [--steps K] [--warmup W]
-                    [--workload stencil16|stencil32|dense4096|batched512|casea|invert16]
+                    [--workload stencil16|stencil32|dense4096|batched512|casea|invert16|
+                                tek289|tek289inv]
 
 Prints one JSON line.  Only one GPU is used; --gpus N > 1 exits with a message.
 """
@@ -49,6 +50,15 @@ WORKLOADS = {
     # for TRLAN-JSYM (nev, mwin, m) = (8, 16, 48)
     "invert16": dict(kind="stencil", L=(16, 16, 16, 16), seed=4, nev=8, m=48, mwin=16,
                      tol=1e-5, tol_relative=False, invert=True, cg_tol=1e-7),
+    # Case B operator (Sec. 4.2): A = D D^H, twisted Eguchi-Kawai Wilson-Dirac
+    # with Haar SU(289) links in place of the Monte Carlo ensemble (n = 334080,
+    # the paper's size); the paper's (nev, mwin, m) = (8, 16, 48) for the large
+    # eigenvalues in normal mode and the small ones in invert mode
+    "tek289": dict(kind="tek", N=289, kappa=0.15, seed=289, nev=8, m=48, mwin=16,
+                   which="largest", tol=1e-5, tol_relative=True, tol_fp64=1e-10),
+    "tek289inv": dict(kind="tek", N=289, kappa=0.15, seed=289, nev=8, m=48, mwin=16,
+                      which="lowest", tol=1e-5, tol_relative=True, tol_fp64=1e-10,
+                      invert=True, cg_tol=1e-6, cg_tol_fp64=1e-11),
     # Table 1 (Case A, Sec. 4.1): ten known-spectrum matrices of size 2000,
     # largest eigenvalues, tol 1e-13, FP64; the J-restricted method against
     # the standard one over the published (nev, mwin, m) grid
@@ -66,6 +76,14 @@ def describe(w):
                 f"64..1024, {w['nev']} lowest pairs each, m={w['m']}, mwin={w['mwin']}, "
                 f"tol={w['tol']:g} rel (mixed) / {w['tol_fp64']:g} rel (fp64), seed {w['seed']}, "
                 f"one persistent launch in a hipGraph")
+    if w["kind"] == "tek":
+        N = w["N"]
+        inv = (f", invert mode (CG to {w['cg_tol']:g} / {w['cg_tol_fp64']:g})" if w.get("invert")
+               else ", normal mode")
+        return (f"Case B operator A = D D^H (twisted Eguchi-Kawai Wilson-Dirac, J = C gamma_5), "
+                f"N={N} (n={4 * (N * N - 1)}), kappa={w['kappa']}, Haar SU(N) links seed {w['seed']}, "
+                f"{w['nev']} {w['which']} pairs, m={w['m']}, mwin={w['mwin']}, tol={w['tol']:g} rel "
+                f"(mixed) / {w['tol_fp64']:g} rel (fp64){inv}")
     if w["kind"] == "stencil":
         L = w["L"]
         n = 2 * int(np.prod(L)) * 4
@@ -98,6 +116,8 @@ def make_host_inputs(w):
     if w["kind"] == "stencil":
         U, B = inputs.stencil_links(w["seed"], w["L"])
         return dict(U=U, B=B)
+    if w["kind"] == "tek":
+        return dict(U=inputs.haar_su(w["seed"], w["N"], 4))
     A11, A12 = inputs.dense_jsym(w["seed"], w["h"])
     return dict(A11=A11, A12=A12)
 
@@ -108,6 +128,8 @@ def make_op(J, ctx, w, host, dtype):
         U = torch.from_numpy(host["U"]).to("cuda:0", dtype)
         B = torch.from_numpy(host["B"]).to("cuda:0", dtype)
         return J.jl_op_create_stencil(ctx, w["L"], U, B)
+    if w["kind"] == "tek":
+        return J.jl_op_create_tek(ctx, torch.from_numpy(host["U"]).to("cuda:0", dtype), w["kappa"])
     A11 = torch.from_numpy(host["A11"]).to("cuda:0", dtype)
     A12 = torch.from_numpy(host["A12"]).to("cuda:0", dtype)
     return J.jl_op_create_dense(ctx, A11, A12)
@@ -118,14 +140,17 @@ def run_precision(J, ctx, w, host, mixed, steps, warmup, verbose):
     dtype = torch.complex64 if mixed else torch.complex128
     op = make_op(J, ctx, w, host, dtype)
     tol = w["tol"] if mixed or "tol_fp64" not in w else w["tol_fp64"]
-    rel = w["tol_relative"] if mixed else False
     inv = bool(w.get("invert", False))
     nb = J.jl_workspace_bytes(op, w["nev"], w["m"], w["mwin"], tol, invert=inv)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
 
+    cg_tol = w.get("cg_tol", 0.0) if mixed else w.get("cg_tol_fp64", w.get("cg_tol", 0.0))
+    rel = w["tol_relative"] if (mixed or w["kind"] == "tek") else False
+
     def solve(timing):
-        return J.jl_solve(op, w["nev"], w["m"], w["mwin"], tol, tol_relative=rel, timing=timing,
-                          workspace=ws, verbose=verbose, invert=inv, cg_tol=w.get("cg_tol", 0.0))
+        return J.jl_solve(op, w["nev"], w["m"], w["mwin"], tol, which=w.get("which", "lowest"),
+                          tol_relative=rel, timing=timing, workspace=ws, verbose=verbose,
+                          invert=inv, cg_tol=cg_tol)
 
     for _ in range(warmup):
         solve(False)
@@ -339,13 +364,19 @@ def cpu_baseline(w, host, gpu_stats, budget_s):
         U, B, L = host["U"], host["B"], w["L"]
         n = 2 * int(np.prod(L)) * 4
         apply = lambda v: jsym.stencil_apply(U, B, L, v)
+    elif w["kind"] == "tek":
+        from oracle import tek
+        Us, kap, na = host["U"], w["kappa"], w["N"] ** 2 - 1
+        n = 4 * na
+        apply = lambda v: tek.to_canonical(
+            tek.apply_A(Us, kap, tek.from_canonical(v, na), entries=True), na)
     else:
         A = jsym.dense_from_blocks(host["A11"], host["A12"])
         n = A.shape[0]
         apply = lambda v: A @ v
     step = apply
     if w.get("invert"):   # invert mode: every Lanczos step solves by the oracle's CG
-        step = lambda v: cg.cg(apply, v, w["cg_tol"], 100000)[0]
+        step = lambda v: cg.cg(apply, v, w.get("cg_tol_fp64", w["cg_tol"]), 100000)[0]
     smax = 64
     V = np.zeros((n, smax + 1), dtype=np.complex128)
     T = np.zeros((smax + 1, smax))
@@ -446,7 +477,22 @@ def main():
         print("[bench] fp64 solves", file=sys.stderr, flush=True)
         fp64 = run_precision(J, ctx, w, host, False, args.steps, args.warmup, args.verbose)
     rates = kernel_rates(mixed["stats"])
-    if "cg" in rates:   # invert mode: the CG loop dominates
+    if w["kind"] == "tek":   # bound by the matrix products of the operator apply
+        st = mixed["stats"]
+        N = w["N"]
+        flops = 1024.0 * N ** 3      # 128 complex N x N products per apply of A
+        if w.get("invert"):
+            per, what = st["t_cg"] / st["cg_iters"], "CG iteration (apply + fused update)"
+        else:
+            per, what = st["t_matvec"] / st["n_matvec_launch"], "operator apply"
+        achieved = flops / per / 1e12
+        roof = dict(bound="mfma", kernel=f"k_zgemm (TEK {what}, FP32 MFMA)",
+                    achieved=round(achieved, 2), peak=157.3, unit="TFLOP/s",
+                    frac=round(achieved / 157.3, 4), traffic=None,
+                    algorithmic_flops_per_launch=flops, avg_launch_us=round(per * 1e6, 1),
+                    note="flops of the unpadded products over the whole apply (conversions "
+                         "and combines included)")
+    elif "cg" in rates:   # invert mode: the CG loop dominates
         achieved = rates["cg"]["gbps"]
         roof = dict(bound="hbm", kernel="cg_iteration (apply + alpha/update/beta/direction)",
                     achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
