@@ -335,15 +335,15 @@ def kernel_rates(stats):
     return out
 
 
-def traffic_for(kernel, achieved_bytes_per_launch):
+def traffic_for(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source (else None)."""
+    was taken on this workload and on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
     src = os.path.join(ROOT, "paper_2001_07428_amd", "csrc", "k_reorth.hip")
     try:
         rec = json.load(open(path))
         h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if rec.get("source_sha256") != h:
+        if rec.get("source_sha256") != h or rec.get("bench_workload") != workload:
             return None
         return rec.get("hbm_bytes_per_launch")
     except (OSError, ValueError):
@@ -480,7 +480,7 @@ def main():
     if w["kind"] == "tek":   # bound by the matrix products of the operator apply
         st = mixed["stats"]
         N = w["N"]
-        flops = 1024.0 * N ** 3      # 128 complex N x N products per apply of A
+        flops = 512.0 * N ** 3       # 64 complex N x N products per apply of A (half-spinors)
         if w.get("invert"):
             per, what = st["t_cg"] / st["cg_iters"], "CG iteration (apply + fused update)"
         else:
@@ -505,7 +505,7 @@ def main():
         achieved = rates[dom]["gbps"]
         roof = dict(bound="hbm", kernel=f"reorth_{dom}", achieved=round(achieved, 1),
                     peak=HBM_PEAK_GBPS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBPS, 4),
-                    traffic=traffic_for(dom, rates[dom]["bytes_per_launch"]),
+                    traffic=traffic_for(dom, args.workload),
                     algorithmic_bytes_per_launch=rates[dom]["bytes_per_launch"],
                     avg_launch_us=round(rates[dom]["avg_us"], 2))
     line = dict(

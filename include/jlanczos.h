@@ -114,11 +114,12 @@ jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double
  * [[0, -I], [I, 0]] of every other call here.
  *  U: device [4][N][N] row-major complex of the dtype (U_mu in SU(N); not
  *     checked), copied at creation (not referenced afterwards).
- * The operator owns 72 Np^2 complex elements of device scratch (Np = N
+ * The operator owns 56 Np^2 complex elements of device scratch (Np = N
  * rounded up to 64), so two applies of one operator must not run at the
  * same time.  D is applied through (V_mu psi)_a T_a = U_mu X U_mu^H with
- * X = psi_b T_b: 128 N x N complex products per apply of A, on the matrix
- * cores in the storage precision.  Errors: JL_EINVAL for N outside 2..1024
+ * X = psi_b T_b, on the rank-2 spin projections of I -/+ gamma_mu: 64 N x N
+ * complex products per apply of A, on the matrix cores in the storage
+ * precision.  Errors: JL_EINVAL for N outside 2..1024
  * or NULL pointers, JL_ENOMEM when the scratch cannot be allocated. */
 jl_status jl_op_create_tek(jl_ctx ctx, int32_t N, double kappa, const void* U, jl_dtype dtype,
                            jl_op* out);

@@ -105,10 +105,12 @@ template <typename S> struct TekArgs {
   int64_t na;                 // N^2 - 1 coefficients per spin
   double kappa;
   cplx<S>* X;                 // [4][Np][Np] spin matrices (scratch)
-  cplx<S>* FB;                // [32][Np][Np]: U X_b U^H for (mu, b), then U^H X_b U
+  cplx<S>* H;                 // [16][Np][Np] half-spinors h (mu*4 + q; q < 2 for U h U^H)
+  cplx<S>* FB;                // [16][Np][Np] U h U^H and U^H h U, same order
   double* zd;                 // [4][N] complex diagonal scratch (FP64)
-  const ZJob<S>* jobs1;       // 32 first products: U X_b, U^H X_b
-  const ZJob<S>* jobs2;       // 32 second products: (U X_b) U^H, (U^H X_b) U
+  const double* proj;         // spin projection tables: B [2][4][2][4], A [2][4][4][2] complex
+  const ZJob<S>* jobs1;       // 16 first products: U h, U^H h
+  const ZJob<S>* jobs2;       // 16 second products: (U h) U^H, (U^H h) U
   const double* skip;         // as StencilArgs::skip
 };
 template <typename S> struct TekSrc {   // operand x, or p = r + beta x stored to pnew

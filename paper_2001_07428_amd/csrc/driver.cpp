@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <complex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -811,45 +812,108 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
 
 namespace {
 
+// Memory of the TEK operator: [U 4 | X 4 | H 16 | T 16 | FB 16] matrices of
+// Np x Np, the diagonal scratch, the projection tables, the product jobs.
 template <typename S>
 TekArgs<S> tek_layout(char* base, int N, int Np, double kappa, size_t* total) {
-  // [U 4 | X 4 | P 32 | FB 32] matrices, then the diagonal scratch, then the job tables
   const size_t M = (size_t)Np * Np * sizeof(cplx<S>);
   TekArgs<S> a{};
   a.N = N;
   a.Np = Np;
   a.na = (int64_t)N * N - 1;
   a.kappa = kappa;
-  cplx<S>* U = reinterpret_cast<cplx<S>*>(base);
   a.X = reinterpret_cast<cplx<S>*>(base + 4 * M);
+  a.H = reinterpret_cast<cplx<S>*>(base + 8 * M);
   a.FB = reinterpret_cast<cplx<S>*>(base + 40 * M);
-  a.zd = reinterpret_cast<double*>(base + 72 * M);
-  const size_t jobs_off = 72 * M + ((8 * (size_t)N * sizeof(double) + 255) & ~size_t(255));
+  a.zd = reinterpret_cast<double*>(base + 56 * M);
+  const size_t proj_off = 56 * M + ((8 * (size_t)N * sizeof(double) + 255) & ~size_t(255));
+  a.proj = reinterpret_cast<const double*>(base + proj_off);
+  const size_t jobs_off = proj_off + 256 * sizeof(double);
   a.jobs1 = reinterpret_cast<const ZJob<S>*>(base + jobs_off);
-  a.jobs2 = a.jobs1 + 32;
-  *total = jobs_off + 64 * sizeof(ZJob<S>);
-  (void)U;
+  a.jobs2 = a.jobs1 + 16;
+  *total = jobs_off + 32 * sizeof(ZJob<S>);
   return a;
 }
 
-// Host copies of the 64 product jobs (pointers into the device block).
+// Host copies of the 32 product jobs (pointers into the device block):
+// T = U h (q < 2) or U^H h (q >= 2), then FB = T U^H or T U.
 template <typename S>
 std::vector<ZJob<S>> tek_jobs(char* base, int Np) {
   const size_t M = (size_t)Np * Np;
   cplx<S>* U = reinterpret_cast<cplx<S>*>(base);
-  cplx<S>* X = U + 4 * M;
-  cplx<S>* P = U + 8 * M;
+  cplx<S>* H = U + 8 * M;
+  cplx<S>* T = U + 24 * M;
   cplx<S>* FB = U + 40 * M;
-  std::vector<ZJob<S>> j(64);
+  std::vector<ZJob<S>> j(32);
   for (int mu = 0; mu < 4; ++mu)
-    for (int b = 0; b < 4; ++b) {
-      const int q = mu * 4 + b;
-      j[q] = ZJob<S>{U + mu * M, X + b * M, P + q * M, 0, 0};                    // U X_b
-      j[16 + q] = ZJob<S>{U + mu * M, X + b * M, P + (16 + q) * M, 1, 0};        // U^H X_b
-      j[32 + q] = ZJob<S>{P + q * M, U + mu * M, FB + q * M, 0, 1};              // (U X_b) U^H
-      j[48 + q] = ZJob<S>{P + (16 + q) * M, U + mu * M, FB + (16 + q) * M, 0, 0};  // (U^H X_b) U
+    for (int q = 0; q < 4; ++q) {
+      const int i = mu * 4 + q;
+      const int dag = q >= 2 ? 1 : 0;
+      j[i] = ZJob<S>{U + mu * M, H + i * M, T + i * M, dag, 0};
+      j[16 + i] = ZJob<S>{T + i * M, U + mu * M, FB + i * M, 0, 1 - dag};
     }
   return j;
+}
+
+// Rank-2 factorisations I + s gamma_mu = A B (s = -1, +1; gamma_mu of the
+// appendix), laid out as TekArgs::proj expects.  Returns false if a check of
+// A B against I + s gamma_mu fails.
+bool tek_projections(double* out) {
+  using Z = std::complex<double>;
+  const Z i1(0.0, 1.0);
+  Z g[4][4][4] = {};
+  g[0][0][3] = -i1; g[0][1][2] = -i1; g[0][2][1] = i1; g[0][3][0] = i1;
+  g[1][0][3] = -1.0; g[1][1][2] = 1.0; g[1][2][1] = 1.0; g[1][3][0] = -1.0;
+  g[2][0][2] = -i1; g[2][1][3] = i1; g[2][2][0] = i1; g[2][3][1] = -i1;
+  g[3][0][0] = 1.0; g[3][1][1] = 1.0; g[3][2][2] = -1.0; g[3][3][3] = -1.0;
+  for (int sg = 0; sg < 2; ++sg)
+    for (int mu = 0; mu < 4; ++mu) {
+      Z P[4][4];
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) P[r][c] = (r == c ? 1.0 : 0.0) + (sg ? 1.0 : -1.0) * g[mu][r][c];
+      auto nrm = [&](int r) { double t = 0; for (int c = 0; c < 4; ++c) t += std::norm(P[r][c]); return t; };
+      auto lead = [&](const Z* row) { int j = 0; for (int c = 1; c < 4; ++c) if (std::abs(row[c]) > std::abs(row[j])) j = c; return j; };
+      auto ratio = [&](int r, const Z* brow, Z* c) {   // P[r] = c brow ?
+        const int j = lead(brow);
+        *c = P[r][j] / brow[j];
+        double d = 0;
+        for (int q = 0; q < 4; ++q) d += std::norm(P[r][q] - *c * brow[q]);
+        return d < 1e-24;
+      };
+      Z B[2][4], A[4][2] = {};
+      int nb = 0;
+      for (int r = 0; r < 4 && nb < 2; ++r) {
+        if (nrm(r) < 1e-24) continue;
+        Z c;
+        if (nb == 1 && ratio(r, B[0], &c)) continue;
+        for (int q = 0; q < 4; ++q) B[nb][q] = P[r][q];
+        ++nb;
+      }
+      if (nb != 2) return false;
+      for (int r = 0; r < 4; ++r) {
+        if (nrm(r) < 1e-24) continue;
+        Z c;
+        if (ratio(r, B[0], &c)) A[r][0] = c;
+        else if (ratio(r, B[1], &c)) A[r][1] = c;
+        else return false;
+      }
+      for (int r = 0; r < 4; ++r)   // check A B = P
+        for (int q = 0; q < 4; ++q)
+          if (std::abs(A[r][0] * B[0][q] + A[r][1] * B[1][q] - P[r][q]) > 1e-12) return false;
+      for (int k = 0; k < 2; ++k)
+        for (int b = 0; b < 4; ++b) {
+          const int i = ((sg * 4 + mu) * 2 + k) * 4 + b;
+          out[2 * i] = B[k][b].real();
+          out[2 * i + 1] = B[k][b].imag();
+        }
+      for (int al = 0; al < 4; ++al)
+        for (int k = 0; k < 2; ++k) {
+          const int i = 64 + ((sg * 4 + mu) * 4 + al) * 2 + k;
+          out[2 * i] = A[al][k].real();
+          out[2 * i + 1] = A[al][k].imag();
+        }
+    }
+  return true;
 }
 
 }  // namespace
@@ -981,6 +1045,9 @@ jl_status jl_op_create_tek(jl_ctx ctx, int32_t N, double kappa, const void* U, j
   if (N < 2 || N > 1024) return set_err(ctx, JL_EINVAL, "N must be in 2..1024 (got %d)", N);
   if (!U) return set_err(ctx, JL_EINVAL, "U is required");
   if (dtype != JL_C64 && dtype != JL_C128) return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
+  double proj[256];
+  if (!tek_projections(proj))
+    return set_err(ctx, JL_EHIP, "TEK operator set-up: spin projection factorisation failed");
   const int Np = (N + 63) / 64 * 64;
   const size_t es = dtype == JL_C64 ? sizeof(float2) : sizeof(double2);
   size_t total = 0;
@@ -1001,7 +1068,11 @@ jl_status jl_op_create_tek(jl_ctx ctx, int32_t N, double kappa, const void* U, j
   jl_op o = new jl_op_s();
   o->tf = tek_layout<float>(base, N, Np, kappa, &total);
   o->td = tek_layout<double>(base, N, Np, kappa, &total);
-  const size_t jobs_bytes = 64 * (dtype == JL_C64 ? sizeof(ZJob<float>) : sizeof(ZJob<double>));
+  const size_t jobs_bytes = 32 * (dtype == JL_C64 ? sizeof(ZJob<float>) : sizeof(ZJob<double>));
+  const double* proj_dev = dtype == JL_C64 ? o->tf.proj : o->td.proj;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(const_cast<double*>(proj_dev), proj, sizeof(proj), hipMemcpyHostToDevice,
+                       ctx->stream);
   std::vector<ZJob<float>> jf;
   std::vector<ZJob<double>> jd;
   const void* jobs_host = nullptr;

@@ -9,10 +9,13 @@
 // V_mu is never formed: with X_beta = sum_a psi_{a, beta} T_a (T_a the
 // generalised Gell-Mann basis of su(N), tr(T_a T_b) = delta_ab / 2),
 //   (V_mu psi_beta)_a T_a = U_mu X_beta U_mu^H,  (V_mu^T psi_beta)_a T_a = U_mu^H X_beta U_mu,
-// so an apply is 4 coefficient-to-matrix conversions, 128 complex N x N
-// matrix products on the matrix cores (D^H then D, 32 products per launch),
-// two spin combines and the conversion back.  The matrices are padded to
-// Np (a multiple of 64) with zeros, which the products keep zero.
+// and I -/+ gamma_mu has rank 2: with I + s gamma_mu = A B (A 4 x 2, B 2 x 4),
+//   sum_b (I + s gamma_mu)_{ab} U X_b U^H = sum_k A_{ak} U h_k U^H,  h_k = sum_b B_{kb} X_b,
+// so each of D^H and D takes 4 spin projections per mu (the half-spinors of
+// lattice Wilson-Dirac codes) and 32 complex N x N products on the matrix
+// cores (16 per launch), with the combines and the conversions around them.
+// The matrices are padded to Np (a multiple of 64) with zeros, which the
+// products keep zero.
 //
 // Coefficient order per spin block (length N^2 - 1): the symmetric
 // generators (E_jk + E_kj)/2 for j < k (row-major over the strict upper
@@ -31,18 +34,6 @@ constexpr int kTekScan = 1024;   // threads of the diagonal kernels (N <= 1024)
 // canonical block of physical spin alpha (and, the map being an involution,
 // the physical spin of canonical block c)
 __constant__ int kCanon[4] = {0, 2, 1, 3};
-
-// gamma_mu of the appendix, (re, im) of entry [mu][row][col]
-__constant__ double kGre[4][4][4] = {
-    {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}},
-    {{0, 0, 0, -1}, {0, 0, 1, 0}, {0, 1, 0, 0}, {-1, 0, 0, 0}},
-    {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}},
-    {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, -1, 0}, {0, 0, 0, -1}}};
-__constant__ double kGim[4][4][4] = {
-    {{0, 0, 0, -1}, {0, 0, -1, 0}, {0, 1, 0, 0}, {1, 0, 0, 0}},
-    {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}},
-    {{0, 0, -1, 0}, {0, 0, 0, 1}, {1, 0, 0, 0}, {0, -1, 0, 0}},
-    {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}}};
 
 template <typename C> struct zc { C re, im; };
 
@@ -149,9 +140,10 @@ __global__ __launch_bounds__(kTekScan) void k_tek_c2m_diag(TekArgs<S> a, TekSrc<
 // -------------------------------------------------------- batched ZGEMM
 // C = op(A) op(B), all Np x Np row-major complex, op in {N, conjugate
 // transpose}.  Tile 64 x 64 per block of four wavefronts (2 x 2, 32 x 32 each
-// as 2 x 2 MFMA 16 x 16 tiles), K staged through LDS in steps of 16 as
-// separate real and imaginary planes; a complex product is four real MFMAs.
-constexpr int ZT = 64, ZBK = 16, ZLD = ZT + 4;
+// as 2 x 2 MFMA 16 x 16 tiles), K staged through two LDS buffers in steps of
+// 16 as separate real and imaginary planes, the next step's loads in flight
+// during the current step's products; a complex product is four real MFMAs.
+constexpr int ZT = 64, ZBK = 16, ZLD = ZT + 16;   // row stride: two rows per 32 banks
 
 template <typename S> struct ZMfma;
 template <> struct ZMfma<float> {
@@ -179,7 +171,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const ZJob<S>* __restrict__ jobs,
   if (skip && *skip != 0.0) return;
   using MF = ZMfma<S>;
   using v4 = typename MF::v4;
-  __shared__ S Ar[ZBK][ZLD], Ai[ZBK][ZLD], Br[ZBK][ZLD], Bi[ZBK][ZLD];
+  __shared__ S Ar[2][ZBK][ZLD], Ai[2][ZBK][ZLD], Br[2][ZBK][ZLD], Bi[2][ZBK][ZLD];
   const ZJob<S> jb = jobs[blockIdx.y];
   const int tiles = Np / ZT;
   const int i0 = (blockIdx.x / tiles) * ZT, j0 = (blockIdx.x % tiles) * ZT;
@@ -191,52 +183,56 @@ __global__ __launch_bounds__(256) void k_zgemm(const ZJob<S>* __restrict__ jobs,
 #pragma unroll
     for (int j = 0; j < 2; ++j) cr[i][j] = ci[i][j] = v4{0, 0, 0, 0};
 
-  for (int k0 = 0; k0 < Np; k0 += ZBK) {
-    cplx<S> va[4], vb[4];
-    if (jb.opA == 0) {   // A[i][k], k contiguous
-      const int i = tid / 4, k = (tid % 4) * 4;
-      ld4<S>(jb.A + (int64_t)(i0 + i) * Np + k0 + k, va);
+  // loader roles: 4 complex of A and 4 of B per thread and K step
+  const bool an = jb.opA == 0, bn = jb.opB == 0;
+  const int ai = an ? tid / 4 : (tid % 16) * 4, ak = an ? (tid % 4) * 4 : tid / 16;
+  const int bk = bn ? tid / 16 : (tid % 4) * 4, bj = bn ? (tid % 16) * 4 : tid / 4;
+  cplx<S> va[4], vb[4];
+  auto load = [&](int k0) {
+    if (an) ld4<S>(jb.A + (int64_t)(i0 + ai) * Np + k0 + ak, va);   // A[i][k], k contiguous
+    else ld4<S>(jb.A + (int64_t)(k0 + ak) * Np + i0 + ai, va);      // A[k][i], i contiguous
+    if (bn) ld4<S>(jb.B + (int64_t)(k0 + bk) * Np + j0 + bj, vb);   // B[k][j], j contiguous
+    else ld4<S>(jb.B + (int64_t)(j0 + bj) * Np + k0 + bk, vb);      // B[j][k], k contiguous
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) { Ar[k + e][i] = va[e].x; Ai[k + e][i] = va[e].y; }
-    } else {             // conj(A[k][i]), i contiguous
-      const int k = tid / 16, i = (tid % 16) * 4;
-      ld4<S>(jb.A + (int64_t)(k0 + k) * Np + i0 + i, va);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) { Ar[k][i + e] = va[e].x; Ai[k][i + e] = -va[e].y; }
+    for (int e = 0; e < 4; ++e) {
+      if (an) { Ar[buf][ak + e][ai] = va[e].x; Ai[buf][ak + e][ai] = va[e].y; }
+      else { Ar[buf][ak][ai + e] = va[e].x; Ai[buf][ak][ai + e] = -va[e].y; }   // conj
+      if (bn) { Br[buf][bk][bj + e] = vb[e].x; Bi[buf][bk][bj + e] = vb[e].y; }
+      else { Br[buf][bk + e][bj] = vb[e].x; Bi[buf][bk + e][bj] = -vb[e].y; }   // conj
     }
-    if (jb.opB == 0) {   // B[k][j], j contiguous
-      const int k = tid / 16, j = (tid % 16) * 4;
-      ld4<S>(jb.B + (int64_t)(k0 + k) * Np + j0 + j, vb);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) { Br[k][j + e] = vb[e].x; Bi[k][j + e] = vb[e].y; }
-    } else {             // conj(B[j][k]), k contiguous
-      const int j = tid / 4, k = (tid % 4) * 4;
-      ld4<S>(jb.B + (int64_t)(j0 + j) * Np + k0 + k, vb);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) { Br[k + e][j] = vb[e].x; Bi[k + e][j] = -vb[e].y; }
-    }
-    __syncthreads();
+  };
+
+  const int nk = Np / ZBK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * ZBK);   // in flight during the products below
 #pragma unroll
     for (int kk = 0; kk < ZBK; kk += 4) {
       const int kr = kk + lane / 16;
-      S ar[2], ai[2], br[2], bi[2];
+      S ar[2], ai2[2], br[2], bi[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        ar[t] = Ar[kr][wm * 32 + t * 16 + lane % 16];
-        ai[t] = Ai[kr][wm * 32 + t * 16 + lane % 16];
-        br[t] = Br[kr][wn * 32 + t * 16 + lane % 16];
-        bi[t] = Bi[kr][wn * 32 + t * 16 + lane % 16];
+        ar[t] = Ar[cur][kr][wm * 32 + t * 16 + lane % 16];
+        ai2[t] = Ai[cur][kr][wm * 32 + t * 16 + lane % 16];
+        br[t] = Br[cur][kr][wn * 32 + t * 16 + lane % 16];
+        bi[t] = Bi[cur][kr][wn * 32 + t * 16 + lane % 16];
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           cr[i][j] = MF::op(ar[i], br[j], cr[i][j]);
-          cr[i][j] = MF::op(-ai[i], bi[j], cr[i][j]);
+          cr[i][j] = MF::op(-ai2[i], bi[j], cr[i][j]);
           ci[i][j] = MF::op(ar[i], bi[j], ci[i][j]);
-          ci[i][j] = MF::op(ai[i], br[j], ci[i][j]);
+          ci[i][j] = MF::op(ai2[i], br[j], ci[i][j]);
         }
     }
+    if (kt + 1 < nk) store(cur ^ 1);   // the other buffer: last read before the previous barrier
     __syncthreads();
   }
   // lane holds rows 4 (lane / 16) + r, column lane % 16 of each 16 x 16 tile
@@ -256,9 +252,57 @@ __global__ __launch_bounds__(256) void k_zgemm(const ZJob<S>* __restrict__ jobs,
 }
 
 // -------------------------------------------------------- spin combine
-// Y_alpha(j,k) = X_alpha(j,k) - kappa sum_mu sum_beta [G1 F_{mu beta} + G2 B_{mu beta}](j,k)
-// with F = U X U^H, B = U^H X U and, for D: G1 = I - gamma_mu, G2 = I + gamma_mu;
-// for D^H: G1 = I + gamma_mu, G2 = I - gamma_mu.  FP64 arithmetic.
+// Projection tables (FP64 complex as (re, im) pairs), for sign s = 0 (I -
+// gamma_mu) and s = 1 (I + gamma_mu): B[s][mu][k][b] builds the half-spinor
+// h_k = sum_b B X_b, A[s][mu][a][k] spreads the products back over the spins.
+__device__ __forceinline__ zc<double> projB(const double* t, int sg, int mu, int k, int b) {
+  const int i = ((sg * 4 + mu) * 2 + k) * 4 + b;
+  return zc<double>{t[2 * i], t[2 * i + 1]};
+}
+__device__ __forceinline__ zc<double> projA(const double* t, int sg, int mu, int al, int k) {
+  const int i = 64 + ((sg * 4 + mu) * 4 + al) * 2 + k;
+  return zc<double>{t[2 * i], t[2 * i + 1]};
+}
+
+// Half-spinors for one pass: H[mu*4 + k] (k < 2) feed U h U^H, H[mu*4 + 2 + k]
+// feed U^H h U.  D uses I - gamma_mu for the first and I + gamma_mu for the
+// second; D^H the other way round.
+template <typename S, bool DAG>
+__global__ __launch_bounds__(kTekThreads) void k_tek_half(TekArgs<S> a) {
+  if (tek_skip(a)) return;
+  const int64_t t = (int64_t)blockIdx.x * kTekThreads + threadIdx.x;
+  if (t >= (int64_t)a.N * a.N) return;
+  const int64_t e = (t / a.N) * a.Np + t % a.N;
+  const int64_t M = (int64_t)a.Np * a.Np;
+  zc<double> x[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const cplx<S> v = a.X[b * M + e];
+    x[b] = zc<double>{(double)v.x, (double)v.y};
+  }
+  const int sgF = DAG ? 1 : 0, sgB = DAG ? 0 : 1;
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {   // q < 2: F inputs, q >= 2: B inputs
+      const int sg = q < 2 ? sgF : sgB, k = q & 1;
+      double hr = 0.0, hi = 0.0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const zc<double> c = projB(a.proj, sg, mu, k, b);
+        hr += c.re * x[b].re - c.im * x[b].im;
+        hi += c.re * x[b].im + c.im * x[b].re;
+      }
+      cplx<S> o;
+      o.x = (S)hr;
+      o.y = (S)hi;
+      a.H[(int64_t)(mu * 4 + q) * M + e] = o;
+    }
+  }
+}
+
+// Y_alpha = X_alpha - kappa sum_mu sum_k [A_F(mu)_{alpha k} F_{mu k} + A_B(mu)_{alpha k} B_{mu k}]
+// with F = U h U^H, B = U^H h U from the half-spinors above.  FP64 arithmetic.
 template <typename S, bool DAG>
 __device__ __forceinline__ void combine_entry(const TekArgs<S>& a, int64_t e, zc<double> y[4]) {
   const int64_t M = (int64_t)a.Np * a.Np;
@@ -268,21 +312,18 @@ __device__ __forceinline__ void combine_entry(const TekArgs<S>& a, int64_t e, zc
     y[al] = zc<double>{(double)x.x, (double)x.y};
   }
   const double kap = a.kappa;
+  const int sgF = DAG ? 1 : 0, sgB = DAG ? 0 : 1;
 #pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
 #pragma unroll
-    for (int be = 0; be < 4; ++be) {
-      const cplx<S> f = a.FB[(int64_t)(mu * 4 + be) * M + e];
-      const cplx<S> b = a.FB[(int64_t)(16 + mu * 4 + be) * M + e];
+    for (int q = 0; q < 4; ++q) {
+      const int sg = q < 2 ? sgF : sgB, k = q & 1;
+      const cplx<S> f = a.FB[(int64_t)(mu * 4 + q) * M + e];
 #pragma unroll
       for (int al = 0; al < 4; ++al) {
-        const double gr = kGre[mu][al][be], gi = kGim[mu][al][be];
-        const double id = al == be ? 1.0 : 0.0;
-        // coefficient of F: (I -/+ gamma), of B: (I +/- gamma)
-        const double fr = DAG ? id + gr : id - gr, fi = DAG ? gi : -gi;
-        const double br = DAG ? id - gr : id + gr, bi = DAG ? -gi : gi;
-        y[al].re -= kap * (fr * f.x - fi * f.y + br * b.x - bi * b.y);
-        y[al].im -= kap * (fr * f.y + fi * f.x + br * b.y + bi * b.x);
+        const zc<double> c = projA(a.proj, sg, mu, al, k);
+        y[al].re -= kap * (c.re * f.x - c.im * f.y);
+        y[al].im -= kap * (c.re * f.y + c.im * f.x);
       }
     }
   }
@@ -447,12 +488,14 @@ hipError_t tek_apply(const TekArgs<S>& a, const TekSrc<S>& src, const TekOut<S>&
                      hipStream_t st) {
   const int N = a.N;
   const int64_t P = (int64_t)N * (N - 1) / 2;
-  const dim3 gz((unsigned)((a.Np / ZT) * (a.Np / ZT)), 32u);
+  const dim3 gz((unsigned)((a.Np / ZT) * (a.Np / ZT)), 16u);
   const dim3 gN((unsigned)(((int64_t)N * N + kTekThreads - 1) / kTekThreads));
   hipLaunchKernelGGL(k_tek_c2m<S>, dim3((unsigned)((4 * P + kTekThreads - 1) / kTekThreads)),
                      dim3(kTekThreads), 0, st, a, src);
   hipLaunchKernelGGL(k_tek_c2m_diag<S>, dim3(4), dim3(kTekScan), 0, st, a, src);
   for (int pass = 0; pass < 2; ++pass) {   // D^H, then D
+    if (pass == 0) hipLaunchKernelGGL((k_tek_half<S, true>), gN, dim3(kTekThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_tek_half<S, false>), gN, dim3(kTekThreads), 0, st, a);
     hipLaunchKernelGGL(k_zgemm<S>, gz, dim3(256), 0, st, a.jobs1, a.Np, a.skip);
     hipLaunchKernelGGL(k_zgemm<S>, gz, dim3(256), 0, st, a.jobs2, a.Np, a.skip);
     if (pass == 0)
