@@ -329,16 +329,16 @@ __device__ __forceinline__ void combine_entry(const TekArgs<S>& a, int64_t e, zc
   }
 }
 
-// X <- D^H X (matrix form, in place, entries j, k < N).
-template <typename S>
-__global__ __launch_bounds__(kTekThreads) void k_tek_combine_dag(TekArgs<S> a) {
+// X <- D^H X or D X (matrix form, in place, entries j, k < N).
+template <typename S, bool DAG>
+__global__ __launch_bounds__(kTekThreads) void k_tek_combine(TekArgs<S> a) {
   if (tek_skip(a)) return;
   const int64_t t = (int64_t)blockIdx.x * kTekThreads + threadIdx.x;
   if (t >= (int64_t)a.N * a.N) return;
   const int j = (int)(t / a.N), k = (int)(t % a.N);
   const int64_t e = (int64_t)j * a.Np + k;
   zc<double> y[4];
-  combine_entry<S, true>(a, e, y);
+  combine_entry<S, DAG>(a, e, y);
   const int64_t M = (int64_t)a.Np * a.Np;
 #pragma unroll
   for (int al = 0; al < 4; ++al) {
@@ -392,40 +392,50 @@ __device__ __forceinline__ void put(const TekOut<S>& o, int64_t i, double yr, do
   }
 }
 
-// y = coefficients of D X (off-diagonal generators), one thread per (pair):
-// s = Z_jk + Z_kj, a = i (Z_jk - Z_kj) for every spin; the diagonal entries
-// Z_jj go to a.zd for the diagonal kernel.
+// y = coefficients of Z = D X (off-diagonal generators): s = Z_jk + Z_kj,
+// a = i (Z_jk - Z_kj) for every spin; the diagonal entries Z_jj go to a.zd
+// for the diagonal kernel.  One block per pair of 32 x 32 tiles (I, K),
+// I <= K: the tiles Z[I][K] and Z[K][I] are read row by row into LDS, so
+// both Z_jk and its mirror Z_kj arrive by coalesced loads.
+constexpr int MT = 32;
 template <typename S>
-__global__ __launch_bounds__(kTekThreads) void k_tek_out(TekArgs<S> a, TekOut<S> o) {
+__global__ __launch_bounds__(kTekThreads) void k_tek_m2c(TekArgs<S> a, TekOut<S> o) {
   if (tek_skip(a)) return;
+  __shared__ cplx<S> ta[MT][MT + 1], tb[MT][MT + 1];
   __shared__ double sh[kTekThreads / 64];
-  const int N = a.N;
+  const int N = a.N, T = (N + MT - 1) / MT;
+  int I = 0, b = blockIdx.x;
+  while (b >= T - I) { b -= T - I; ++I; }
+  const int K = I + b;
   const int64_t P = (int64_t)N * (N - 1) / 2;
-  const int64_t t = (int64_t)blockIdx.x * kTekThreads + threadIdx.x;
+  const int64_t M = (int64_t)a.Np * a.Np;
   double acc[2] = {0.0, 0.0};
-  if (t < P + N) {
-    if (t < P) {
-      int j, k;
-      pair_jk(t, N, j, k);
-      zc<double> u[4], l[4];
-      combine_entry<S, false>(a, (int64_t)j * a.Np + k, u);
-      combine_entry<S, false>(a, (int64_t)k * a.Np + j, l);
-#pragma unroll
-      for (int al = 0; al < 4; ++al) {
-        const int64_t base = (int64_t)kCanon[al] * a.na;
-        put(o, base + t, u[al].re + l[al].re, u[al].im + l[al].im, acc);       // s
-        put(o, base + P + t, -(u[al].im - l[al].im), u[al].re - l[al].re, acc);  // a = i (u - l)
-      }
-    } else {
-      const int j = (int)(t - P);
-      zc<double> d[4];
-      combine_entry<S, false>(a, (int64_t)j * a.Np + j, d);
-#pragma unroll
-      for (int al = 0; al < 4; ++al) {
-        a.zd[2 * ((int64_t)al * N + j)] = d[al].re;
-        a.zd[2 * ((int64_t)al * N + j) + 1] = d[al].im;
+  for (int al = 0; al < 4; ++al) {
+    const cplx<S>* Z = a.X + al * M;
+    for (int i = threadIdx.x; i < MT * MT; i += kTekThreads) {
+      const int r = i / MT, c = i % MT;   // within Np (zero padding beyond N)
+      ta[r][c] = Z[(int64_t)(I * MT + r) * a.Np + K * MT + c];
+      tb[r][c] = Z[(int64_t)(K * MT + r) * a.Np + I * MT + c];
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)kCanon[al] * a.na;
+    for (int i = threadIdx.x; i < MT * MT; i += kTekThreads) {
+      const int r = i / MT, c = i % MT;
+      const int j = I * MT + r, k = K * MT + c;
+      if (k >= N) continue;
+      const cplx<S> u = ta[r][c];
+      if (j < k) {
+        const cplx<S> l = tb[c][r];
+        const int64_t p = (int64_t)j * N - (int64_t)j * (j + 1) / 2 + (k - j - 1);
+        const double ur = u.x, ui = u.y, lr = l.x, li = l.y;
+        put(o, base + p, ur + lr, ui + li, acc);                  // s
+        put(o, base + P + p, -(ui - li), ur - lr, acc);           // a = i (u - l)
+      } else if (j == k) {
+        a.zd[2 * ((int64_t)al * N + j)] = (double)u.x;
+        a.zd[2 * ((int64_t)al * N + j) + 1] = (double)u.y;
       }
     }
+    __syncthreads();
   }
   if (o.part) {
     acc[0] = tek_block_sum(acc[0], sh);
@@ -442,7 +452,7 @@ __global__ __launch_bounds__(kTekThreads) void k_tek_out(TekArgs<S> a, TekOut<S>
 }
 
 // Diagonal generators: d_l = 2 (sum_{j < l} Z_jj - l Z_ll) / sqrt(2 l (l + 1)).
-// One block per spin; its partials go after those of k_tek_out (block
+// One block per spin; its partials go after those of k_tek_m2c (block
 // index nb_out + spin).
 template <typename S>
 __global__ __launch_bounds__(kTekScan) void k_tek_out_diag(TekArgs<S> a, TekOut<S> o, int nb_out) {
@@ -477,9 +487,9 @@ __global__ __launch_bounds__(kTekScan) void k_tek_out_diag(TekArgs<S> a, TekOut<
   }
 }
 
-int out_blocks(int N) {
-  const int64_t P = (int64_t)N * (N - 1) / 2;
-  return (int)((P + N + kTekThreads - 1) / kTekThreads);
+int out_blocks(int N) {   // tile pairs I <= K of the output kernel
+  const int T = (N + MT - 1) / MT;
+  return T * (T + 1) / 2;
 }
 
 // The whole apply: coefficients -> X, D^H (in place on X), D, coefficients.
@@ -498,11 +508,11 @@ hipError_t tek_apply(const TekArgs<S>& a, const TekSrc<S>& src, const TekOut<S>&
     else hipLaunchKernelGGL((k_tek_half<S, false>), gN, dim3(kTekThreads), 0, st, a);
     hipLaunchKernelGGL(k_zgemm<S>, gz, dim3(256), 0, st, a.jobs1, a.Np, a.skip);
     hipLaunchKernelGGL(k_zgemm<S>, gz, dim3(256), 0, st, a.jobs2, a.Np, a.skip);
-    if (pass == 0)
-      hipLaunchKernelGGL(k_tek_combine_dag<S>, gN, dim3(kTekThreads), 0, st, a);
+    if (pass == 0) hipLaunchKernelGGL((k_tek_combine<S, true>), gN, dim3(kTekThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_tek_combine<S, false>), gN, dim3(kTekThreads), 0, st, a);
   }
   const int nb = out_blocks(N);
-  hipLaunchKernelGGL(k_tek_out<S>, dim3((unsigned)nb), dim3(kTekThreads), 0, st, a, o);
+  hipLaunchKernelGGL(k_tek_m2c<S>, dim3((unsigned)nb), dim3(kTekThreads), 0, st, a, o);
   hipLaunchKernelGGL(k_tek_out_diag<S>, dim3(4), dim3(kTekScan), 0, st, a, o, nb);
   return hipGetLastError();
 }
