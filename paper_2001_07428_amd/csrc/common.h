@@ -144,17 +144,25 @@ constexpr int kReorthMaxCols = 2048;   // largest basis dots supports
 // u <- u - t v_jl - beta v_{jl-1} (t = tloc[0] + i tloc[1] on the device,
 // beta = 0 skips the second term), rounds u once to S, stores it, and then
 // takes the inner products of the new u.
+// groups > 1 splits the columns over gridDim.y (reorth_dots_groups); with
+// tloc the locally updated u then goes to uout, which must not be u.
 template <typename S>
 hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
                               double* partial, int nblk, hipStream_t st,
-                              const double* tloc = nullptr, double beta = 0.0, int jl = 0);
+                              const double* tloc = nullptr, double beta = 0.0, int jl = 0,
+                              cplx<S>* uout = nullptr, int groups = 1);
+int reorth_dots_groups(int64_t h);
 // update: u -= V c_v + W c_w (W = J V^*), coef = [4*ncol] FP64 (Re cv, Im cv,
 // Re cw, Im cw per column); partial[blk] = ||u_new||^2 per block.
 template <typename S>
 // jsym = false leaves out the W projection (standard Gram-Schmidt against V).
+// The result goes to u, computed from uin (default u).  groups > 1 splits
+// the columns (reorth_update_groups) and needs d: groups x n complex scratch.
 hipError_t launch_reorth_update(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
                                 const double* coef, double* partial, int nblk, hipStream_t st,
-                                bool jsym = true);
+                                bool jsym = true, const cplx<S>* uin = nullptr, int groups = 1,
+                                cplx<S>* d = nullptr);
+int reorth_update_groups(int64_t h, int es);
 // out[c] = sum_b partial[b * stride + c] for c < ncols (deterministic order).
 hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int ncols, double* out,
                               hipStream_t st);

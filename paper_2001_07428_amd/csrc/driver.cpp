@@ -257,7 +257,7 @@ double op_bytes(const jl_op_s* op, int es) {
 // ----------------------------------------------------------- workspace layout
 struct Layout {
   size_t V[2], apart, dots_part, upd_part, coef, scal, Tdev, ritz, lam_s, Zs, zlast, res_part,
-      res_out, res_lam, res_cols, cg_vec[5], cg_part, cg_s, total;
+      res_out, res_lam, res_cols, cg_vec[5], cg_part, cg_s, rloc, rd, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -289,6 +289,9 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   L.res_out = take(sizeof(double) * p->nev);
   L.res_lam = take(sizeof(double) * p->nev);
   L.res_cols = take(sizeof(int) * p->nev);
+  const int gd = reorth_dots_groups(h), gu = reorth_update_groups(h, es);
+  if (gd > 1) L.rloc = take((size_t)n * es);              // the locally updated u (column groups)
+  if (gu > 1) L.rd = take((size_t)gu * n * es);           // per-group corrections
   if (p->invert) {   // CG: x, r, q, two directions; partial sums; device scalars
     for (int i = 0; i < 5; ++i) L.cg_vec[i] = take((size_t)n * es);
     L.cg_part = take(sizeof(double) * 2 * (size_t)cg_blocks(n));
@@ -444,6 +447,10 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     cgs = reinterpret_cast<double*>(base + L.cg_s);
   }
   const int ncgb = cg_blocks(n);
+  // column groups of the reorthogonalisation kernels for short vectors
+  const int gd = reorth_dots_groups(h), gu = reorth_update_groups(h, es);
+  cplx<S>* uloc = gd > 1 ? reinterpret_cast<cplx<S>*>(base + L.rloc) : nullptr;
+  cplx<S>* dscr = gu > 1 ? reinterpret_cast<cplx<S>*>(base + L.rd) : nullptr;
 
   const int ndots = reorth_dots_blocks(h);
   const int napply = op_apply_blocks(op);
@@ -571,13 +578,15 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       // first inner products against [V_j, W_j]; then the first update pass
       const double beta_prev = (j > k) ? Tat(j, j - 1) : 0.0;
       tm.start(Timer::DOTS);
-      JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st, scal, beta_prev, j));
+      JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st, scal, beta_prev, j,
+                                        uloc, gd));
       tm.stop();
       JL_HIP(ctx, launch_reduce_cols(dots_part, ndots, stride, stride, coef, st));
       S_.n_dots_launch++;
       S_.bytes_dots += (double)(ncol + 1) * n * es;
       tm.start(Timer::UPDATE);
-      JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st, jsym));
+      JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st, jsym,
+                                          uloc ? uloc : u, gu, dscr));
       tm.stop();
       JL_HIP(ctx, launch_reduce_cols(upd_part, nupd, 1, 1, scal + 2, st));
       S_.n_update_launch++;
@@ -597,13 +606,15 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       while (!(passes >= min_passes && b1 * sqrt2 > b0) && b1 > btol && passes < max_passes) {
         b0 = b1;
         tm.start(Timer::DOTS);
-        JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st));
+        JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st, nullptr, 0.0, 0,
+                                          nullptr, gd));
         tm.stop();
         JL_HIP(ctx, launch_reduce_cols(dots_part, ndots, stride, stride, coef, st));
         S_.n_dots_launch++;
         S_.bytes_dots += (double)(ncol + 1) * n * es;
         tm.start(Timer::UPDATE);
-        JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st, jsym));
+        JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st, jsym,
+                                            u, gu, dscr));
         tm.stop();
         JL_HIP(ctx, launch_reduce_cols(upd_part, nupd, 1, 1, scal + 2, st));
         S_.n_update_launch++;

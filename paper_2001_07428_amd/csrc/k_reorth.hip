@@ -12,6 +12,8 @@
 //         registers (converted to FP64), FP64 products and accumulation.
 // update: u -= V c_v + W c_w with the FP64 coefficients rounded to the
 //         storage type, then ||u||^2 in FP64; one pass over the basis.
+#include <algorithm>
+
 #include "common.h"
 
 namespace jl {
@@ -55,13 +57,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 // LOCAL: before the inner products apply the local three-term step
 // u <- u - t v_jl - beta v_{jl-1} (t read from the device), rounded once to
 // S and stored back by wavefront 0 after every wavefront has read the chunk.
+// Column groups (gridDim.y > 1, for vectors too short to fill the device):
+// block (x, g) takes the columns c with (c / 4) % G == g, every group
+// applies the local step in registers, and only group 0 stores it, to uout
+// (which must then differ from u, since the other groups still read u) and
+// adds ||u||^2.
 template <typename S, int E, bool LOCAL>
 __global__ __launch_bounds__(kReorthThreads) void k_dots(const cplx<S>* __restrict__ V, int64_t ldv,
-                                                         int ncol, cplx<S>* __restrict__ u,
+                                                         int ncol, const cplx<S>* __restrict__ u,
                                                          int64_t h, int chunks,
                                                          double* __restrict__ partial,
                                                          const double* __restrict__ tloc,
-                                                         double beta, int jl) {
+                                                         double beta, int jl,
+                                                         cplx<S>* __restrict__ uout) {
   constexpr int Q = kPairsPerLane / E;     // loads per half per lane per chunk
   constexpr int CH = 64 * E * Q;           // pairs per chunk
   extern __shared__ double acc[];          // 4*ncol + 1 column accumulators
@@ -120,19 +128,19 @@ __global__ __launch_bounds__(kReorthThreads) void k_dots(const cplx<S>* __restri
           ubr[q][e] = (double)(S)(ubr[q][e] - (t_re * br[e] - t_im * bi[e]) - beta * mbr[e]);
           ubi[q][e] = (double)(S)(ubi[q][e] - (t_re * bi[e] + t_im * br[e]) - beta * mbi[e]);
         }
-        if (wave == 0) {
+        if (wave == 0 && blockIdx.y == 0) {
 #pragma unroll
           for (int e = 0; e < E; ++e) {
             cplx<S> a, b;
             a.x = (S)utr[q][e]; a.y = (S)uti[q][e];
             b.x = (S)ubr[q][e]; b.y = (S)ubi[q][e];
-            u[p + e] = a;
-            u[h + p + e] = b;
+            uout[p + e] = a;
+            uout[h + p + e] = b;
           }
         }
       }
     }
-    if (wave == 0) {
+    if (wave == 0 && blockIdx.y == 0) {
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -140,7 +148,7 @@ __global__ __launch_bounds__(kReorthThreads) void k_dots(const cplx<S>* __restri
           unorm += utr[q][e] * utr[q][e] + uti[q][e] * uti[q][e] + ubr[q][e] * ubr[q][e] +
                    ubi[q][e] * ubi[q][e];
     }
-    for (int c = wave; c < ncol; c += 4) {
+    for (int c = (int)blockIdx.y * 4 + wave; c < ncol; c += 4 * (int)gridDim.y) {
       const cplx<S>* vt = V + (int64_t)c * ldv;
       const cplx<S>* vb = vt + h;
       S tr[Q][E], ti[Q][E], br[Q][E], bi[Q][E];
@@ -179,25 +187,34 @@ __global__ __launch_bounds__(kReorthThreads) void k_dots(const cplx<S>* __restri
       }
     }
   }
-  if (wave == 0) {
+  if (wave == 0 && blockIdx.y == 0) {
     unorm = wave_sum(unorm);
     if (lane == 0) acc[4 * ncol] = unorm;
   }
   __syncthreads();
+  // this group's columns (and, for group 0, the norm) of the block's row
   double* out = partial + (int64_t)blockIdx.x * (4 * ncol + 1);
-  for (int i = threadIdx.x; i < 4 * ncol + 1; i += kReorthThreads) out[i] = acc[i];
+  const int G = gridDim.y, g = blockIdx.y;
+  for (int i = threadIdx.x; i < 4 * ncol + 1; i += kReorthThreads)
+    if (i == 4 * ncol ? g == 0 : ((i / 16) % G == g)) out[i] = acc[i];
 }
 
 // u -= sum_c v_c cv_c + w_c cw_c (JSYM; without it the W projection is
 // left out: standard Gram-Schmidt against V alone); each lane keeps the
 // corrections of its E*Q pairs in registers across the column loop (Q loads
 // of 16 bytes per half per column).  partial[blk] = ||u_new||^2.
-template <typename S, int E, int Q, bool JSYM>
+// uout = uin - corrections (uin == uout in place).  With SPLIT (column groups,
+// gridDim.y = G > 1) block (x, g) sums the columns c = g, g + G, ... and
+// stores its corrections to d[g] (2h complex each) instead; k_update_fin
+// then forms uout and the norms.
+template <typename S, int E, int Q, bool JSYM, bool SPLIT>
 __global__ __launch_bounds__(kReorthThreads) void k_update(const cplx<S>* __restrict__ V,
                                                            int64_t ldv, int ncol,
-                                                           cplx<S>* __restrict__ u, int64_t h,
+                                                           const cplx<S>* uin, cplx<S>* uout,
+                                                           int64_t h,
                                                            const double* __restrict__ coef,
-                                                           double* __restrict__ partial) {
+                                                           double* __restrict__ partial,
+                                                           cplx<S>* __restrict__ d) {
   constexpr int CH = 4 * 64 * E * Q;       // pairs per block
   __shared__ double sh[4];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -210,8 +227,9 @@ __global__ __launch_bounds__(kReorthThreads) void k_update(const cplx<S>* __rest
 #pragma unroll
     for (int e = 0; e < E; ++e) dtr[q][e] = dti[q][e] = dbr[q][e] = dbi[q][e] = (S)0;
   }
+  const int c0 = SPLIT ? (int)blockIdx.y : 0, cs = SPLIT ? (int)gridDim.y : 1;
 #pragma unroll 4
-  for (int c = 0; c < ncol; ++c) {
+  for (int c = c0; c < ncol; c += cs) {
     const S cvr = (S)coef[4 * c + 0], cvi = (S)coef[4 * c + 1];
     const S cwr = JSYM ? (S)coef[4 * c + 2] : (S)0, cwi = JSYM ? (S)coef[4 * c + 3] : (S)0;
     const cplx<S>* vt = V + (int64_t)c * ldv;
@@ -238,21 +256,77 @@ __global__ __launch_bounds__(kReorthThreads) void k_update(const cplx<S>* __rest
       }
     }
   }
+  if constexpr (SPLIT) {
+    cplx<S>* dg = d + (int64_t)blockIdx.y * 2 * h;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if (!ok[q]) continue;
+      const int64_t p = p0 + (int64_t)q * 64 * E + lane * E;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        cplx<S> t, b;
+        t.x = dtr[q][e]; t.y = dti[q][e];
+        b.x = dbr[q][e]; b.y = dbi[q][e];
+        dg[p + e] = t;
+        dg[h + p + e] = b;
+      }
+    }
+    return;
+  }
   double nrm = 0.0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     if (!ok[q]) continue;
     const int64_t p = p0 + (int64_t)q * 64 * E + lane * E;
     S tr[E], ti[E], br[E], bi[E];
-    Ld<S, E>::get(u + p, tr, ti);
-    Ld<S, E>::get(u + h + p, br, bi);
+    Ld<S, E>::get(uin + p, tr, ti);
+    Ld<S, E>::get(uin + h + p, br, bi);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       cplx<S> t, b;
       t.x = tr[e] - dtr[q][e]; t.y = ti[e] - dti[q][e];
       b.x = br[e] - dbr[q][e]; b.y = bi[e] - dbi[q][e];
-      u[p + e] = t;
-      u[h + p + e] = b;
+      uout[p + e] = t;
+      uout[h + p + e] = b;
+      nrm += (double)t.x * t.x + (double)t.y * t.y + (double)b.x * b.x + (double)b.y * b.y;
+    }
+  }
+  nrm = wave_sum(nrm);
+  if (lane == 0) sh[wave] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// uout = uin - (d[0] + ... + d[G-1]) (summed in that order, storage type),
+// partial[blk] = ||uout||^2; the block shape of k_update.
+template <typename S, int E, int Q>
+__global__ __launch_bounds__(kReorthThreads) void k_update_fin(const cplx<S>* uin, cplx<S>* uout,
+                                                               int64_t h,
+                                                               const cplx<S>* __restrict__ d,
+                                                               int G, double* __restrict__ partial) {
+  constexpr int CH = 4 * 64 * E * Q;
+  __shared__ double sh[4];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int64_t p0 = (int64_t)blockIdx.x * CH + (int64_t)wave * (64 * E * Q);
+  double nrm = 0.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t pq = p0 + (int64_t)q * 64 * E + lane * E;
+    if (pq >= h) continue;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t p = pq + e;
+      S dtr = 0, dti = 0, dbr = 0, dbi = 0;
+      for (int g = 0; g < G; ++g) {
+        const cplx<S> t = d[(int64_t)g * 2 * h + p], b = d[(int64_t)g * 2 * h + h + p];
+        dtr += t.x; dti += t.y; dbr += b.x; dbi += b.y;
+      }
+      const cplx<S> a = uin[p], c = uin[h + p];
+      cplx<S> t, b;
+      t.x = a.x - dtr; t.y = a.y - dti;
+      b.x = c.x - dbr; b.y = c.y - dbi;
+      uout[p] = t;
+      uout[h + p] = b;
       nrm += (double)t.x * t.x + (double)t.y * t.y + (double)b.x * b.x + (double)b.y * b.y;
     }
   }
@@ -362,31 +436,34 @@ static int dots_chunks(int64_t h) {
 template <typename S>
 hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
                               double* partial, int nblk, hipStream_t st, const double* tloc,
-                              double beta, int jl) {
+                              double beta, int jl, cplx<S>* uout, int groups) {
   if (ncol > kMaxCols) return hipErrorInvalidValue;
   if (tloc && (jl < 0 || jl >= ncol || (beta != 0.0 && jl < 1))) return hipErrorInvalidValue;
+  if (groups < 1) return hipErrorInvalidValue;
+  if (!uout) uout = u;
+  if (tloc && groups > 1 && uout == u) return hipErrorInvalidValue;   // the groups still read u
   const int64_t ch = 64 * kPairsPerLane;
   const int64_t nch = (h + ch - 1) / ch;
   const int per = (int)((nch + nblk - 1) / nblk);
   const unsigned grid = (unsigned)((nch + per - 1) / per);
   if ((int)grid != nblk) return hipErrorInvalidValue;
+  const dim3 g2(grid, (unsigned)groups);
   const size_t lds = sizeof(double) * (4 * (size_t)ncol + 1);
   const bool e2 = sizeof(S) == 4 && h % 2 == 0;
   if (tloc) {
     if (e2)
-      hipLaunchKernelGGL((k_dots<S, sizeof(S) == 4 ? 2 : 1, true>), dim3(grid), dim3(kReorthThreads),
-                         lds, st, V, ldv, ncol, u, h, per, partial, tloc, beta, jl);
+      hipLaunchKernelGGL((k_dots<S, sizeof(S) == 4 ? 2 : 1, true>), g2, dim3(kReorthThreads), lds, st,
+                         V, ldv, ncol, u, h, per, partial, tloc, beta, jl, uout);
     else
-      hipLaunchKernelGGL((k_dots<S, 1, true>), dim3(grid), dim3(kReorthThreads), lds, st, V, ldv,
-                         ncol, u, h, per, partial, tloc, beta, jl);
+      hipLaunchKernelGGL((k_dots<S, 1, true>), g2, dim3(kReorthThreads), lds, st, V, ldv, ncol, u, h,
+                         per, partial, tloc, beta, jl, uout);
   } else {
     if (e2)
-      hipLaunchKernelGGL((k_dots<S, sizeof(S) == 4 ? 2 : 1, false>), dim3(grid),
-                         dim3(kReorthThreads), lds, st, V, ldv, ncol, u, h, per, partial, tloc,
-                         beta, jl);
+      hipLaunchKernelGGL((k_dots<S, sizeof(S) == 4 ? 2 : 1, false>), g2, dim3(kReorthThreads), lds,
+                         st, V, ldv, ncol, u, h, per, partial, tloc, beta, jl, uout);
     else
-      hipLaunchKernelGGL((k_dots<S, 1, false>), dim3(grid), dim3(kReorthThreads), lds, st, V, ldv,
-                         ncol, u, h, per, partial, tloc, beta, jl);
+      hipLaunchKernelGGL((k_dots<S, 1, false>), g2, dim3(kReorthThreads), lds, st, V, ldv, ncol, u,
+                         h, per, partial, tloc, beta, jl, uout);
   }
   return hipGetLastError();
 }
@@ -400,38 +477,63 @@ int reorth_dots_blocks(int64_t h) {
 }
 
 template <typename S, int E, int Q>
-static void launch_update_q(unsigned grid, const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u,
-                            int64_t h, const double* coef, double* partial, hipStream_t st,
-                            bool jsym) {
+static void launch_update_q(unsigned grid, const cplx<S>* V, int64_t ldv, int ncol,
+                            const cplx<S>* uin, cplx<S>* u, int64_t h, const double* coef,
+                            double* partial, hipStream_t st, bool jsym, int groups, cplx<S>* d) {
+  if (groups > 1) {
+    const dim3 g2(grid, (unsigned)groups);
+    if (jsym)
+      hipLaunchKernelGGL((k_update<S, E, Q, true, true>), g2, dim3(kReorthThreads), 0, st, V, ldv,
+                         ncol, uin, u, h, coef, partial, d);
+    else
+      hipLaunchKernelGGL((k_update<S, E, Q, false, true>), g2, dim3(kReorthThreads), 0, st, V, ldv,
+                         ncol, uin, u, h, coef, partial, d);
+    hipLaunchKernelGGL((k_update_fin<S, E, Q>), dim3(grid), dim3(kReorthThreads), 0, st, uin, u, h,
+                       (const cplx<S>*)d, groups, partial);
+    return;
+  }
   if (jsym)
-    hipLaunchKernelGGL((k_update<S, E, Q, true>), dim3(grid), dim3(kReorthThreads), 0, st, V, ldv, ncol,
-                       u, h, coef, partial);
+    hipLaunchKernelGGL((k_update<S, E, Q, true, false>), dim3(grid), dim3(kReorthThreads), 0, st, V,
+                       ldv, ncol, uin, u, h, coef, partial, d);
   else
-    hipLaunchKernelGGL((k_update<S, E, Q, false>), dim3(grid), dim3(kReorthThreads), 0, st, V, ldv,
-                       ncol, u, h, coef, partial);
+    hipLaunchKernelGGL((k_update<S, E, Q, false, false>), dim3(grid), dim3(kReorthThreads), 0, st, V,
+                       ldv, ncol, uin, u, h, coef, partial, d);
 }
 
 template <typename S>
 hipError_t launch_reorth_update(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
                                 const double* coef, double* partial, int nblk, hipStream_t st,
-                                bool jsym) {
+                                bool jsym, const cplx<S>* uin, int groups, cplx<S>* d) {
   const int E = elems_per_load(h, (int)sizeof(cplx<S>));
   const int ppl = update_ppl(h, E);
   const unsigned grid = (unsigned)((h + 256 * (int64_t)ppl - 1) / (256 * (int64_t)ppl));
   if ((int)grid != nblk) return hipErrorInvalidValue;
+  if (groups < 1 || (groups > 1 && !d)) return hipErrorInvalidValue;
+  if (!uin) uin = u;
   if (E == 2) {
     if constexpr (sizeof(S) == 4) {
-      if (ppl == 8) launch_update_q<S, 2, 4>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
-      else if (ppl == 4) launch_update_q<S, 2, 2>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
-      else launch_update_q<S, 2, 1>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
+      if (ppl == 8) launch_update_q<S, 2, 4>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
+      else if (ppl == 4) launch_update_q<S, 2, 2>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
+      else launch_update_q<S, 2, 1>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
     }
   } else {
-    if (ppl == 8) launch_update_q<S, 1, 8>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
-    else if (ppl == 4) launch_update_q<S, 1, 4>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
-    else if (ppl == 2) launch_update_q<S, 1, 2>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
-    else launch_update_q<S, 1, 1>(grid, V, ldv, ncol, u, h, coef, partial, st, jsym);
+    if (ppl == 8) launch_update_q<S, 1, 8>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
+    else if (ppl == 4) launch_update_q<S, 1, 4>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
+    else if (ppl == 2) launch_update_q<S, 1, 2>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
+    else launch_update_q<S, 1, 1>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
   }
   return hipGetLastError();
+}
+
+// Column groups for vectors too short to fill the device (see k_dots and
+// k_update): enough groups for about 256 dots and 512 update blocks, at most 16.
+int reorth_dots_groups(int64_t h) {
+  const int nb = reorth_dots_blocks(h);
+  return nb >= 128 ? 1 : std::min(16, std::max(1, 256 / nb));
+}
+int reorth_update_groups(int64_t h, int es) {
+  const int nb = reorth_update_blocks(h, es);
+  return nb >= 128 ? 1 : std::min(16, std::max(1, 512 / nb));
 }
 
 hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int ncols, double* out,
@@ -479,9 +581,10 @@ hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t l
 #define JL_INST(S)                                                                                \
   template hipError_t launch_reorth_dots<S>(const cplx<S>*, int64_t, int, cplx<S>*, int64_t,       \
                                             double*, int, hipStream_t, const double*, double,     \
-                                            int);                                                 \
+                                            int, cplx<S>*, int);                                  \
   template hipError_t launch_reorth_update<S>(const cplx<S>*, int64_t, int, cplx<S>*, int64_t,    \
-                                              const double*, double*, int, hipStream_t, bool);    \
+                                              const double*, double*, int, hipStream_t, bool,     \
+                                              const cplx<S>*, int, cplx<S>*);                     \
   template hipError_t launch_scale<S>(cplx<S>*, int64_t, double, hipStream_t);                    \
   template hipError_t launch_fill<S>(cplx<S>*, int64_t, double, hipStream_t);                     \
   template hipError_t launch_pair<S>(const cplx<S>*, int64_t, cplx<S>*, int64_t, int64_t, int,    \
