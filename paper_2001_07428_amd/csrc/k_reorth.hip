@@ -22,6 +22,7 @@ namespace {
 constexpr int kReorthThreads = 256;   // 4 wavefronts
 constexpr int kPairsPerLane = 4;      // pairs of u each lane holds per chunk (more resident waves than 8)
 constexpr int kMaxCols = 2048;        // LDS column accumulators
+constexpr int kMaxGroups = 16;        // column groups for short vectors
 
 // E = complex elements per 16-byte load (2 for FP32 with an even half
 // length, else 1).
@@ -317,9 +318,12 @@ __global__ __launch_bounds__(kReorthThreads) void k_update_fin(const cplx<S>* ui
     for (int e = 0; e < E; ++e) {
       const int64_t p = pq + e;
       S dtr = 0, dti = 0, dbr = 0, dbi = 0;
-      for (int g = 0; g < G; ++g) {
-        const cplx<S> t = d[(int64_t)g * 2 * h + p], b = d[(int64_t)g * 2 * h + h + p];
-        dtr += t.x; dti += t.y; dbr += b.x; dbi += b.y;
+#pragma unroll
+      for (int g = 0; g < kMaxGroups; ++g) {   // unrolled: the loads are independent
+        if (g < G) {
+          const cplx<S> t = d[(int64_t)g * 2 * h + p], b = d[(int64_t)g * 2 * h + h + p];
+          dtr += t.x; dti += t.y; dbr += b.x; dbi += b.y;
+        }
       }
       const cplx<S> a = uin[p], c = uin[h + p];
       cplx<S> t, b;
@@ -529,11 +533,11 @@ hipError_t launch_reorth_update(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>
 // k_update): enough groups for about 256 dots and 512 update blocks, at most 16.
 int reorth_dots_groups(int64_t h) {
   const int nb = reorth_dots_blocks(h);
-  return nb >= 128 ? 1 : std::min(16, std::max(1, 256 / nb));
+  return nb >= 128 ? 1 : std::min(kMaxGroups, std::max(1, 256 / nb));
 }
 int reorth_update_groups(int64_t h, int es) {
   const int nb = reorth_update_blocks(h, es);
-  return nb >= 128 ? 1 : std::min(16, std::max(1, 512 / nb));
+  return nb >= 128 ? 1 : std::min(kMaxGroups, std::max(1, 512 / nb));
 }
 
 hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int ncols, double* out,
