@@ -53,7 +53,7 @@ enum {
   JL_EINVAL = -1,          /* invalid argument (message says which)        */
   JL_EHIP = -2,            /* a HIP runtime call failed                    */
   JL_ENOMEM = -3,          /* workspace smaller than jl_workspace_bytes    */
-  JL_EUNSUPPORTED = -4,    /* valid request this build does not implement  */
+  JL_EUNSUPPORTED = -4,    /* valid request the library does not implement */
   JL_NOT_CONVERGED = 1,    /* max_cycles reached; first stats.icnv valid   */
   JL_BREAKDOWN = 2         /* invariant subspace reached before nev pairs  */
 };
