@@ -142,7 +142,8 @@ __global__ __launch_bounds__(kTekScan) void k_tek_c2m_diag(TekArgs<S> a, TekSrc<
 // transpose}.  Tile 64 x 64 per block of four wavefronts (2 x 2, 32 x 32 each
 // as 2 x 2 MFMA 16 x 16 tiles), K staged through two LDS buffers in steps of
 // 16 as separate real and imaginary planes, the next step's loads in flight
-// during the current step's products; a complex product is four real MFMAs.
+// during the current step's products; a complex step is three real MFMAs in
+// FP32 and four in FP64.
 constexpr int ZT = 64, ZBK = 16, ZLD = ZT + 16;   // row stride: two rows per 32 banks
 
 template <typename S> struct ZMfma;
@@ -165,46 +166,62 @@ __device__ __forceinline__ void ld4(const cplx<S>* p, cplx<S> (&o)[4]) {
   for (int e = 0; e < 4; ++e) o[e] = p[e];
 }
 
+// Nk = N rounded up to 16: the K loop and the 16 x 16 MFMA tiles stop there
+// (the matrices are zero beyond N, so the skipped work is all zeros and the
+// accumulators of skipped tiles store the zeros the padding must hold).
 template <typename S>
-__global__ __launch_bounds__(256) void k_zgemm(const ZJob<S>* __restrict__ jobs, int Np,
+__global__ __launch_bounds__(256) void k_zgemm(const ZJob<S>* __restrict__ jobs, int Np, int Nk,
                                                const double* __restrict__ skip) {
   if (skip && *skip != 0.0) return;
   using MF = ZMfma<S>;
   using v4 = typename MF::v4;
+  // FP32: three real products per complex step, Ar Br, Ai Bi and
+  // (Ar + Ai)(Br + Bi) (Re = first - second, Im = third - first - second),
+  // from a third LDS plane of sums; FP64 keeps four (its planes are twice
+  // the size, and a fifth and sixth would leave one workgroup per CU).
+  constexpr bool M3 = sizeof(S) == 4;
+  constexpr int P3 = M3 ? 2 : 1, K3 = M3 ? ZBK : 1, L3 = M3 ? ZLD : 1;
   __shared__ S Ar[2][ZBK][ZLD], Ai[2][ZBK][ZLD], Br[2][ZBK][ZLD], Bi[2][ZBK][ZLD];
+  __shared__ S As[P3][K3][L3], Bs[P3][K3][L3];
   const ZJob<S> jb = jobs[blockIdx.y];
   const int tiles = Np / ZT;
   const int i0 = (blockIdx.x / tiles) * ZT, j0 = (blockIdx.x % tiles) * ZT;
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave / 2, wn = wave % 2;
-  v4 cr[2][2], ci[2][2];
+  v4 cr[2][2], ci[2][2], c3[2][2];   // M3: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) cr[i][j] = ci[i][j] = v4{0, 0, 0, 0};
+    for (int j = 0; j < 2; ++j) cr[i][j] = ci[i][j] = c3[i][j] = v4{0, 0, 0, 0};
 
   // loader roles: 4 complex of A and 4 of B per thread and K step
   const bool an = jb.opA == 0, bn = jb.opB == 0;
-  const int ai = an ? tid / 4 : (tid % 16) * 4, ak = an ? (tid % 4) * 4 : tid / 16;
+  const int ai0 = an ? tid / 4 : (tid % 16) * 4, ak = an ? (tid % 4) * 4 : tid / 16;
   const int bk = bn ? tid / 16 : (tid % 4) * 4, bj = bn ? (tid % 16) * 4 : tid / 4;
   cplx<S> va[4], vb[4];
   auto load = [&](int k0) {
-    if (an) ld4<S>(jb.A + (int64_t)(i0 + ai) * Np + k0 + ak, va);   // A[i][k], k contiguous
-    else ld4<S>(jb.A + (int64_t)(k0 + ak) * Np + i0 + ai, va);      // A[k][i], i contiguous
+    if (an) ld4<S>(jb.A + (int64_t)(i0 + ai0) * Np + k0 + ak, va);   // A[i][k], k contiguous
+    else ld4<S>(jb.A + (int64_t)(k0 + ak) * Np + i0 + ai0, va);      // A[k][i], i contiguous
     if (bn) ld4<S>(jb.B + (int64_t)(k0 + bk) * Np + j0 + bj, vb);   // B[k][j], j contiguous
     else ld4<S>(jb.B + (int64_t)(j0 + bj) * Np + k0 + bk, vb);      // B[j][k], k contiguous
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      if (an) { Ar[buf][ak + e][ai] = va[e].x; Ai[buf][ak + e][ai] = va[e].y; }
-      else { Ar[buf][ak][ai + e] = va[e].x; Ai[buf][ak][ai + e] = -va[e].y; }   // conj
-      if (bn) { Br[buf][bk][bj + e] = vb[e].x; Bi[buf][bk][bj + e] = vb[e].y; }
-      else { Br[buf][bk + e][bj] = vb[e].x; Bi[buf][bk + e][bj] = -vb[e].y; }   // conj
+      const S ar = va[e].x, ai = an ? va[e].y : -va[e].y;   // conj for op C
+      const S br = vb[e].x, bi = bn ? vb[e].y : -vb[e].y;
+      const int ka = an ? ak + e : ak, ia = an ? ai0 : ai0 + e;
+      const int kb = bn ? bk : bk + e, jb = bn ? bj + e : bj;
+      Ar[buf][ka][ia] = ar; Ai[buf][ka][ia] = ai;
+      Br[buf][kb][jb] = br; Bi[buf][kb][jb] = bi;
+      if constexpr (M3) {
+        As[buf][ka][ia] = ar + ai;
+        Bs[buf][kb][jb] = br + bi;
+      }
     }
   };
 
-  const int nk = Np / ZBK;
+  const int nk = Nk / ZBK;
   load(0);
   store(0);
   __syncthreads();
@@ -214,22 +231,34 @@ __global__ __launch_bounds__(256) void k_zgemm(const ZJob<S>* __restrict__ jobs,
 #pragma unroll
     for (int kk = 0; kk < ZBK; kk += 4) {
       const int kr = kk + lane / 16;
-      S ar[2], ai2[2], br[2], bi[2];
+      S ar[2], ai2[2], br[2], bi[2], as[2], bs[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        ar[t] = Ar[cur][kr][wm * 32 + t * 16 + lane % 16];
-        ai2[t] = Ai[cur][kr][wm * 32 + t * 16 + lane % 16];
-        br[t] = Br[cur][kr][wn * 32 + t * 16 + lane % 16];
-        bi[t] = Bi[cur][kr][wn * 32 + t * 16 + lane % 16];
+        const int ia = wm * 32 + t * 16 + lane % 16, jb2 = wn * 32 + t * 16 + lane % 16;
+        ar[t] = Ar[cur][kr][ia];
+        ai2[t] = Ai[cur][kr][ia];
+        br[t] = Br[cur][kr][jb2];
+        bi[t] = Bi[cur][kr][jb2];
+        if constexpr (M3) {
+          as[t] = As[cur][kr][ia];
+          bs[t] = Bs[cur][kr][jb2];
+        }
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          cr[i][j] = MF::op(ar[i], br[j], cr[i][j]);
-          cr[i][j] = MF::op(-ai2[i], bi[j], cr[i][j]);
-          ci[i][j] = MF::op(ar[i], bi[j], ci[i][j]);
-          ci[i][j] = MF::op(ai2[i], br[j], ci[i][j]);
+          if (i0 + wm * 32 + i * 16 >= Nk || j0 + wn * 32 + j * 16 >= Nk) continue;   // wave-uniform
+          if constexpr (M3) {
+            cr[i][j] = MF::op(ar[i], br[j], cr[i][j]);
+            ci[i][j] = MF::op(ai2[i], bi[j], ci[i][j]);
+            c3[i][j] = MF::op(as[i], bs[j], c3[i][j]);
+          } else {
+            cr[i][j] = MF::op(ar[i], br[j], cr[i][j]);
+            cr[i][j] = MF::op(-ai2[i], bi[j], cr[i][j]);
+            ci[i][j] = MF::op(ar[i], bi[j], ci[i][j]);
+            ci[i][j] = MF::op(ai2[i], br[j], ci[i][j]);
+          }
         }
     }
     if (kt + 1 < nk) store(cur ^ 1);   // the other buffer: last read before the previous barrier
@@ -245,8 +274,13 @@ __global__ __launch_bounds__(256) void k_zgemm(const ZJob<S>* __restrict__ jobs,
         const int row = i0 + wm * 32 + i * 16 + 4 * (lane / 16) + r;
         const int col = j0 + wn * 32 + j * 16 + lane % 16;
         cplx<S> o;
-        o.x = cr[i][j][r];
-        o.y = ci[i][j][r];
+        if constexpr (M3) {
+          o.x = cr[i][j][r] - ci[i][j][r];
+          o.y = c3[i][j][r] - cr[i][j][r] - ci[i][j][r];
+        } else {
+          o.x = cr[i][j][r];
+          o.y = ci[i][j][r];
+        }
         jb.C[(int64_t)row * Np + col] = o;
       }
 }
@@ -395,8 +429,8 @@ __device__ __forceinline__ void put(const TekOut<S>& o, int64_t i, double yr, do
 // y = coefficients of Z = D X (off-diagonal generators): s = Z_jk + Z_kj,
 // a = i (Z_jk - Z_kj) for every spin; the diagonal entries Z_jj go to a.zd
 // for the diagonal kernel.  One block per pair of 32 x 32 tiles (I, K),
-// I <= K: the tiles Z[I][K] and Z[K][I] are read row by row into LDS, so
-// both Z_jk and its mirror Z_kj arrive by coalesced loads.
+// I <= K, and spin (gridDim.y): the tiles Z[I][K] and Z[K][I] are read row
+// by row into LDS, so both Z_jk and its mirror Z_kj arrive by coalesced loads.
 constexpr int MT = 32;
 template <typename S>
 __global__ __launch_bounds__(kTekThreads) void k_tek_m2c(TekArgs<S> a, TekOut<S> o) {
@@ -410,7 +444,8 @@ __global__ __launch_bounds__(kTekThreads) void k_tek_m2c(TekArgs<S> a, TekOut<S>
   const int64_t P = (int64_t)N * (N - 1) / 2;
   const int64_t M = (int64_t)a.Np * a.Np;
   double acc[2] = {0.0, 0.0};
-  for (int al = 0; al < 4; ++al) {
+  {
+    const int al = blockIdx.y;   // one spin per block row of the grid
     const cplx<S>* Z = a.X + al * M;
     for (int i = threadIdx.x; i < MT * MT; i += kTekThreads) {
       const int r = i / MT, c = i % MT;   // within Np (zero padding beyond N)
@@ -441,11 +476,12 @@ __global__ __launch_bounds__(kTekThreads) void k_tek_m2c(TekArgs<S> a, TekOut<S>
     acc[0] = tek_block_sum(acc[0], sh);
     acc[1] = tek_block_sum(acc[1], sh);
     if (threadIdx.x == 0) {
+      const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
       if (o.y) {
-        o.part[2 * blockIdx.x] = acc[0];
-        o.part[2 * blockIdx.x + 1] = acc[1];
+        o.part[2 * blk] = acc[0];
+        o.part[2 * blk + 1] = acc[1];
       } else {
-        o.part[(int64_t)blockIdx.x * o.stride + o.col] = acc[0];
+        o.part[blk * o.stride + o.col] = acc[0];
       }
     }
   }
@@ -487,10 +523,11 @@ __global__ __launch_bounds__(kTekScan) void k_tek_out_diag(TekArgs<S> a, TekOut<
   }
 }
 
-int out_blocks(int N) {   // tile pairs I <= K of the output kernel
+int m2c_tiles(int N) {   // tile pairs I <= K of the output kernel
   const int T = (N + MT - 1) / MT;
   return T * (T + 1) / 2;
 }
+int out_blocks(int N) { return 4 * m2c_tiles(N); }   // one grid row per spin
 
 // The whole apply: coefficients -> X, D^H (in place on X), D, coefficients.
 template <typename S>
@@ -500,19 +537,20 @@ hipError_t tek_apply(const TekArgs<S>& a, const TekSrc<S>& src, const TekOut<S>&
   const int64_t P = (int64_t)N * (N - 1) / 2;
   const dim3 gz((unsigned)((a.Np / ZT) * (a.Np / ZT)), 16u);
   const dim3 gN((unsigned)(((int64_t)N * N + kTekThreads - 1) / kTekThreads));
+  const int Nk = (N + ZBK - 1) / ZBK * ZBK;
   hipLaunchKernelGGL(k_tek_c2m<S>, dim3((unsigned)((4 * P + kTekThreads - 1) / kTekThreads)),
                      dim3(kTekThreads), 0, st, a, src);
   hipLaunchKernelGGL(k_tek_c2m_diag<S>, dim3(4), dim3(kTekScan), 0, st, a, src);
   for (int pass = 0; pass < 2; ++pass) {   // D^H, then D
     if (pass == 0) hipLaunchKernelGGL((k_tek_half<S, true>), gN, dim3(kTekThreads), 0, st, a);
     else hipLaunchKernelGGL((k_tek_half<S, false>), gN, dim3(kTekThreads), 0, st, a);
-    hipLaunchKernelGGL(k_zgemm<S>, gz, dim3(256), 0, st, a.jobs1, a.Np, a.skip);
-    hipLaunchKernelGGL(k_zgemm<S>, gz, dim3(256), 0, st, a.jobs2, a.Np, a.skip);
+    hipLaunchKernelGGL(k_zgemm<S>, gz, dim3(256), 0, st, a.jobs1, a.Np, Nk, a.skip);
+    hipLaunchKernelGGL(k_zgemm<S>, gz, dim3(256), 0, st, a.jobs2, a.Np, Nk, a.skip);
     if (pass == 0) hipLaunchKernelGGL((k_tek_combine<S, true>), gN, dim3(kTekThreads), 0, st, a);
     else hipLaunchKernelGGL((k_tek_combine<S, false>), gN, dim3(kTekThreads), 0, st, a);
   }
   const int nb = out_blocks(N);
-  hipLaunchKernelGGL(k_tek_m2c<S>, dim3((unsigned)nb), dim3(kTekThreads), 0, st, a, o);
+  hipLaunchKernelGGL(k_tek_m2c<S>, dim3((unsigned)m2c_tiles(N), 4u), dim3(kTekThreads), 0, st, a, o);
   hipLaunchKernelGGL(k_tek_out_diag<S>, dim3(4), dim3(kTekScan), 0, st, a, o, nb);
   return hipGetLastError();
 }
