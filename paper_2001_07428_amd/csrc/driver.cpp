@@ -10,6 +10,11 @@
 //     host); one stream synchronisation per pass;
 //   - once per cycle the sorted Ritz values, the last row of Z and the true
 //     residuals of the candidates.
+// In invert mode each step's u = A^-1 v_j comes from conjugate gradients
+// run entirely on the device (k_cg.hip); the host queues batches of
+// iterations and looks at the device's done flag between batches.  The
+// operators are the dense blocks, the 4D stencil and the Case B operator
+// (k_tek.hip), all in the layout where J is the canonical [[0, -I], [I, 0]].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -7,10 +7,15 @@
 // Stencil: one thread per lattice site computes all 4 internal components of
 // both halves; the link U_mu(x) is read once for the forward hop of both
 // halves and U_mu(x - mu) once for the backward hop, from the operator's
-// site-fastest copy of the links (coalesced across the wavefront).
+// site-fastest copy of the links (coalesced across the wavefront).  On
+// small FP32 lattices four threads share a site, one direction each
+// (k_stencil_apply4), for four times the wavefronts.
 // Dense: one wavefront per row of [A11 A12]; the row is read once for both
 // right-hand sides [a; b] and [conj(b); -conj(a)] (u_bot = conj(A11 conj(b) -
 // A12 conj(a)) because A11^T = conj(A11) and A12^H = -conj(A12)).
+// Every apply can take its operand as the conjugate-gradient direction
+// p = r + beta p_old, formed on the fly and stored (Operand below), and can
+// return at once on a device flag (StencilArgs::skip, DenseArgs::skip).
 #include "common.h"
 
 namespace jl {

@@ -155,3 +155,18 @@ def test_tek_rejects_bad_sizes(ctx):
     U1 = torch.zeros((4, 1, 1), dtype=torch.complex128, device="cuda:0")
     with pytest.raises(J.JLError):
         J.jl_op_create_tek(ctx, U1, KAPPA)
+
+
+def test_tek_standard_mode_finds_pairs_twice(ctx):
+    from paper_2001_07428_amd import jlanczos as J
+    say("tek standard N5")
+    N = 5
+    Us = inputs.haar_su(71, N, 4)
+    na = N * N - 1
+    A = tek.dense_A(Us, KAPPA)
+    P = tek.canonical_matrix(np.kron(tek.J4.real, np.eye(na)))
+    ref, _ = jsym.brute(P.T @ A @ P)
+    op = _op(ctx, Us, False)
+    out = J.jl_solve(op, 8, 40, 16, 1e-10, standard=True)
+    assert out.status == J.JL_OK
+    assert np.abs(np.sort(out.evals) - np.repeat(ref[:4], 2)).max() < 1e-10 * ref[-1]
