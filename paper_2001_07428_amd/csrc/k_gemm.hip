@@ -36,7 +36,7 @@ constexpr int kThreads = 256;
 
 // S: storage type of A and C; T: MFMA (accumulation) type, also the type of B.
 template <typename S, typename T>
-__global__ __launch_bounds__(kThreads) void k_gemm_nn(const S* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A, int64_t lda,
                                                       const T* __restrict__ B, int64_t ldb,
                                                       S* __restrict__ C, int64_t ldc, int64_t M,
                                                       int N, int K, int64_t tiles_m, int tiles_n) {
