@@ -469,7 +469,7 @@ __global__ void k_links_site_fastest(const cplx<S>* __restrict__ src, cplx<S>* _
 }
 
 // ------------------------------------------------------------------ dense
-constexpr int kDenseThreads = 256;   // 4 rows per block, one wavefront per row
+constexpr int kDenseThreads = 256;   // k_dense_resid: one wavefront per row
 
 template <typename S, typename C, typename X>
 __device__ __forceinline__ void dense_row(const DenseArgs<S>& a, const X& xo, int64_t r, cx<C>& s1,
@@ -499,6 +499,47 @@ __device__ __forceinline__ void dense_row(const DenseArgs<S>& a, const X& xo, in
   s2 = q;
 }
 
+// k_dense_apply: kDenseRows rows per block.  The block's threads stride over
+// the columns together (every wavefront reads 512 contiguous bytes of each
+// row per column step), so the operand is read once per kDenseRows rows, and
+// each thread issues the loads of kDenseUnroll column steps before any
+// product, which keeps enough bytes in flight to stream the matrix.
+constexpr int kDenseRows = 4;
+template <typename S> constexpr int dense_unroll() { return sizeof(S) == 4 ? 4 : 2; }
+
+template <typename S, int U, bool CHECK, typename X>
+__device__ __forceinline__ void dense_cols(const DenseArgs<S>& a, const X& xo,
+                                           const cplx<S>* const r11[kDenseRows],
+                                           const cplx<S>* const r12[kDenseRows], int64_t c0,
+                                           cx<S> p[kDenseRows], cx<S> q[kDenseRows]) {
+  cplx<S> va[U], vb[U], m11[U][kDenseRows], m12[U][kDenseRows];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t c = c0 + (int64_t)u * kDenseThreads;
+    const bool ok = !CHECK || c < a.h;
+    const int64_t cc = ok ? c : 0;   // a clamped, in-bounds load; its terms are zeroed
+    va[u] = xo.elem(cc);
+    vb[u] = xo.elem(a.h + cc);
+    if (!ok) va[u].x = va[u].y = vb[u].x = vb[u].y = (S)0;
+#pragma unroll
+    for (int k = 0; k < kDenseRows; ++k) {
+      m11[u][k] = r11[k][cc];
+      m12[u][k] = r12[k][cc];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+#pragma unroll
+    for (int k = 0; k < kDenseRows; ++k) {
+      // s1 += A11 a + A12 b;  s2 += A11 conj(b) - A12 conj(a)
+      mac(p[k], m11[u][k].x, m11[u][k].y, va[u].x, va[u].y);
+      mac(p[k], m12[u][k].x, m12[u][k].y, vb[u].x, vb[u].y);
+      mac(q[k], m11[u][k].x, m11[u][k].y, vb[u].x, -vb[u].y);
+      mac(q[k], m12[u][k].x, m12[u][k].y, -va[u].x, va[u].y);
+    }
+  }
+}
+
 // As k_stencil_apply: with DIR the operand is p = r + beta p_old (p_old = x)
 // and p is stored to pnew.
 template <typename S, bool DIR>
@@ -510,31 +551,69 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(DenseArgs<S> a,
                                                                const double* __restrict__ dbeta,
                                                                cplx<S>* __restrict__ pnew) {
   if (a.skip && *a.skip != 0.0) return;   // uniform over the grid
-  __shared__ double sh[kDenseThreads / 64];
-  const int64_t r = (int64_t)blockIdx.x * (kDenseThreads / 64) + threadIdx.x / 64;
+  constexpr int U = dense_unroll<S>(), NW = kDenseThreads / 64, R = kDenseRows;
+  __shared__ S red[NW][R][4];
+  __shared__ double sh[NW];
+  const int64_t r0 = (int64_t)blockIdx.x * R;
   Operand<S, DIR> xo;
   if constexpr (DIR) xo = Operand<S, true>{dr, x, *dbeta};
   else xo = Operand<S, false>{x + (int64_t)blockIdx.y * ld};
   cplx<S>* yc = y + (int64_t)blockIdx.y * ld;
+  const cplx<S>* r11[R];
+  const cplx<S>* r12[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {   // rows past the end repeat the last row; not stored
+    const int64_t r = r0 + k < a.h ? r0 + k : a.h - 1;
+    r11[k] = a.A11 + r * a.ld;
+    r12[k] = a.A12 + r * a.ld;
+  }
+  cx<S> p[R], q[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) p[k] = q[k] = cx<S>{(S)0, (S)0};
+  int64_t c0 = threadIdx.x;
+  for (; c0 + (int64_t)(U - 1) * kDenseThreads < a.h; c0 += (int64_t)U * kDenseThreads)
+    dense_cols<S, U, false>(a, xo, r11, r12, c0, p, q);
+  if (c0 < a.h) dense_cols<S, U, true>(a, xo, r11, r12, c0, p, q);
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      p[k].re += __shfl_xor(p[k].re, o);
+      p[k].im += __shfl_xor(p[k].im, o);
+      q[k].re += __shfl_xor(q[k].re, o);
+      q[k].im += __shfl_xor(q[k].im, o);
+    }
+    if (lane == 0) {
+      red[w][k][0] = p[k].re;
+      red[w][k][1] = p[k].im;
+      red[w][k][2] = q[k].re;
+      red[w][k][3] = q[k].im;
+    }
+  }
+  __syncthreads();
   double are = 0.0, aim = 0.0;
-  if (r < a.h) {
-    cx<S> s1, s2;
-    dense_row<S, S>(a, xo, r, s1, s2);
-    if (threadIdx.x % 64 == 0) {
-      cplx<S> t, b;
-      t.x = s1.re; t.y = s1.im;
-      b.x = s2.re; b.y = -s2.im;   // u_bot = conj(s2)
-      yc[r] = t;
-      yc[a.h + r] = b;
-      if (apart || DIR) {
-        const cplx<S> xt = xo.elem(r), xb = xo.elem(a.h + r);
-        if constexpr (DIR) {
-          pnew[r] = xt;
-          pnew[a.h + r] = xb;
-        }
-        are = (double)xt.x * t.x + (double)xt.y * t.y + (double)xb.x * b.x + (double)xb.y * b.y;
-        aim = (double)xt.x * t.y - (double)xt.y * t.x + (double)xb.x * b.y - (double)xb.y * b.x;
+  const int k = threadIdx.x;
+  if (k < R && r0 + k < a.h) {   // thread k stores row r0 + k
+    S v[4] = {(S)0, (S)0, (S)0, (S)0};
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] += red[ww][k][e];
+    const int64_t r = r0 + k;
+    cplx<S> t, b;
+    t.x = v[0]; t.y = v[1];
+    b.x = v[2]; b.y = -v[3];   // u_bot = conj(s2)
+    yc[r] = t;
+    yc[a.h + r] = b;
+    if (apart || DIR) {
+      const cplx<S> xt = xo.elem(r), xb = xo.elem(a.h + r);
+      if constexpr (DIR) {
+        pnew[r] = xt;
+        pnew[a.h + r] = xb;
       }
+      are = (double)xt.x * t.x + (double)xt.y * t.y + (double)xb.x * b.x + (double)xb.y * b.y;
+      aim = (double)xt.x * t.y - (double)xt.y * t.x + (double)xb.x * b.y - (double)xb.y * b.x;
     }
   }
   if (apart) {
@@ -590,7 +669,7 @@ int stencil_apply_blocks(int64_t V, int es) {
   return stencil_quad(V, es) ? (int)((4 * V + kStencilThreads - 1) / kStencilThreads)
                              : stencil_resid_blocks(V);
 }
-int dense_apply_blocks(int64_t h) { return (int)((h + kDenseThreads / 64 - 1) / (kDenseThreads / 64)); }
+int dense_apply_blocks(int64_t h) { return (int)((h + kDenseRows - 1) / kDenseRows); }
 int dense_resid_blocks(int64_t h) { return (int)((h + kDenseThreads / 64 - 1) / (kDenseThreads / 64)); }
 
 template <typename S, bool DIR>
@@ -659,7 +738,7 @@ template <typename S>
 hipError_t launch_dense_apply(const DenseArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ldv,
                               int nrhs, double* apart, hipStream_t st) {
   if (apart && nrhs != 1) return hipErrorInvalidValue;
-  dim3 grid((unsigned)dense_resid_blocks(a.h), (unsigned)nrhs);
+  dim3 grid((unsigned)dense_apply_blocks(a.h), (unsigned)nrhs);
   hipLaunchKernelGGL((k_dense_apply<S, false>), grid, dim3(kDenseThreads), 0, st, a, x, y, ldv,
                      apart, nullptr, nullptr, nullptr);
   return hipGetLastError();
@@ -669,7 +748,7 @@ template <typename S>
 hipError_t launch_dense_apply_dir(const DenseArgs<S>& a, const cplx<S>* r, const cplx<S>* pold,
                                   const double* beta, cplx<S>* pnew, cplx<S>* y, double* apart,
                                   hipStream_t st) {
-  dim3 grid((unsigned)dense_resid_blocks(a.h), 1u);
+  dim3 grid((unsigned)dense_apply_blocks(a.h), 1u);
   hipLaunchKernelGGL((k_dense_apply<S, true>), grid, dim3(kDenseThreads), 0, st, a, pold, y,
                      2 * a.h, apart, r, beta, pnew);
   return hipGetLastError();

@@ -57,7 +57,7 @@ def test_stencil_apply_large(ctx, L, mixed):
     assert _rel(y, jsym.stencil_apply(U, B, L, x[0])) < (2e-6 if mixed else 1e-14)
 
 
-@pytest.mark.parametrize("h", [100, 33, 1])
+@pytest.mark.parametrize("h", [100, 33, 1, 1500, 2053])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_dense_apply(ctx, h, mixed):
     from paper_2001_07428_amd import jlanczos as J
