@@ -166,6 +166,16 @@ int reorth_update_groups(int64_t h, int es);
 // out[c] = sum_b partial[b * stride + c] for c < ncols (deterministic order).
 hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int ncols, double* out,
                               hipStream_t st);
+// The same sum for many columns (the reorthogonalisation's 4*ncol + 1 inner
+// products), spread over reduce_wide_tiles(ncols) x reduce_wide_slices(nblk)
+// workgroups.  scr: reduce_wide_scratch_doubles(nblk, ncols) doubles; cnt:
+// reduce_wide_tiles(ncols) counters, zero before the first launch and left
+// zero by every launch (launches that share them must not overlap).
+int reduce_wide_slices(int nblk);
+int reduce_wide_tiles(int ncols);
+size_t reduce_wide_scratch_doubles(int nblk, int ncols);
+hipError_t launch_reduce_wide(const double* partial, int nblk, int stride, int ncols, double* out,
+                              double* scr, unsigned* cnt, hipStream_t st);
 // u *= scale (n complex).
 template <typename S>
 hipError_t launch_scale(cplx<S>* u, int64_t n, double scale, hipStream_t st);

@@ -262,7 +262,7 @@ double op_bytes(const jl_op_s* op, int es) {
 // ----------------------------------------------------------- workspace layout
 struct Layout {
   size_t V[2], apart, dots_part, upd_part, coef, scal, Tdev, ritz, lam_s, Zs, zlast, res_part,
-      res_out, res_lam, res_cols, cg_vec[5], cg_part, cg_s, rloc, rd, total;
+      res_out, res_lam, res_cols, cg_vec[5], cg_part, cg_s, rloc, rd, wide_scr, wide_cnt, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -284,6 +284,9 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   L.dots_part = take(sizeof(double) * (size_t)reorth_dots_blocks(h) * (4 * (size_t)(m + 1) + 1));
   L.upd_part = take(sizeof(double) * (size_t)std::max(reorth_update_blocks(h, es), 1));
   L.coef = take(sizeof(double) * (4 * (size_t)(m + 1) + 1));
+  const int wcols = 4 * (m + 1) + 1;   // the most inner products one pass reduces
+  L.wide_scr = take(sizeof(double) * reduce_wide_scratch_doubles(reorth_dots_blocks(h), wcols));
+  L.wide_cnt = take(sizeof(unsigned) * (size_t)reduce_wide_tiles(wcols));
   L.scal = take(sizeof(double) * 64);
   L.Tdev = take(sizeof(double) * (size_t)m * m);
   L.ritz = take(sizeof(double) * ritz_scratch_doubles(m));
@@ -433,6 +436,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   double* dots_part = reinterpret_cast<double*>(base + L.dots_part);
   double* upd_part = reinterpret_cast<double*>(base + L.upd_part);
   double* coef = reinterpret_cast<double*>(base + L.coef);
+  double* wide_scr = reinterpret_cast<double*>(base + L.wide_scr);
+  unsigned* wide_cnt = reinterpret_cast<unsigned*>(base + L.wide_cnt);
   double* scal = reinterpret_cast<double*>(base + L.scal);
   double* Tdev = reinterpret_cast<double*>(base + L.Tdev);
   double* ritz_scr = reinterpret_cast<double*>(base + L.ritz);
@@ -458,6 +463,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   cplx<S>* dscr = gu > 1 ? reinterpret_cast<cplx<S>*>(base + L.rd) : nullptr;
 
   const int ndots = reorth_dots_blocks(h);
+  JL_HIP(ctx, hipMemsetAsync(wide_cnt, 0, sizeof(unsigned) * (size_t)reduce_wide_tiles(4 * (m + 1) + 1),
+                             st));
   const int napply = op_apply_blocks(op);
   const int nupd = reorth_update_blocks(h, es);
   const int64_t ldv = n;
@@ -586,7 +593,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st, scal, beta_prev, j,
                                         uloc, gd));
       tm.stop();
-      JL_HIP(ctx, launch_reduce_cols(dots_part, ndots, stride, stride, coef, st));
+      JL_HIP(ctx, launch_reduce_wide(dots_part, ndots, stride, stride, coef, wide_scr, wide_cnt, st));
       S_.n_dots_launch++;
       S_.bytes_dots += (double)(ncol + 1) * n * es;
       tm.start(Timer::UPDATE);
@@ -614,7 +621,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
         JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st, nullptr, 0.0, 0,
                                           nullptr, gd));
         tm.stop();
-        JL_HIP(ctx, launch_reduce_cols(dots_part, ndots, stride, stride, coef, st));
+        JL_HIP(ctx, launch_reduce_wide(dots_part, ndots, stride, stride, coef, wide_scr, wide_cnt, st));
         S_.n_dots_launch++;
         S_.bytes_dots += (double)(ncol + 1) * n * es;
         tm.start(Timer::UPDATE);

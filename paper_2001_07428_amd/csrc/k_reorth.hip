@@ -52,6 +52,78 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sums over the wavefront of r[0..7]: three halving steps (lanes whose
+// xor-partner bit is set keep the upper half of the values) and three plain
+// steps; afterwards every lane l holds the sum of r[l >> 3].  Fixed order.
+__device__ __forceinline__ double wave_sum8(const double r[8]) {
+  const int lane = threadIdx.x % 64;
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+  double a[4], b[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a[k] = (h5 ? r[k + 4] : r[k]) + __shfl_xor(h5 ? r[k] : r[k + 4], 32);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) b[k] = (h4 ? a[k + 2] : a[k]) + __shfl_xor(h4 ? a[k] : a[k + 2], 16);
+  double t = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8);
+  t += __shfl_xor(t, 4);
+  t += __shfl_xor(t, 2);
+  t += __shfl_xor(t, 1);
+  return t;
+}
+// As wave_sum8 for r[0..3]: every lane l holds the sum of r[l >> 4].
+__device__ __forceinline__ double wave_sum4(const double r[4]) {
+  const int lane = threadIdx.x % 64;
+  const bool h5 = lane & 32, h4 = lane & 16;
+  double a[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) a[k] = (h5 ? r[k + 2] : r[k]) + __shfl_xor(h5 ? r[k] : r[k + 2], 32);
+  double t = (h4 ? a[1] : a[0]) + __shfl_xor(h4 ? a[0] : a[1], 16);
+  t += __shfl_xor(t, 8);
+  t += __shfl_xor(t, 4);
+  t += __shfl_xor(t, 2);
+  t += __shfl_xor(t, 1);
+  return t;
+}
+
+// This lane's share of v^H u and w^H u (w = J conj(v)) for the column at vt
+// (top half; bottom at vt + h): r = {Re v^H u, Im v^H u, Re w^H u, Im w^H u}.
+template <typename S, int E, int Q>
+__device__ __forceinline__ void col_dots(const cplx<S>* __restrict__ vt, int64_t h, int64_t p0,
+                                         int lane, const bool ok[Q], const double utr[Q][E],
+                                         const double uti[Q][E], const double ubr[Q][E],
+                                         const double ubi[Q][E], double r[4]) {
+  const cplx<S>* vb = vt + h;
+  S tr[Q][E], ti[Q][E], br[Q][E], bi[Q][E];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t p = p0 + (int64_t)q * 64 * E + lane * E;
+    if (ok[q]) {
+      Ld<S, E>::get(vt + p, tr[q], ti[q]);
+      Ld<S, E>::get(vb + p, br[q], bi[q]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) tr[q][e] = ti[q][e] = br[q][e] = bi[q][e] = (S)0;
+    }
+  }
+  double cvr = 0, cvi = 0, cwr = 0, cwi = 0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double vtr = tr[q][e], vti = ti[q][e], vbr = br[q][e], vbi = bi[q][e];
+      // v^H u = conj(v_t) u_t + conj(v_b) u_b
+      cvr = fma(vtr, utr[q][e], cvr); cvr = fma(vti, uti[q][e], cvr);
+      cvr = fma(vbr, ubr[q][e], cvr); cvr = fma(vbi, ubi[q][e], cvr);
+      cvi = fma(vtr, uti[q][e], cvi); cvi = fma(-vti, utr[q][e], cvi);
+      cvi = fma(vbr, ubi[q][e], cvi); cvi = fma(-vbi, ubr[q][e], cvi);
+      // w^H u = v_t u_b - v_b u_t
+      cwr = fma(vtr, ubr[q][e], cwr); cwr = fma(-vti, ubi[q][e], cwr);
+      cwr = fma(-vbr, utr[q][e], cwr); cwr = fma(vbi, uti[q][e], cwr);
+      cwi = fma(vtr, ubi[q][e], cwi); cwi = fma(vti, ubr[q][e], cwi);
+      cwi = fma(-vbr, uti[q][e], cwi); cwi = fma(-vbi, utr[q][e], cwi);
+    }
+  r[0] = cvr; r[1] = cvi; r[2] = cwr; r[3] = cwi;
+}
+
 // grid.x = blocks, each covering `chunks` consecutive chunks of
 // 64*E*kPairsPerLane pairs.  Column c is owned by wavefront c % 4 of every
 // block.  partial row stride = 4*ncol + 1.
@@ -64,7 +136,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // (which must then differ from u, since the other groups still read u) and
 // adds ||u||^2.
 template <typename S, int E, bool LOCAL>
-__global__ __launch_bounds__(kReorthThreads) void k_dots(const cplx<S>* __restrict__ V, int64_t ldv,
+__global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots(const cplx<S>* __restrict__ V, int64_t ldv,
                                                          int ncol, const cplx<S>* __restrict__ u,
                                                          int64_t h, int chunks,
                                                          double* __restrict__ partial,
@@ -149,42 +221,34 @@ __global__ __launch_bounds__(kReorthThreads) void k_dots(const cplx<S>* __restri
           unorm += utr[q][e] * utr[q][e] + uti[q][e] * uti[q][e] + ubr[q][e] * ubr[q][e] +
                    ubi[q][e] * ubi[q][e];
     }
-    for (int c = (int)blockIdx.y * 4 + wave; c < ncol; c += 4 * (int)gridDim.y) {
-      const cplx<S>* vt = V + (int64_t)c * ldv;
-      const cplx<S>* vb = vt + h;
-      S tr[Q][E], ti[Q][E], br[Q][E], bi[Q][E];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int64_t p = p0 + (int64_t)q * 64 * E + lane * E;
-        if (ok[q]) {
-          Ld<S, E>::get(vt + p, tr[q], ti[q]);
-          Ld<S, E>::get(vb + p, br[q], bi[q]);
-        } else {
-#pragma unroll
-          for (int e = 0; e < E; ++e) tr[q][e] = ti[q][e] = br[q][e] = bi[q][e] = (S)0;
+    // FP32: two columns (c, c + cs) per pass, so both columns' loads are in
+    // flight together, and their eight sums reduce in one butterfly (FP64
+    // holds twice the registers per column and stays at one column a pass).
+    const int cs = 4 * (int)gridDim.y;
+    int c = (int)blockIdx.y * 4 + wave;
+    if constexpr (sizeof(S) == 4) {
+      for (; c + cs < ncol; c += 2 * cs) {
+        double r[8];
+        col_dots<S, E, Q>(V + (int64_t)c * ldv, h, p0, lane, ok, utr, uti, ubr, ubi, r);
+        col_dots<S, E, Q>(V + (int64_t)(c + cs) * ldv, h, p0, lane, ok, utr, uti, ubr, ubi, r + 4);
+        const double t = wave_sum8(r);   // lane 8k holds sum k
+        if ((lane & 7) == 0) {   // columns c, c + cs are only ever touched by this wavefront
+          const int k = lane >> 3;
+          acc[4 * (k < 4 ? c : c + cs) + (k & 3)] += t;
         }
       }
-      double cvr = 0, cvi = 0, cwr = 0, cwi = 0;
-#pragma unroll
-      for (int q = 0; q < Q; ++q)
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const double vtr = tr[q][e], vti = ti[q][e], vbr = br[q][e], vbi = bi[q][e];
-          // v^H u = conj(v_t) u_t + conj(v_b) u_b
-          cvr = fma(vtr, utr[q][e], cvr); cvr = fma(vti, uti[q][e], cvr);
-          cvr = fma(vbr, ubr[q][e], cvr); cvr = fma(vbi, ubi[q][e], cvr);
-          cvi = fma(vtr, uti[q][e], cvi); cvi = fma(-vti, utr[q][e], cvi);
-          cvi = fma(vbr, ubi[q][e], cvi); cvi = fma(-vbi, ubr[q][e], cvi);
-          // w^H u = v_t u_b - v_b u_t
-          cwr = fma(vtr, ubr[q][e], cwr); cwr = fma(-vti, ubi[q][e], cwr);
-          cwr = fma(-vbr, utr[q][e], cwr); cwr = fma(vbi, uti[q][e], cwr);
-          cwi = fma(vtr, ubi[q][e], cwi); cwi = fma(vti, ubr[q][e], cwi);
-          cwi = fma(-vbr, uti[q][e], cwi); cwi = fma(-vbi, utr[q][e], cwi);
-        }
-      cvr = wave_sum(cvr); cvi = wave_sum(cvi); cwr = wave_sum(cwr); cwi = wave_sum(cwi);
-      if (lane == 0) {   // column c is only ever touched by this wavefront
-        acc[4 * c + 0] += cvr; acc[4 * c + 1] += cvi;
-        acc[4 * c + 2] += cwr; acc[4 * c + 3] += cwi;
+      if (c < ncol) {   // at most one column left
+        double r[4];
+        col_dots<S, E, Q>(V + (int64_t)c * ldv, h, p0, lane, ok, utr, uti, ubr, ubi, r);
+        const double t = wave_sum4(r);   // lane 16k holds sum k
+        if ((lane & 15) == 0) acc[4 * c + (lane >> 4)] += t;
+      }
+    } else {
+      for (; c < ncol; c += cs) {
+        double r[4];
+        col_dots<S, E, Q>(V + (int64_t)c * ldv, h, p0, lane, ok, utr, uti, ubr, ubi, r);
+        const double t = wave_sum4(r);
+        if ((lane & 15) == 0) acc[4 * c + (lane >> 4)] += t;
       }
     }
   }
@@ -363,6 +427,61 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ 
     __syncthreads();
   }
   if (ty == 0 && c < ncols) out[c] = sh[tx];
+}
+
+// out[c] = sum over b of partial[b*stride + c] for many columns (the inner
+// products of the reorthogonalisation, 4*ncol + 1 of them): grid (tiles of
+// 64 columns, R row slices).  Block (t, r) sums its slice of rows for 64
+// columns (four wavefronts over interleaved rows, combined in LDS) into
+// scr[r * ncols + c]; the last slice of a tile to finish, found with the
+// per-tile counter cnt[t], sums the R slice values in order r = 0 .. R-1 and
+// resets the counter.  The slice sums are agent-scope stores, complete before
+// the counter moves, and are read back with agent-scope loads (the per-XCD
+// L2s are not coherent with each other).  Deterministic for a given nblk.
+__global__ __launch_bounds__(256) void k_reduce_wide(const double* __restrict__ partial, int nblk,
+                                                     int stride, int ncols, double* __restrict__ out,
+                                                     double* scr, unsigned* cnt) {
+  __shared__ double sh[4][64];
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int c = blockIdx.x * 64 + lane;
+  const int R = gridDim.y, r = blockIdx.y;
+  const int per = (nblk + R - 1) / R;
+  const int b1 = min(nblk, (r + 1) * per);
+  double s = 0.0;
+  if (c < ncols) {
+    int b = r * per + w;
+    for (; b + 12 < b1; b += 16) {   // four independent loads per pass
+      const double x0 = partial[(int64_t)b * stride + c];
+      const double x1 = partial[(int64_t)(b + 4) * stride + c];
+      const double x2 = partial[(int64_t)(b + 8) * stride + c];
+      const double x3 = partial[(int64_t)(b + 12) * stride + c];
+      s += (x0 + x1) + (x2 + x3);
+    }
+    for (; b < b1; b += 4) s += partial[(int64_t)b * stride + c];
+  }
+  sh[w][lane] = s;
+  __syncthreads();
+  if (w != 0) return;
+  const double t = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+  if (R == 1) {
+    if (c < ncols) out[c] = t;
+    return;
+  }
+  if (c < ncols)
+    __hip_atomic_store(&scr[(int64_t)r * ncols + c], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);   // this wavefront's slice sums are complete
+  unsigned done = 0;
+  if (lane == 0) done = atomicAdd(&cnt[blockIdx.x], 1u);
+  done = __shfl(done, 0);
+  if (done != (unsigned)(R - 1)) return;   // uniform within the wavefront
+  if (c < ncols) {
+    double v = 0.0;
+    for (int rr = 0; rr < R; ++rr)
+      v += __hip_atomic_load(&scr[(int64_t)rr * ncols + c], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    out[c] = v;
+  }
+  if (lane == 0) cnt[blockIdx.x] = 0u;   // ready for the next launch
 }
 
 template <typename S>
@@ -549,6 +668,22 @@ hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int n
   else
     hipLaunchKernelGGL(k_reduce_cols<16>, dim3(blocks_for(ncols, 16)), dim3(256), 0, st, partial,
                        nblk, stride, ncols, out);
+  return hipGetLastError();
+}
+
+int reduce_wide_slices(int nblk) { return std::max(1, std::min(16, nblk / 64)); }
+int reduce_wide_tiles(int ncols) { return (ncols + 63) / 64; }
+size_t reduce_wide_scratch_doubles(int nblk, int ncols) {
+  return (size_t)reduce_wide_slices(nblk) * (size_t)ncols;
+}
+
+hipError_t launch_reduce_wide(const double* partial, int nblk, int stride, int ncols, double* out,
+                              double* scr, unsigned* cnt, hipStream_t st) {
+  if (ncols <= 0 || nblk <= 0) return hipErrorInvalidValue;
+  const int R = reduce_wide_slices(nblk);
+  if (R > 1 && (!scr || !cnt)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_wide, dim3((unsigned)reduce_wide_tiles(ncols), (unsigned)R), dim3(256),
+                     0, st, partial, nblk, stride, ncols, out, scr, cnt);
   return hipGetLastError();
 }
 

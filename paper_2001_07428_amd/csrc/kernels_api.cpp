@@ -13,12 +13,21 @@ namespace {
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-size_t reorth_ws(int64_t n, int ncol) {
+// dots partials | update partials | wide-reduction slices | its tile counters
+size_t reorth_ws_part(int64_t n, int ncol, int which) {
   const int64_t h = n / 2;
-  return align_up(sizeof(double) * (size_t)reorth_dots_blocks(h) * (4 * (size_t)ncol + 1)) +
-         align_up(sizeof(double) *
-                  (size_t)std::max({reorth_update_blocks(h, 8), reorth_update_blocks(h, 16), 1}));
+  const int nd = reorth_dots_blocks(h), stride = 4 * ncol + 1;
+  const size_t sz[4] = {
+      align_up(sizeof(double) * (size_t)nd * (size_t)stride),
+      align_up(sizeof(double) *
+               (size_t)std::max({reorth_update_blocks(h, 8), reorth_update_blocks(h, 16), 1})),
+      align_up(sizeof(double) * reduce_wide_scratch_doubles(nd, stride)),
+      align_up(sizeof(unsigned) * (size_t)reduce_wide_tiles(stride))};
+  size_t off = 0;
+  for (int i = 0; i < which; ++i) off += sz[i];
+  return off;
 }
+size_t reorth_ws(int64_t n, int ncol) { return reorth_ws_part(n, ncol, 4); }
 
 template <typename S>
 hipError_t reorth_pass(int64_t n, int ncol, const cplx<S>* V, int64_t ldv, cplx<S>* u, double* coef,
@@ -26,11 +35,16 @@ hipError_t reorth_pass(int64_t n, int ncol, const cplx<S>* V, int64_t ldv, cplx<
   const int64_t h = n / 2;
   const int nd = reorth_dots_blocks(h), nu = reorth_update_blocks(h, (int)sizeof(cplx<S>));
   double* dp = reinterpret_cast<double*>(ws);
-  double* up = reinterpret_cast<double*>(ws + align_up(sizeof(double) * (size_t)nd * (4 * (size_t)ncol + 1)));
+  double* up = reinterpret_cast<double*>(ws + reorth_ws_part(n, ncol, 1));
+  double* scr = reinterpret_cast<double*>(ws + reorth_ws_part(n, ncol, 2));
+  unsigned* cnt = reinterpret_cast<unsigned*>(ws + reorth_ws_part(n, ncol, 3));
   const int stride = 4 * ncol + 1;
   hipError_t e;
+  if ((e = hipMemsetAsync(cnt, 0, sizeof(unsigned) * (size_t)reduce_wide_tiles(stride), st)) !=
+      hipSuccess)
+    return e;
   if ((e = launch_reorth_dots<S>(V, ldv, ncol, u, h, dp, nd, st)) != hipSuccess) return e;
-  if ((e = launch_reduce_cols(dp, nd, stride, stride, coef, st)) != hipSuccess) return e;
+  if ((e = launch_reduce_wide(dp, nd, stride, stride, coef, scr, cnt, st)) != hipSuccess) return e;
   if ((e = launch_reorth_update<S>(V, ldv, ncol, u, h, coef, up, nu, st)) != hipSuccess) return e;
   return launch_reduce_cols(up, nu, 1, 1, coef + 4 * ncol + 1, st);
 }
