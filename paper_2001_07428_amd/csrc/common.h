@@ -154,14 +154,18 @@ hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* 
 int reorth_dots_groups(int64_t h);
 // update: u -= V c_v + W c_w (W = J V^*), coef = [4*ncol] FP64 (Re cv, Im cv,
 // Re cw, Im cw per column); partial[blk] = ||u_new||^2 per block.
-template <typename S>
 // jsym = false leaves out the W projection (standard Gram-Schmidt against V).
 // The result goes to u, computed from uin (default u).  groups > 1 splits
 // the columns (reorth_update_groups) and needs d: groups x n complex scratch.
+// With fin the kernel also sums the block norms into *fin, using the counter
+// *cnt (zero before the first launch, left zero; launches sharing it must not
+// overlap).
+template <typename S>
 hipError_t launch_reorth_update(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
                                 const double* coef, double* partial, int nblk, hipStream_t st,
                                 bool jsym = true, const cplx<S>* uin = nullptr, int groups = 1,
-                                cplx<S>* d = nullptr);
+                                cplx<S>* d = nullptr, double* fin = nullptr,
+                                unsigned* cnt = nullptr);
 int reorth_update_groups(int64_t h, int es);
 // out[c] = sum_b partial[b * stride + c] for c < ncols (deterministic order).
 hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int ncols, double* out,
@@ -171,11 +175,13 @@ hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int n
 // workgroups.  scr: reduce_wide_scratch_doubles(nblk, ncols) doubles; cnt:
 // reduce_wide_tiles(ncols) counters, zero before the first launch and left
 // zero by every launch (launches that share them must not overlap).
+// last_out (optional) also receives out[ncols - 1].
 int reduce_wide_slices(int nblk);
 int reduce_wide_tiles(int ncols);
 size_t reduce_wide_scratch_doubles(int nblk, int ncols);
 hipError_t launch_reduce_wide(const double* partial, int nblk, int stride, int ncols, double* out,
-                              double* scr, unsigned* cnt, hipStream_t st);
+                              double* scr, unsigned* cnt, hipStream_t st,
+                              double* last_out = nullptr);
 // u *= scale (n complex).
 template <typename S>
 hipError_t launch_scale(cplx<S>* u, int64_t n, double scale, hipStream_t st);

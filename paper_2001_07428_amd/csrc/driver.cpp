@@ -286,7 +286,7 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   L.coef = take(sizeof(double) * (4 * (size_t)(m + 1) + 1));
   const int wcols = 4 * (m + 1) + 1;   // the most inner products one pass reduces
   L.wide_scr = take(sizeof(double) * reduce_wide_scratch_doubles(reorth_dots_blocks(h), wcols));
-  L.wide_cnt = take(sizeof(unsigned) * (size_t)reduce_wide_tiles(wcols));
+  L.wide_cnt = take(sizeof(unsigned) * ((size_t)reduce_wide_tiles(wcols) + 1));   // + update norm
   L.scal = take(sizeof(double) * 64);
   L.Tdev = take(sizeof(double) * (size_t)m * m);
   L.ritz = take(sizeof(double) * ritz_scratch_doubles(m));
@@ -463,8 +463,9 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   cplx<S>* dscr = gu > 1 ? reinterpret_cast<cplx<S>*>(base + L.rd) : nullptr;
 
   const int ndots = reorth_dots_blocks(h);
-  JL_HIP(ctx, hipMemsetAsync(wide_cnt, 0, sizeof(unsigned) * (size_t)reduce_wide_tiles(4 * (m + 1) + 1),
-                             st));
+  const int wtiles = reduce_wide_tiles(4 * (m + 1) + 1);
+  unsigned* upd_cnt = wide_cnt + wtiles;
+  JL_HIP(ctx, hipMemsetAsync(wide_cnt, 0, sizeof(unsigned) * ((size_t)wtiles + 1), st));
   const int napply = op_apply_blocks(op);
   const int nupd = reorth_update_blocks(h, es);
   const int64_t ldv = n;
@@ -593,18 +594,18 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st, scal, beta_prev, j,
                                         uloc, gd));
       tm.stop();
-      JL_HIP(ctx, launch_reduce_wide(dots_part, ndots, stride, stride, coef, wide_scr, wide_cnt, st));
+      // the norm entering the loop (the last reduced column) also to scal[3]
+      JL_HIP(ctx, launch_reduce_wide(dots_part, ndots, stride, stride, coef, wide_scr, wide_cnt, st,
+                                     scal + 3));
       S_.n_dots_launch++;
       S_.bytes_dots += (double)(ncol + 1) * n * es;
       tm.start(Timer::UPDATE);
       JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st, jsym,
-                                          uloc ? uloc : u, gu, dscr));
+                                          uloc ? uloc : u, gu, dscr, scal + 2, upd_cnt));
       tm.stop();
-      JL_HIP(ctx, launch_reduce_cols(upd_part, nupd, 1, 1, scal + 2, st));
       S_.n_update_launch++;
       S_.bytes_update += (double)(ncol + 2) * n * es;
-      JL_HIP(ctx, hipMemcpyAsync(hs, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-      JL_HIP(ctx, hipMemcpyAsync(hs + 3, coef + 4 * ncol, sizeof(double), hipMemcpyDeviceToHost, st));
+      JL_HIP(ctx, hipMemcpyAsync(hs, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
       JL_HIP(ctx, hipStreamSynchronize(st));
       tm.resolve();
       const double alpha = hs[0];
@@ -626,9 +627,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
         S_.bytes_dots += (double)(ncol + 1) * n * es;
         tm.start(Timer::UPDATE);
         JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st, jsym,
-                                            u, gu, dscr));
+                                            u, gu, dscr, scal + 2, upd_cnt));
         tm.stop();
-        JL_HIP(ctx, launch_reduce_cols(upd_part, nupd, 1, 1, scal + 2, st));
         S_.n_update_launch++;
         S_.bytes_update += (double)(ncol + 2) * n * es;
         JL_HIP(ctx, hipMemcpyAsync(hs + 2, scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));

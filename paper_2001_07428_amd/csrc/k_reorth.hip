@@ -264,10 +264,43 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
     if (i == 4 * ncol ? g == 0 : ((i / 16) % G == g)) out[i] = acc[i];
 }
 
+// Stores this block's share of ||u||^2 (bsum, the same in every thread).
+// With fin the kernel also finishes the sum: each block's share is an
+// agent-scope store, complete before the counter *cnt moves; the last block
+// to count sums the shares in block order into *fin and resets the counter
+// (the per-XCD L2s are not coherent, hence agent-scope loads as well).
+__device__ __forceinline__ void block_norm_out(double bsum, double* partial, double* fin,
+                                               unsigned* cnt) {
+  __shared__ bool last;
+  __shared__ double red[kReorthThreads / 64];
+  if (!fin) {
+    if (threadIdx.x == 0) partial[blockIdx.x] = bsum;
+    return;
+  }
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&partial[blockIdx.x], bsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);
+    last = atomicAdd(cnt, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;   // uniform within the block
+  double s = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += kReorthThreads)
+    s += __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  s = wave_sum(s);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *fin = (red[0] + red[1]) + (red[2] + red[3]);
+    *cnt = 0u;   // ready for the next launch
+  }
+}
+
 // u -= sum_c v_c cv_c + w_c cw_c (JSYM; without it the W projection is
 // left out: standard Gram-Schmidt against V alone); each lane keeps the
 // corrections of its E*Q pairs in registers across the column loop (Q loads
-// of 16 bytes per half per column).  partial[blk] = ||u_new||^2.
+// of 16 bytes per half per column).  partial[blk] = the block's share of
+// ||u_new||^2; with fin the last block also sums them into *fin.
 // uout = uin - corrections (uin == uout in place).  With SPLIT (column groups,
 // gridDim.y = G > 1) block (x, g) sums the columns c = g, g + G, ... and
 // stores its corrections to d[g] (2h complex each) instead; k_update_fin
@@ -278,8 +311,9 @@ __global__ __launch_bounds__(kReorthThreads) void k_update(const cplx<S>* __rest
                                                            const cplx<S>* uin, cplx<S>* uout,
                                                            int64_t h,
                                                            const double* __restrict__ coef,
-                                                           double* __restrict__ partial,
-                                                           cplx<S>* __restrict__ d) {
+                                                           double* partial,
+                                                           cplx<S>* __restrict__ d, double* fin,
+                                                           unsigned* cnt) {
   constexpr int CH = 4 * 64 * E * Q;       // pairs per block
   __shared__ double sh[4];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -359,7 +393,7 @@ __global__ __launch_bounds__(kReorthThreads) void k_update(const cplx<S>* __rest
   nrm = wave_sum(nrm);
   if (lane == 0) sh[wave] = nrm;
   __syncthreads();
-  if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  block_norm_out((sh[0] + sh[1]) + (sh[2] + sh[3]), partial, fin, cnt);
 }
 
 // uout = uin - (d[0] + ... + d[G-1]) (summed in that order, storage type),
@@ -368,7 +402,8 @@ template <typename S, int E, int Q>
 __global__ __launch_bounds__(kReorthThreads) void k_update_fin(const cplx<S>* uin, cplx<S>* uout,
                                                                int64_t h,
                                                                const cplx<S>* __restrict__ d,
-                                                               int G, double* __restrict__ partial) {
+                                                               int G, double* partial, double* fin,
+                                                               unsigned* cnt) {
   constexpr int CH = 4 * 64 * E * Q;
   __shared__ double sh[4];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -401,7 +436,7 @@ __global__ __launch_bounds__(kReorthThreads) void k_update_fin(const cplx<S>* ui
   nrm = wave_sum(nrm);
   if (lane == 0) sh[wave] = nrm;
   __syncthreads();
-  if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  block_norm_out((sh[0] + sh[1]) + (sh[2] + sh[3]), partial, fin, cnt);
 }
 
 // out[c] = sum over b of partial[b*stride + c].  A block of 256 threads
@@ -435,12 +470,13 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ 
 // columns (four wavefronts over interleaved rows, combined in LDS) into
 // scr[r * ncols + c]; the last slice of a tile to finish, found with the
 // per-tile counter cnt[t], sums the R slice values in order r = 0 .. R-1 and
-// resets the counter.  The slice sums are agent-scope stores, complete before
+// resets the counter; last_out, if given, also receives out[ncols - 1].
+// The slice sums are agent-scope stores, complete before
 // the counter moves, and are read back with agent-scope loads (the per-XCD
 // L2s are not coherent with each other).  Deterministic for a given nblk.
 __global__ __launch_bounds__(256) void k_reduce_wide(const double* __restrict__ partial, int nblk,
                                                      int stride, int ncols, double* __restrict__ out,
-                                                     double* scr, unsigned* cnt) {
+                                                     double* scr, unsigned* cnt, double* last_out) {
   __shared__ double sh[4][64];
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   const int c = blockIdx.x * 64 + lane;
@@ -465,6 +501,7 @@ __global__ __launch_bounds__(256) void k_reduce_wide(const double* __restrict__ 
   const double t = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
   if (R == 1) {
     if (c < ncols) out[c] = t;
+    if (last_out && c == ncols - 1) *last_out = t;
     return;
   }
   if (c < ncols)
@@ -480,6 +517,7 @@ __global__ __launch_bounds__(256) void k_reduce_wide(const double* __restrict__ 
       v += __hip_atomic_load(&scr[(int64_t)rr * ncols + c], __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     out[c] = v;
+    if (last_out && c == ncols - 1) *last_out = v;
   }
   if (lane == 0) cnt[blockIdx.x] = 0u;   // ready for the next launch
 }
@@ -602,48 +640,50 @@ int reorth_dots_blocks(int64_t h) {
 template <typename S, int E, int Q>
 static void launch_update_q(unsigned grid, const cplx<S>* V, int64_t ldv, int ncol,
                             const cplx<S>* uin, cplx<S>* u, int64_t h, const double* coef,
-                            double* partial, hipStream_t st, bool jsym, int groups, cplx<S>* d) {
+                            double* partial, hipStream_t st, bool jsym, int groups, cplx<S>* d,
+                            double* fin, unsigned* cnt) {
   if (groups > 1) {
     const dim3 g2(grid, (unsigned)groups);
     if (jsym)
       hipLaunchKernelGGL((k_update<S, E, Q, true, true>), g2, dim3(kReorthThreads), 0, st, V, ldv,
-                         ncol, uin, u, h, coef, partial, d);
+                         ncol, uin, u, h, coef, partial, d, nullptr, nullptr);
     else
       hipLaunchKernelGGL((k_update<S, E, Q, false, true>), g2, dim3(kReorthThreads), 0, st, V, ldv,
-                         ncol, uin, u, h, coef, partial, d);
+                         ncol, uin, u, h, coef, partial, d, nullptr, nullptr);
     hipLaunchKernelGGL((k_update_fin<S, E, Q>), dim3(grid), dim3(kReorthThreads), 0, st, uin, u, h,
-                       (const cplx<S>*)d, groups, partial);
+                       (const cplx<S>*)d, groups, partial, fin, cnt);
     return;
   }
   if (jsym)
     hipLaunchKernelGGL((k_update<S, E, Q, true, false>), dim3(grid), dim3(kReorthThreads), 0, st, V,
-                       ldv, ncol, uin, u, h, coef, partial, d);
+                       ldv, ncol, uin, u, h, coef, partial, d, fin, cnt);
   else
     hipLaunchKernelGGL((k_update<S, E, Q, false, false>), dim3(grid), dim3(kReorthThreads), 0, st, V,
-                       ldv, ncol, uin, u, h, coef, partial, d);
+                       ldv, ncol, uin, u, h, coef, partial, d, fin, cnt);
 }
 
 template <typename S>
 hipError_t launch_reorth_update(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
                                 const double* coef, double* partial, int nblk, hipStream_t st,
-                                bool jsym, const cplx<S>* uin, int groups, cplx<S>* d) {
+                                bool jsym, const cplx<S>* uin, int groups, cplx<S>* d,
+                                double* fin, unsigned* cnt) {
   const int E = elems_per_load(h, (int)sizeof(cplx<S>));
   const int ppl = update_ppl(h, E);
   const unsigned grid = (unsigned)((h + 256 * (int64_t)ppl - 1) / (256 * (int64_t)ppl));
   if ((int)grid != nblk) return hipErrorInvalidValue;
-  if (groups < 1 || (groups > 1 && !d)) return hipErrorInvalidValue;
+  if (groups < 1 || (groups > 1 && !d) || (fin && !cnt)) return hipErrorInvalidValue;
   if (!uin) uin = u;
   if (E == 2) {
     if constexpr (sizeof(S) == 4) {
-      if (ppl == 8) launch_update_q<S, 2, 4>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
-      else if (ppl == 4) launch_update_q<S, 2, 2>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
-      else launch_update_q<S, 2, 1>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
+      if (ppl == 8) launch_update_q<S, 2, 4>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d, fin, cnt);
+      else if (ppl == 4) launch_update_q<S, 2, 2>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d, fin, cnt);
+      else launch_update_q<S, 2, 1>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d, fin, cnt);
     }
   } else {
-    if (ppl == 8) launch_update_q<S, 1, 8>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
-    else if (ppl == 4) launch_update_q<S, 1, 4>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
-    else if (ppl == 2) launch_update_q<S, 1, 2>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
-    else launch_update_q<S, 1, 1>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d);
+    if (ppl == 8) launch_update_q<S, 1, 8>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d, fin, cnt);
+    else if (ppl == 4) launch_update_q<S, 1, 4>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d, fin, cnt);
+    else if (ppl == 2) launch_update_q<S, 1, 2>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d, fin, cnt);
+    else launch_update_q<S, 1, 1>(grid, V, ldv, ncol, uin, u, h, coef, partial, st, jsym, groups, d, fin, cnt);
   }
   return hipGetLastError();
 }
@@ -678,12 +718,12 @@ size_t reduce_wide_scratch_doubles(int nblk, int ncols) {
 }
 
 hipError_t launch_reduce_wide(const double* partial, int nblk, int stride, int ncols, double* out,
-                              double* scr, unsigned* cnt, hipStream_t st) {
+                              double* scr, unsigned* cnt, hipStream_t st, double* last_out) {
   if (ncols <= 0 || nblk <= 0) return hipErrorInvalidValue;
   const int R = reduce_wide_slices(nblk);
   if (R > 1 && (!scr || !cnt)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce_wide, dim3((unsigned)reduce_wide_tiles(ncols), (unsigned)R), dim3(256),
-                     0, st, partial, nblk, stride, ncols, out, scr, cnt);
+                     0, st, partial, nblk, stride, ncols, out, scr, cnt, last_out);
   return hipGetLastError();
 }
 
@@ -723,7 +763,7 @@ hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t l
                                             int, cplx<S>*, int);                                  \
   template hipError_t launch_reorth_update<S>(const cplx<S>*, int64_t, int, cplx<S>*, int64_t,    \
                                               const double*, double*, int, hipStream_t, bool,     \
-                                              const cplx<S>*, int, cplx<S>*);                     \
+                                              const cplx<S>*, int, cplx<S>*, double*, unsigned*); \
   template hipError_t launch_scale<S>(cplx<S>*, int64_t, double, hipStream_t);                    \
   template hipError_t launch_fill<S>(cplx<S>*, int64_t, double, hipStream_t);                     \
   template hipError_t launch_pair<S>(const cplx<S>*, int64_t, cplx<S>*, int64_t, int64_t, int,    \
