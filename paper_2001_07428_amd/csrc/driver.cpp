@@ -369,16 +369,22 @@ struct Timer {
     pending.push_back({cur, {cur_start, e}});
     cur_start = nullptr;
   }
-  // Call only after the stream has been synchronised.
+  // Adds the intervals that have completed; the others stay pending (work
+  // queued behind a partial wait).
   void resolve() {
+    size_t keep = 0;
     for (auto& pr : pending) {
+      if (hipEventQuery(pr.second.second) != hipSuccess) {
+        pending[keep++] = pr;
+        continue;
+      }
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, pr.second.first, pr.second.second) == hipSuccess)
         t[pr.first] += 1e-3 * ms;
       pool.push_back(pr.second.first);
       pool.push_back(pr.second.second);
     }
-    pending.clear();
+    pending.resize(keep);
   }
   ~Timer() {
     for (auto e : pool) hipEventDestroy(e);
@@ -470,6 +476,13 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   const int nupd = reorth_update_blocks(h, es);
   const int64_t ldv = n;
 
+  struct Ev {
+    hipEvent_t e = nullptr;
+    ~Ev() {
+      if (e) hipEventDestroy(e);
+    }
+  } ev_copy;
+  JL_HIP(ctx, hipEventCreateWithFlags(&ev_copy.e, hipEventDisableTiming));
   Pinned pin;
   const size_t pin_doubles = 16 + CG_NSLOTS + 3 * (size_t)m + 3 * (size_t)nev;
   JL_HIP(ctx, hipHostMalloc((void**)&pin.p, sizeof(double) * pin_doubles, hipHostMallocDefault));
@@ -568,6 +581,20 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     cplx<S>* Vn = Vb[1 - cur];
     int meff = m;
     bool broke = false;
+    // Normal mode queues the next step's normalisation (factor read on the
+    // device) and operator apply before it waits for this step's scalars, so
+    // the device stays busy over the host's round trip; a step that needs
+    // another Gram-Schmidt pass redoes the apply.
+    bool applied = false;   // u = A v_j of this step is already queued
+    auto queue_apply = [&](const cplx<S>* x, cplx<S>* y) -> hipError_t {
+      tm.start(Timer::MATVEC);
+      hipError_t e = op_apply<S>(op, x, y, ldv, 1, apart, st);
+      tm.stop();
+      if (e == hipSuccess) e = launch_reduce_cols(apart, napply, 2, 2, scal, st);
+      S_.n_matvec_launch++;
+      S_.bytes_matvec += op_bytes(op, es);
+      return e;
+    };
     // ================= Algorithm 2: Lanczos steps j = k .. m-1
     for (int j = k; j < m; ++j) {
       cplx<S>* vj = V + (int64_t)j * ldv;
@@ -577,14 +604,10 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       if (invert) {   // u = A^-1 v_j by CG, t_jj = v_j^H u into scal
         const jl_status cs = cg_solve(vj, u);
         if (cs != JL_OK) return cs;
-      } else {        // u = A v_j, with the block partial sums of t_jj = v_j^H u
-        tm.start(Timer::MATVEC);
-        JL_HIP(ctx, op_apply<S>(op, vj, u, ldv, 1, apart, st));
-        tm.stop();
-        JL_HIP(ctx, launch_reduce_cols(apart, napply, 2, 2, scal, st));
-        S_.n_matvec_launch++;
-        S_.bytes_matvec += op_bytes(op, es);
+      } else if (!applied) {   // u = A v_j, with the block partial sums of t_jj = v_j^H u
+        JL_HIP(ctx, queue_apply(vj, u));
       }
+      applied = false;
       S_.n_mv++;
       S_.sum_ncol += ncol;
       // local three-term step u -= t_jj v_j + beta_{j-1} v_{j-1} fused into the
@@ -606,13 +629,24 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       S_.n_update_launch++;
       S_.bytes_update += (double)(ncol + 2) * n * es;
       JL_HIP(ctx, hipMemcpyAsync(hs, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-      JL_HIP(ctx, hipStreamSynchronize(st));
+      // speculative: v_{j+1} = u / ||u|| and A v_{j+1}, behind the copy
+      const bool spec = !invert && j + 1 < m;
+      if (spec) {
+        JL_HIP(ctx, hipEventRecord(ev_copy.e, st));
+        JL_HIP(ctx, launch_scale_dev<S>(u, n, scal + 2, st));
+        JL_HIP(ctx, queue_apply(u, u + ldv));
+        JL_HIP(ctx, hipEventSynchronize(ev_copy.e));
+      } else {
+        JL_HIP(ctx, hipStreamSynchronize(st));
+      }
       tm.resolve();
       const double alpha = hs[0];
       Tat(j, j) = alpha;
       maxT = std::max(maxT, std::fabs(alpha));
       double b0 = std::sqrt(hs[3]);   // norm entering the Gram-Schmidt loop
       double b1 = std::sqrt(hs[2]);
+      // u on the device holds (u / usc): usc = b1 after the speculative scaling
+      const double usc = spec ? b1 : 1.0;
       const double btol = bd_factor * uround * std::max(maxT, 1e-300);
       int passes = 1;
       S_.gs_passes++;
@@ -634,7 +668,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
         JL_HIP(ctx, hipMemcpyAsync(hs + 2, scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
         JL_HIP(ctx, hipStreamSynchronize(st));
         tm.resolve();
-        b1 = std::sqrt(hs[2]);
+        b1 = usc * std::sqrt(hs[2]);   // Gram-Schmidt is linear: back to the units of u
         passes++;
         S_.gs_passes++;
       }
@@ -651,7 +685,11 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
         broke = true;
         break;
       }
-      JL_HIP(ctx, launch_scale<S>(u, n, 1.0 / b1, st));
+      if (spec && passes == 1) {
+        applied = true;   // the queued v_{j+1} and A v_{j+1} stand
+      } else {
+        JL_HIP(ctx, launch_scale<S>(u, n, usc / b1, st));
+      }
       Tat(j + 1, j) = b1;
       maxT = std::max(maxT, b1);
     }

@@ -532,6 +532,18 @@ __global__ void k_scale(cplx<S>* __restrict__ u, int64_t n, S s) {
   }
 }
 
+// u *= 1 / sqrt(*nrm2), the factor formed on the device in FP64.
+template <typename S>
+__global__ void k_scale_dev(cplx<S>* __restrict__ u, int64_t n, const double* __restrict__ nrm2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const S s = (S)(1.0 / sqrt(*nrm2));
+    cplx<S> v = u[i];
+    v.x *= s; v.y *= s;
+    u[i] = v;
+  }
+}
+
 template <typename S>
 __global__ void k_fill(cplx<S>* __restrict__ u, int64_t n, S val) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -734,6 +746,12 @@ hipError_t launch_scale(cplx<S>* u, int64_t n, double scale, hipStream_t st) {
 }
 
 template <typename S>
+hipError_t launch_scale_dev(cplx<S>* u, int64_t n, const double* nrm2, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_dev<S>, dim3(blocks_for(n, 256)), dim3(256), 0, st, u, n, nrm2);
+  return hipGetLastError();
+}
+
+template <typename S>
 hipError_t launch_fill(cplx<S>* u, int64_t n, double value, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<S>, dim3(blocks_for(n, 256)), dim3(256), 0, st, u, n, (S)value);
   return hipGetLastError();
@@ -765,6 +783,7 @@ hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t l
                                               const double*, double*, int, hipStream_t, bool,     \
                                               const cplx<S>*, int, cplx<S>*, double*, unsigned*); \
   template hipError_t launch_scale<S>(cplx<S>*, int64_t, double, hipStream_t);                    \
+  template hipError_t launch_scale_dev<S>(cplx<S>*, int64_t, const double*, hipStream_t);         \
   template hipError_t launch_fill<S>(cplx<S>*, int64_t, double, hipStream_t);                     \
   template hipError_t launch_pair<S>(const cplx<S>*, int64_t, cplx<S>*, int64_t, int64_t, int,    \
                                      hipStream_t);                                                \
