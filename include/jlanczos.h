@@ -94,7 +94,8 @@ jl_status jl_op_create_dense(jl_ctx ctx, int64_t n, const void* A11, const void*
  * twice that with per-site B; freed by jl_op_destroy), made on the ctx
  * stream before the call returns: U and B are not referenced afterwards.
  * Vectors passed to this operator must be 16-byte aligned.  Errors:
- * JL_EINVAL for L[i] < 2 or NULL pointers; JL_EUNSUPPORTED for d != 4;
+ * JL_EINVAL for L[i] < 2, 2^31 sites or more, or NULL pointers;
+ * JL_EUNSUPPORTED for d != 4;
  * JL_ENOMEM when the link copy cannot be allocated. */
 jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double diag,
                                double a12_scale, const void* U, const void* B,

@@ -47,7 +47,7 @@ template <typename S> struct StencilArgs {
 template <typename S>
 hipError_t launch_stencil_apply(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
                                 int nrhs, double* apart, hipStream_t st);
-int stencil_apply_blocks(int64_t V, int es);   // es: bytes per complex element
+int stencil_apply_blocks(int64_t V);
 // One CG direction step fused into the apply (single column): the operand is
 // p = r + beta p_old (beta = *beta on the device), y = A p, p is stored to
 // pnew, and apart receives the partials of p^H y as above.

@@ -237,7 +237,7 @@ hipError_t op_resid(const jl_op_s* op, const cplx<S>* X, int64_t ldx, const int*
 
 int op_apply_blocks(const jl_op_s* op) {
   if (op->kind == OP_TEK) return tek_apply_blocks(op->tf.N);
-  return op->kind == OP_STENCIL ? stencil_apply_blocks(op->n / 8, op->dtype == JL_C64 ? 8 : 16)
+  return op->kind == OP_STENCIL ? stencil_apply_blocks(op->n / 8)
                                  : dense_apply_blocks(op->n / 2);
 }
 
@@ -1045,6 +1045,8 @@ jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double
   if (!U || !B) return set_err(ctx, JL_EINVAL, "U and B are required");
   if (dtype != JL_C64 && dtype != JL_C128) return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
   const int64_t V = (int64_t)L[0] * L[1] * L[2] * L[3];
+  if (V >= ((int64_t)1 << 31))
+    return set_err(ctx, JL_EINVAL, "the lattice must have fewer than 2^31 sites (got %lld)", (long long)V);
   const size_t es = dtype == JL_C64 ? sizeof(float2) : sizeof(double2);
   const size_t ubytes = (size_t)64 * V * es;
   const size_t bbytes = b_per_site ? ubytes : 64 * es;

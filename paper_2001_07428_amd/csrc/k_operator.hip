@@ -7,9 +7,9 @@
 // Stencil: one thread per lattice site computes all 4 internal components of
 // both halves; the link U_mu(x) is read once for the forward hop of both
 // halves and U_mu(x - mu) once for the backward hop, from the operator's
-// site-fastest copy of the links (coalesced across the wavefront).  On
-// small FP32 lattices four threads share a site, one direction each
-// (k_stencil_apply4), for four times the wavefronts.
+// site-fastest copy of the links (coalesced across the wavefront).  Each hop
+// issues its 16 link loads and the neighbour's loads together before any
+// product.
 // Dense: one wavefront per row of [A11 A12]; the row is read once for both
 // right-hand sides [a; b] and [conj(b); -conj(a)] (u_bot = conj(A11 conj(b) -
 // A12 conj(a)) because A11^T = conj(A11) and A12^H = -conj(A12)).
@@ -125,15 +125,16 @@ template <typename S> struct Operand<S, true> {
 template <typename S, typename C, bool BSITE, typename X>
 __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const X& xo, int64_t h,
                                              int64_t s, cx<C> top[4], cx<C> bot[4]) {
-  const int Ls[4] = {a.L[0], a.L[1], a.L[2], a.L[3]};
-  const int64_t st[4] = {(int64_t)Ls[1] * Ls[2] * Ls[3], (int64_t)Ls[2] * Ls[3], (int64_t)Ls[3], 1};
-  int x[4];
+  // site coordinates in 32 bits (the lattice has fewer than 2^31 sites)
+  const unsigned Ls[4] = {(unsigned)a.L[0], (unsigned)a.L[1], (unsigned)a.L[2], (unsigned)a.L[3]};
+  const unsigned st[4] = {Ls[1] * Ls[2] * Ls[3], Ls[2] * Ls[3], Ls[3], 1u};
+  unsigned x[4];
   {
-    int64_t r = s;
-    x[0] = (int)(r / st[0]); r -= (int64_t)x[0] * st[0];
-    x[1] = (int)(r / st[1]); r -= (int64_t)x[1] * st[1];
-    x[2] = (int)(r / st[2]); r -= (int64_t)x[2] * st[2];
-    x[3] = (int)r;
+    unsigned r = (unsigned)s;
+    x[0] = r / st[0]; r -= x[0] * st[0];
+    x[1] = r / st[1]; r -= x[1] * st[1];
+    x[2] = r / st[2]; r -= x[2] * st[2];
+    x[3] = r;
   }
   const C dg = (C)a.diag;
   const C sc = (C)a.scale;
@@ -150,21 +151,27 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const X& x
   const int64_t V = a.V;
 #pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
-    const int64_t sf = (x[mu] == Ls[mu] - 1) ? s - (int64_t)(Ls[mu] - 1) * st[mu] : s + st[mu];
-    const int64_t sb = (x[mu] == 0) ? s + (int64_t)(Ls[mu] - 1) * st[mu] : s - st[mu];
+    const int64_t sf = (x[mu] == Ls[mu] - 1) ? s - (int64_t)((Ls[mu] - 1) * st[mu]) : s + st[mu];
+    const int64_t sb = (x[mu] == 0) ? s + (int64_t)((Ls[mu] - 1) * st[mu]) : s - st[mu];
     const cplx<S>* Um = a.U + (int64_t)mu * 16 * V;
     const cplx<S>* Bm = BSITE ? a.B + (int64_t)mu * 16 * V : a.B + mu * 16;
     // ---- forward hop: U(x) a(x+mu), conj(U(x)) b(x+mu), B(x) b(x+mu), conj(B(x)) a(x+mu)
+    // Each hop issues all of its loads before any product (the scheduling
+    // barrier keeps the compiler from waiting for each link entry in turn).
     {
       C ar[4], ai[4], br[4], bi[4];
+      cplx<S> lk[16];
       xo.template site<C>(sf * 4, ar, ai);
       xo.template site<C>(h + sf * 4, br, bi);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) lk[e] = Um[(int64_t)e * V + s];
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         cx<C> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const cplx<S> u = Um[(int64_t)(4 * r + c) * V + s];
+          const cplx<S> u = lk[4 * r + c];
           const cplx<S> w = BSITE ? Bm[(int64_t)(4 * r + c) * V + s] : Bm[4 * r + c];
           const C ur = (C)u.x, ui = (C)u.y, wr = (C)w.x, wi = (C)w.y;
           mac(t, ur, ui, ar[c], ai[c]);          // U a_f
@@ -179,14 +186,18 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const X& x
     // ---- backward hop: U(x-mu)^H a, U(x-mu)^T b, B(x-mu)^T b, B(x-mu)^H a at x-mu
     {
       C ar[4], ai[4], br[4], bi[4];
+      cplx<S> lk[16];
       xo.template site<C>(sb * 4, ar, ai);
       xo.template site<C>(h + sb * 4, br, bi);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) lk[e] = Um[(int64_t)e * V + sb];
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         cx<C> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const cplx<S> u = Um[(int64_t)(4 * c + r) * V + sb];
+          const cplx<S> u = lk[4 * c + r];
           const cplx<S> w = BSITE ? Bm[(int64_t)(4 * c + r) * V + sb] : Bm[4 * c + r];
           const C ur = (C)u.x, ui = (C)u.y, wr = (C)w.x, wi = (C)w.y;
           mac_conj_a(t, ur, ui, ar[c], ai[c]);   // U^H a_b
@@ -282,147 +293,6 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {   // result 
   }
   __syncthreads();
   return r;
-}
-
-// y = A x with four threads per site: thread q of a site handles direction
-// mu = q (both hops); the partial outputs are summed over the site's four
-// lanes with cross-lane exchanges, after which lane q holds row q of both
-// halves and stores it (the four lanes write the site's components
-// contiguously).  Four times the wavefronts of the one-thread-per-site form,
-// for lattices too small to fill the device with one thread per site.
-template <typename S, bool BSITE, bool DIR>
-__global__ __launch_bounds__(kStencilThreads) void k_stencil_apply4(StencilArgs<S> a,
-                                                                    const cplx<S>* __restrict__ x,
-                                                                    cplx<S>* __restrict__ y,
-                                                                    int64_t ld,
-                                                                    double* __restrict__ apart,
-                                                                    const cplx<S>* __restrict__ dr,
-                                                                    const double* __restrict__ dbeta,
-                                                                    cplx<S>* __restrict__ pnew) {
-  if (a.skip && *a.skip != 0.0) return;   // uniform over the grid
-  __shared__ double sh[kStencilThreads / 64];
-  const int64_t gt = (int64_t)blockIdx.x * kStencilThreads + threadIdx.x;
-  const int64_t s = gt >> 2;
-  const int mu = (int)(gt & 3);
-  const int64_t h = a.V * 4;
-  Operand<S, DIR> xo;
-  if constexpr (DIR) xo = Operand<S, true>{dr, x, *dbeta};
-  else xo = Operand<S, false>{x + (int64_t)blockIdx.y * ld};
-  cplx<S>* yc = y + (int64_t)blockIdx.y * ld;
-  const bool active = s < a.V;          // whole quads are active or not (4 | blockDim)
-  const int64_t sc = active ? s : 0;    // inactive quads compute a harmless site
-  cx<S> top[4], bot[4];
-  {
-    const int Ls[4] = {a.L[0], a.L[1], a.L[2], a.L[3]};
-    const int64_t st[4] = {(int64_t)Ls[1] * Ls[2] * Ls[3], (int64_t)Ls[2] * Ls[3], (int64_t)Ls[3], 1};
-    int64_t r = sc;
-    int xm = 0;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const int xd = (int)(r / st[d]);
-      r -= (int64_t)xd * st[d];
-      if (d == mu) xm = xd;
-    }
-    const int Lm = Ls[mu];
-    const int64_t stm = st[mu];
-    const int64_t sf = (xm == Lm - 1) ? sc - (int64_t)(Lm - 1) * stm : sc + stm;
-    const int64_t sb = (xm == 0) ? sc + (int64_t)(Lm - 1) * stm : sc - stm;
-    const S sca = (S)a.scale;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) top[q] = bot[q] = cx<S>{0, 0};
-    if (mu == 0) {   // the diagonal term, once per site
-      const S dg = (S)a.diag;
-      S ar[4], ai[4], br[4], bi[4];
-      xo.template site<S>(sc * 4, ar, ai);
-      xo.template site<S>(h + sc * 4, br, bi);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        top[q].re = dg * ar[q]; top[q].im = dg * ai[q];
-        bot[q].re = dg * br[q]; bot[q].im = dg * bi[q];
-      }
-    }
-    const int64_t V = a.V;
-    const cplx<S>* Um = a.U + (int64_t)mu * 16 * V;
-    const cplx<S>* Bm = BSITE ? a.B + (int64_t)mu * 16 * V : a.B + mu * 16;
-    {   // forward hop: U(x) a(x+mu), conj(U(x)) b(x+mu), B(x) b(x+mu), conj(B(x)) a(x+mu)
-      S ar[4], ai[4], br[4], bi[4];
-      xo.template site<S>(sf * 4, ar, ai);
-      xo.template site<S>(h + sf * 4, br, bi);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        cx<S> t = {0, 0}, u = {0, 0}, tb = {0, 0}, ub = {0, 0};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const cplx<S> l = Um[(int64_t)(4 * q + c) * V + sc];
-          const cplx<S> w = BSITE ? Bm[(int64_t)(4 * q + c) * V + sc] : Bm[4 * q + c];
-          mac(t, l.x, l.y, ar[c], ai[c]);
-          mac_conj_a(u, l.x, l.y, br[c], bi[c]);
-          mac(tb, w.x, w.y, br[c], bi[c]);
-          mac_conj_a(ub, w.x, w.y, ar[c], ai[c]);
-        }
-        top[q].re += sca * tb.re - t.re; top[q].im += sca * tb.im - t.im;
-        bot[q].re -= u.re + sca * ub.re; bot[q].im -= u.im + sca * ub.im;
-      }
-    }
-    {   // backward hop: U(x-mu)^H a, U(x-mu)^T b, B(x-mu)^T b, B(x-mu)^H a at x-mu
-      S ar[4], ai[4], br[4], bi[4];
-      xo.template site<S>(sb * 4, ar, ai);
-      xo.template site<S>(h + sb * 4, br, bi);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        cx<S> t = {0, 0}, u = {0, 0}, tb = {0, 0}, ub = {0, 0};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const cplx<S> l = Um[(int64_t)(4 * c + q) * V + sb];
-          const cplx<S> w = BSITE ? Bm[(int64_t)(4 * c + q) * V + sb] : Bm[4 * c + q];
-          mac_conj_a(t, l.x, l.y, ar[c], ai[c]);
-          mac(u, l.x, l.y, br[c], bi[c]);
-          mac(tb, w.x, w.y, br[c], bi[c]);
-          mac_conj_a(ub, w.x, w.y, ar[c], ai[c]);
-        }
-        top[q].re -= t.re + sca * tb.re; top[q].im -= t.im + sca * tb.im;
-        bot[q].re += sca * ub.re - u.re; bot[q].im += sca * ub.im - u.im;
-      }
-    }
-  }
-  // sum over the site's four lanes (adjacent lanes of one quad)
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-#pragma unroll
-    for (int o = 1; o <= 2; o <<= 1) {
-      top[q].re += __shfl_xor(top[q].re, o); top[q].im += __shfl_xor(top[q].im, o);
-      bot[q].re += __shfl_xor(bot[q].re, o); bot[q].im += __shfl_xor(bot[q].im, o);
-    }
-  }
-  cx<S> ot = top[0], ob = bot[0];   // row mu of this site
-#pragma unroll
-  for (int q = 1; q < 4; ++q)
-    if (mu == q) { ot = top[q]; ob = bot[q]; }
-  double are = 0.0, aim = 0.0;
-  if (active) {
-    cplx<S> t, b;
-    t.x = ot.re; t.y = ot.im;
-    b.x = ob.re; b.y = ob.im;
-    yc[s * 4 + mu] = t;
-    yc[h + s * 4 + mu] = b;
-    if (apart || DIR) {
-      const cplx<S> x0 = xo.elem(s * 4 + mu), x1 = xo.elem(h + s * 4 + mu);
-      if constexpr (DIR) {
-        pnew[s * 4 + mu] = x0;
-        pnew[h + s * 4 + mu] = x1;
-      }
-      are = (double)x0.x * t.x + (double)x0.y * t.y + (double)x1.x * b.x + (double)x1.y * b.y;
-      aim = (double)x0.x * t.y - (double)x0.y * t.x + (double)x1.x * b.y - (double)x1.y * b.x;
-    }
-  }
-  if (apart) {   // uniform over the grid
-    are = block_sum<kStencilThreads>(are, sh);
-    aim = block_sum<kStencilThreads>(aim, sh);
-    if (threadIdx.x == 0) {
-      apart[2 * blockIdx.x] = are;
-      apart[2 * blockIdx.x + 1] = aim;
-    }
-  }
 }
 
 // ||A x_c - lam_c x_c||^2 per block in FP64 (x stored as S).
@@ -656,19 +526,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_resid(DenseArgs<S> a,
 
 }  // namespace
 
-// The apply runs four threads per site (k_stencil_apply4).
-// Four threads per site pay only where one thread per site leaves the device
-// short of wavefronts: measured faster for FP32 at 16^4 (23.7 us against
-// 31.8 us), slower for FP64 at 16^4 (44.1 against 33.5 us) and for both at
-// 32^4 (339 / 584 us against 282 / 490 us), where the longer per-thread work
-// already hides the latency.  es: bytes per complex element.
-static bool stencil_quad(int64_t V, int es) { return es == 8 && V <= (int64_t)1 << 17; }
-
 int stencil_resid_blocks(int64_t V) { return (int)((V + kStencilThreads - 1) / kStencilThreads); }
-int stencil_apply_blocks(int64_t V, int es) {
-  return stencil_quad(V, es) ? (int)((4 * V + kStencilThreads - 1) / kStencilThreads)
-                             : stencil_resid_blocks(V);
-}
+int stencil_apply_blocks(int64_t V) { return stencil_resid_blocks(V); }
 int dense_apply_blocks(int64_t h) { return (int)((h + kDenseRows - 1) / kDenseRows); }
 int dense_resid_blocks(int64_t h) { return (int)((h + kDenseThreads / 64 - 1) / (kDenseThreads / 64)); }
 
@@ -676,17 +535,6 @@ template <typename S, bool DIR>
 hipError_t stencil_apply_impl(const StencilArgs<S>& a, const cplx<S>* x, cplx<S>* y, int64_t ld,
                               int nrhs, double* apart, const cplx<S>* dr, const double* dbeta,
                               cplx<S>* pnew, hipStream_t st) {
-  constexpr int es = (int)sizeof(cplx<S>);
-  if (stencil_quad(a.V, es)) {
-    dim3 grid4((unsigned)stencil_apply_blocks(a.V, es), (unsigned)nrhs);
-    if (a.b_per_site)
-      hipLaunchKernelGGL((k_stencil_apply4<S, true, DIR>), grid4, dim3(kStencilThreads), 0, st, a, x,
-                         y, ld, apart, dr, dbeta, pnew);
-    else
-      hipLaunchKernelGGL((k_stencil_apply4<S, false, DIR>), grid4, dim3(kStencilThreads), 0, st, a,
-                         x, y, ld, apart, dr, dbeta, pnew);
-    return hipGetLastError();
-  }
   dim3 grid((unsigned)((a.V + kStencilThreads - 1) / kStencilThreads), (unsigned)nrhs);
   if (a.b_per_site)
     hipLaunchKernelGGL((k_stencil_apply<S, true, DIR>), grid, dim3(kStencilThreads), 0, st, a, x, y,

@@ -44,8 +44,8 @@ def test_stencil_apply(ctx, L, mixed, b_per_site):
 @pytest.mark.parametrize("L", [(16, 16, 16, 16), (24, 24, 16, 16)])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_stencil_apply_large(ctx, L, mixed):
-    """The benchmark's 16^4 shape and one past the size where FP32 switches
-    from four threads per site to one (V = 147456 > 2^17), every output."""
+    """The benchmark's 16^4 shape and a lattice with unequal extents
+    (V = 147456), every output."""
     from paper_2001_07428_amd import jlanczos as J
     say("stencil_apply large", L, mixed)
     U, B = inputs.stencil_links(4, L)
