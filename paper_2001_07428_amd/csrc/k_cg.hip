@@ -25,7 +25,10 @@ namespace jl {
 namespace {
 
 constexpr int kCgThreads = 256;
-constexpr int kCgMaxBlocks = 2048;
+// At most 256 workgroups, one per CU: every workgroup of the fused step counts
+// itself on one shared counter, and fewer workgroups contend less for it.
+constexpr int kCgMaxBlocks = 256;
+constexpr int kCgUnroll = 4;   // chunks per thread loaded together in the fused step
 
 template <typename S> constexpr int kPerChunk = 16 / (int)sizeof(S);   // scalars per 16 bytes
 
@@ -127,6 +130,27 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_update_fused(
   __shared__ double bcast;
   __shared__ bool last;
   if (cg_done(cs)) return;   // uniform
+  constexpr int K = kPerChunk<S>;
+  constexpr int U = kCgUnroll;
+  const int64_t c0 = (int64_t)blockIdx.x * kCgThreads + threadIdx.x;
+  const int64_t cstep = (int64_t)gridDim.x * kCgThreads;
+  // The operands of the first U chunks do not depend on alpha: their loads go
+  // out before the reduction of the apply partials, so the two waits overlap.
+  S xv[U][K], rv[U][K], pv[U][K], qv[U][K];
+  auto load = [&](int64_t cb) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t c = cb + u * cstep;
+      if (c < nchunk) {
+        ld16<S>(x + c * K, xv[u]);
+        ld16<S>(r + c * K, rv[u]);
+        ld16<S>(p + c * K, pv[u]);
+        ld16<S>(q + c * K, qv[u]);
+      }
+    }
+  };
+  load(c0);
+  const double rr_old = cs[CG_RR];
   const double pap = cg_reduce(apart, napply, 2, sh);
   if (threadIdx.x == 0) bcast = pap;
   __syncthreads();
@@ -135,24 +159,23 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_update_fused(
     if (blockIdx.x == 0 && threadIdx.x == 0) cs[CG_DONE] = 2.0;
     return;
   }
-  const double al = cs[CG_RR] / pq;
-  constexpr int K = kPerChunk<S>;
+  const double al = rr_old / pq;
   double acc = 0.0;
-  for (int64_t c = (int64_t)blockIdx.x * kCgThreads + threadIdx.x; c < nchunk;
-       c += (int64_t)gridDim.x * kCgThreads) {
-    S xv[K], rv[K], pv[K], qv[K];
-    ld16<S>(x + c * K, xv);
-    ld16<S>(r + c * K, rv);
-    ld16<S>(p + c * K, pv);
-    ld16<S>(q + c * K, qv);
+  for (int64_t cb = c0; cb < nchunk; cb += U * cstep) {
+    if (cb != c0) load(cb);
 #pragma unroll
-    for (int e = 0; e < K; ++e) {
-      xv[e] = (S)((double)xv[e] + al * (double)pv[e]);
-      rv[e] = (S)((double)rv[e] - al * (double)qv[e]);
-      acc += (double)rv[e] * rv[e];
+    for (int u = 0; u < U; ++u) {
+      const int64_t c = cb + u * cstep;
+      if (c >= nchunk) continue;
+#pragma unroll
+      for (int e = 0; e < K; ++e) {
+        xv[u][e] = (S)((double)xv[u][e] + al * (double)pv[u][e]);
+        rv[u][e] = (S)((double)rv[u][e] - al * (double)qv[u][e]);
+        acc += (double)rv[u][e] * rv[u][e];
+      }
+      st16<S>(x + c * K, xv[u]);
+      st16<S>(r + c * K, rv[u]);
     }
-    st16<S>(x + c * K, xv);
-    st16<S>(r + c * K, rv);
   }
   acc = cg_block_sum(acc, sh);
   if (threadIdx.x == 0) {
