@@ -117,8 +117,7 @@ __device__ void wg_apply(const BatchProblem& pb, const cplx<S>* __restrict__ x, 
     const cplx<S>* r11 = A11 + r * pb.ld;
     const cplx<S>* r12 = A12 + r * pb.ld;
     cx2<C> p{0, 0}, q{0, 0};
-    for (int64_t c = lane; c < h; c += 64) {
-      const cplx<S> m11 = r11[c], m12 = r12[c];
+    auto acc = [&](const cplx<S>& m11, const cplx<S>& m12, int64_t c) {
       const cplx<S> a = L.sv[c], b = L.sv[h + c];
       const C m11r = m11.x, m11i = m11.y, m12r = m12.x, m12i = m12.y;
       const C ar = a.x, ai = a.y, br = b.x, bi = b.y;
@@ -128,7 +127,20 @@ __device__ void wg_apply(const BatchProblem& pb, const cplx<S>* __restrict__ x, 
       // q += A11 conj(b) - A12 conj(a)
       q.re += m11r * br + m11i * bi - m12r * ar - m12i * ai;
       q.im += -m11r * bi + m11i * br + m12r * ai - m12i * ar;
+    };
+    int64_t c = lane;
+    for (; c + 3 * 64 < h; c += 4 * 64) {   // four steps' loads in flight together
+      cplx<S> m11[4], m12[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        m11[k] = r11[c + 64 * k];
+        m12[k] = r12[c + 64 * k];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc(m11[k], m12[k], c + 64 * k);
     }
+    for (; c < h; c += 64) acc(r11[c], r12[c], c);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       p.re += __shfl_xor(p.re, o);
@@ -191,15 +203,28 @@ __device__ void wg_dots(const cplx<S>* __restrict__ V, int64_t n, int ncol, cplx
     const cplx<S>* vt = V + (int64_t)c * n;
     const cplx<S>* vb = vt + h;
     double cvr = 0, cvi = 0, cwr = 0, cwi = 0;
-    for (int64_t p = lane; p < h; p += 64) {
-      const cplx<S> a = vt[p], b = vb[p], ut = L.su[p], ub = L.su[h + p];
+    auto acc = [&](const cplx<S>& a, const cplx<S>& b, int64_t p) {
+      const cplx<S> ut = L.su[p], ub = L.su[h + p];
       const double vtr = a.x, vti = a.y, vbr = b.x, vbi = b.y;
       const double utr = ut.x, uti = ut.y, ubr = ub.x, ubi = ub.y;
       cvr += vtr * utr + vti * uti + vbr * ubr + vbi * ubi;
       cvi += vtr * uti - vti * utr + vbr * ubi - vbi * ubr;
       cwr += vtr * ubr - vti * ubi - vbr * utr + vbi * uti;
       cwi += vtr * ubi + vti * ubr - vbr * uti - vbi * utr;
+    };
+    int64_t p = lane;
+    for (; p + 3 * 64 < h; p += 4 * 64) {   // four steps' loads in flight together
+      cplx<S> a[4], b[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        a[k] = vt[p + 64 * k];
+        b[k] = vb[p + 64 * k];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc(a[k], b[k], p + 64 * k);
     }
+    for (; p < h; p += 64) acc(vt[p], vb[p], p);
     cvr = wsum(cvr); cvi = wsum(cvi); cwr = wsum(cwr); cwi = wsum(cwi);
     if (lane == 0) {
       L.coef[4 * c + 0] = cvr; L.coef[4 * c + 1] = cvi;
@@ -218,16 +243,28 @@ __device__ double wg_update(const cplx<S>* __restrict__ V, int64_t n, int ncol,
   double nrm = 0.0;
   for (int64_t p = threadIdx.x; p < h; p += NT) {
     double dtr = 0, dti = 0, dbr = 0, dbi = 0;
-    for (int c = 0; c < ncol; ++c) {
+    auto acc = [&](const cplx<S>& a, const cplx<S>& b, int c) {
       const double cvr = L.coef[4 * c], cvi = L.coef[4 * c + 1];
       const double cwr = L.coef[4 * c + 2], cwi = L.coef[4 * c + 3];
-      const cplx<S> a = V[(int64_t)c * n + p], b = V[(int64_t)c * n + h + p];
       const double tr = a.x, ti = a.y, br = b.x, bi = b.y;
       dtr += tr * cvr - ti * cvi - br * cwr - bi * cwi;
       dti += tr * cvi + ti * cvr - br * cwi + bi * cwr;
       dbr += br * cvr - bi * cvi + tr * cwr + ti * cwi;
       dbi += br * cvi + bi * cvr + tr * cwi - ti * cwr;
+    };
+    int c = 0;
+    for (; c + 3 < ncol; c += 4) {   // four columns' loads in flight together
+      cplx<S> a[4], b[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        a[k] = V[(int64_t)(c + k) * n + p];
+        b[k] = V[(int64_t)(c + k) * n + h + p];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc(a[k], b[k], c + k);
     }
+    for (; c < ncol; ++c) acc(V[(int64_t)c * n + p], V[(int64_t)c * n + h + p], c);
     cplx<S> t = L.su[p], b = L.su[h + p];
     t.x = (S)((double)t.x - dtr); t.y = (S)((double)t.y - dti);
     b.x = (S)((double)b.x - dbr); b.y = (S)((double)b.y - dbi);

@@ -8,7 +8,7 @@ times every combination on the caller's batch (replays of the captured graph,
 median of `reps`) and records the fastest in a JSON cache keyed by the device
 name and a signature of the batch (count, size histogram, nev, m, dtype).
 
-    python -m paper_2001_07428_amd.tune --workload batched512   # on a GPU
+    python -m paper_2001_07428_amd.tune   # on a GPU; the defaults are the 512-problem benchmark batch
 
 Batch(..., threads=0, blocks=0) looks the shape up in the cache (tuned.json
 next to this file) and falls back to the library default (256 threads,
