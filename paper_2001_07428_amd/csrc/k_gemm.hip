@@ -73,41 +73,49 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A
   const int b_c = tid / B_TPC;
   const int b_k = (tid % B_TPC) * B_PER_T;
 
-  T ra[A_PER_T], rb[B_PER_T];
+  // Raw loads; the out-of-range values are zeroed when the registers are
+  // stored to LDS, after the products, so nothing waits for the loads before
+  // then.  Every load is unconditional, at an index clamped into the matrix:
+  // a load under a condition is a branch the compiler closes by waiting for
+  // it, which would serialise the prefetch of the next K step instead of
+  // overlapping it with the products.  M is a multiple of AV (checked at
+  // launch), so an A vector is wholly in range or not.
+  S ra[A_PER_T];
+  T rb[B_PER_T];
+  bool a_in[A_PER_T / AV], b_in[B_PER_T];
   auto load = [&](int k0) {
     const int k = k0 + a_k;
+    const int kc = k < K ? k : K - 1;
 #pragma unroll
     for (int v = 0; v < A_PER_T; v += AV) {
       const int64_t row = m0 + a_r + v;
-      if (k < K && row + AV <= M) {
-        const S* p = A + (int64_t)k * lda + row;
-        if constexpr (AV == 4) {
-          const float4 t = *reinterpret_cast<const float4*>(p);
-          ra[v] = t.x; ra[v + 1] = t.y; ra[v + 2] = t.z; ra[v + 3] = t.w;
-        } else {
-          const double2 t = *reinterpret_cast<const double2*>(p);
-          ra[v] = t.x; ra[v + 1] = t.y;
-        }
+      a_in[v / AV] = k < K && row < M;
+      const S* p = A + (int64_t)kc * lda + (row < M ? row : M - AV);
+      if constexpr (AV == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        ra[v] = t.x; ra[v + 1] = t.y; ra[v + 2] = t.z; ra[v + 3] = t.w;
       } else {
-#pragma unroll
-        for (int e = 0; e < AV; ++e) {
-          const int64_t r = row + e;
-          ra[v + e] = (k < K && r < M) ? (T)A[(int64_t)k * lda + r] : (T)0;
-        }
+        const double2 t = *reinterpret_cast<const double2*>(p);
+        ra[v] = t.x; ra[v + 1] = t.y;
       }
     }
     const int col = n0 + b_c;
+    const int colc = col < N ? col : N - 1;
 #pragma unroll
     for (int e = 0; e < B_PER_T; ++e) {
       const int kk = k0 + b_k + e;
-      rb[e] = (col < N && kk < K) ? B[(int64_t)col * ldb + kk] : (T)0;
+      b_in[e] = col < N && kk < K;
+      rb[e] = B[(int64_t)colc * ldb + (kk < K ? kk : K - 1)];
     }
   };
+  // B takes a 0/1 factor rather than a select, which the compiler would turn
+  // back into a branch (the column test is uniform across the wavefront); the
+  // clamped values are finite, so the product is 0.
   auto store = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < A_PER_T; ++e) As[buf][a_k][a_r + e] = ra[e];
+    for (int e = 0; e < A_PER_T; ++e) As[buf][a_k][a_r + e] = a_in[e / AV] ? (T)ra[e] : (T)0;
 #pragma unroll
-    for (int e = 0; e < B_PER_T; ++e) Bs[buf][b_k + e][b_c] = rb[e];
+    for (int e = 0; e < B_PER_T; ++e) Bs[buf][b_k + e][b_c] = rb[e] * (b_in[e] ? (T)1 : (T)0);
   };
 
   typename MF::acc_t acc[4][4];
@@ -122,7 +130,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A
     const int buf = kt & 1;
     store(buf);
     __syncthreads();
-    if (kt + 1 < nk) load((kt + 1) * BK);
+    load((kt + 1) * BK);   // past the last step the values are zeros and unused
+    // the prefetch is issued before the products (the scheduler would
+    // otherwise sink it below them and wait for it at once)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const int kr = ks * 4 + lane / 16;
@@ -168,7 +179,7 @@ hipError_t launch_gemm_nn(const S* A, int64_t lda, const T* B, int64_t ldb, S* C
   // 16-byte vector loads/stores of A and C columns need 4-element (FP32) or
   // 2-element (FP64) alignment of every column start.
   const int AV = 16 / (int)sizeof(S);
-  if ((lda % AV) || (ldc % AV) || ((uintptr_t)A % 16) || ((uintptr_t)C % 16))
+  if ((lda % AV) || (ldc % AV) || (M % AV) || K <= 0 || ((uintptr_t)A % 16) || ((uintptr_t)C % 16))
     return hipErrorInvalidValue;
   const int64_t tm = (M + BM - 1) / BM;
   const int tn = (N + BN - 1) / BN;
