@@ -7,7 +7,10 @@
 //   - per Lanczos step: t_jj (accumulated in the operator apply), the norm
 //     b0 after the local three-term step and the norm b1 after each
 //     reorthogonalisation pass (the sqrt(2) test of Alg. 2 is taken on the
-//     host); one stream synchronisation per pass;
+//     host), fetched in one copy; the normalisation of v_{j+1} (its factor
+//     read on the device) and the next operator apply are queued before the
+//     host waits for that copy, and are redone in the rare step that needs
+//     another pass;
 //   - once per cycle the sorted Ritz values, the last row of Z and the true
 //     residuals of the candidates.
 // In invert mode each step's u = A^-1 v_j comes from conjugate gradients

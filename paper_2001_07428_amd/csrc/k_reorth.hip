@@ -8,10 +8,15 @@
 // element p of the top half with element p of the bottom half.
 //
 // dots:   per block, FP64 partial sums of v_i^H u and w_i^H u for every
-//         column, plus ||u||^2; one wavefront per column at a time, u held in
-//         registers (converted to FP64), FP64 products and accumulation.
+//         column, plus ||u||^2; one wavefront per column (FP32: per two
+//         columns) at a time, u held in registers (converted to FP64), FP64
+//         products and accumulation; the partials are summed by
+//         k_reduce_wide (tiles of columns x slices of blocks).
 // update: u -= V c_v + W c_w with the FP64 coefficients rounded to the
-//         storage type, then ||u||^2 in FP64; one pass over the basis.
+//         storage type, then ||u||^2 in FP64, summed over the blocks by the
+//         last one to finish; one pass over the basis.
+// Both read the basis with non-temporal loads once a pass is larger than
+// the last-level cache.
 #include <algorithm>
 #include <type_traits>
 
