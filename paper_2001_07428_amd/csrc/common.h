@@ -137,7 +137,7 @@ hipError_t launch_tek_resid(const TekArgs<S>& a, const cplx<S>* X, int64_t ldx, 
 // Basis V: ncol columns of length n = 2h, column stride ldv.
 // dots: partial[blk][4*ncol + 1] = per block (Re, Im of v_i^H u, Re, Im of
 // w_i^H u) for each column, then ||u||^2.
-int reorth_dots_blocks(int64_t h);     // partial rows written by dots
+int reorth_dots_blocks(int64_t h, int es);   // partial rows written by dots; es: bytes per complex
 int reorth_update_blocks(int64_t h, int es);   // partial entries written by update (es: bytes per complex)
 constexpr int kReorthMaxCols = 2048;   // largest basis dots supports
 // With tloc != nullptr the kernel first applies the local three-term step
@@ -151,7 +151,7 @@ hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* 
                               double* partial, int nblk, hipStream_t st,
                               const double* tloc = nullptr, double beta = 0.0, int jl = 0,
                               cplx<S>* uout = nullptr, int groups = 1);
-int reorth_dots_groups(int64_t h);
+int reorth_dots_groups(int64_t h, int es);
 // update: u -= V c_v + W c_w (W = J V^*), coef = [4*ncol] FP64 (Re cv, Im cv,
 // Re cw, Im cw per column); partial[blk] = ||u_new||^2 per block.
 // jsym = false leaves out the W projection (standard Gram-Schmidt against V).

@@ -284,11 +284,11 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   L.V[0] = take((size_t)n * (m + 1) * es);
   L.V[1] = take((size_t)n * (m + 1) * es);
   L.apart = take(sizeof(double) * 2 * (size_t)op_apply_blocks(op));
-  L.dots_part = take(sizeof(double) * (size_t)reorth_dots_blocks(h) * (4 * (size_t)(m + 1) + 1));
+  L.dots_part = take(sizeof(double) * (size_t)reorth_dots_blocks(h, es) * (4 * (size_t)(m + 1) + 1));
   L.upd_part = take(sizeof(double) * (size_t)std::max(reorth_update_blocks(h, es), 1));
   L.coef = take(sizeof(double) * (4 * (size_t)(m + 1) + 1));
   const int wcols = 4 * (m + 1) + 1;   // the most inner products one pass reduces
-  L.wide_scr = take(sizeof(double) * reduce_wide_scratch_doubles(reorth_dots_blocks(h), wcols));
+  L.wide_scr = take(sizeof(double) * reduce_wide_scratch_doubles(reorth_dots_blocks(h, es), wcols));
   L.wide_cnt = take(sizeof(unsigned) * ((size_t)reduce_wide_tiles(wcols) + 1));   // + update norm
   L.scal = take(sizeof(double) * 64);
   L.Tdev = take(sizeof(double) * (size_t)m * m);
@@ -300,7 +300,7 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   L.res_out = take(sizeof(double) * p->nev);
   L.res_lam = take(sizeof(double) * p->nev);
   L.res_cols = take(sizeof(int) * p->nev);
-  const int gd = reorth_dots_groups(h), gu = reorth_update_groups(h, es);
+  const int gd = reorth_dots_groups(h, es), gu = reorth_update_groups(h, es);
   if (gd > 1) L.rloc = take((size_t)n * es);              // the locally updated u (column groups)
   if (gu > 1) L.rd = take((size_t)gu * n * es);           // per-group corrections
   if (p->invert) {   // CG: x, r, q, two directions; partial sums; device scalars
@@ -467,11 +467,11 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   }
   const int ncgb = cg_blocks(n);
   // column groups of the reorthogonalisation kernels for short vectors
-  const int gd = reorth_dots_groups(h), gu = reorth_update_groups(h, es);
+  const int gd = reorth_dots_groups(h, es), gu = reorth_update_groups(h, es);
   cplx<S>* uloc = gd > 1 ? reinterpret_cast<cplx<S>*>(base + L.rloc) : nullptr;
   cplx<S>* dscr = gu > 1 ? reinterpret_cast<cplx<S>*>(base + L.rd) : nullptr;
 
-  const int ndots = reorth_dots_blocks(h);
+  const int ndots = reorth_dots_blocks(h, es);
   const int wtiles = reduce_wide_tiles(4 * (m + 1) + 1);
   unsigned* upd_cnt = wide_cnt + wtiles;
   JL_HIP(ctx, hipMemsetAsync(wide_cnt, 0, sizeof(unsigned) * ((size_t)wtiles + 1), st));

@@ -16,7 +16,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // dots partials | update partials | wide-reduction slices | its tile counters
 size_t reorth_ws_part(int64_t n, int ncol, int which) {
   const int64_t h = n / 2;
-  const int nd = reorth_dots_blocks(h), stride = 4 * ncol + 1;
+  const int nd = std::max(reorth_dots_blocks(h, 8), reorth_dots_blocks(h, 16)), stride = 4 * ncol + 1;
   const size_t sz[4] = {
       align_up(sizeof(double) * (size_t)nd * (size_t)stride),
       align_up(sizeof(double) *
@@ -33,7 +33,8 @@ template <typename S>
 hipError_t reorth_pass(int64_t n, int ncol, const cplx<S>* V, int64_t ldv, cplx<S>* u, double* coef,
                        char* ws, hipStream_t st) {
   const int64_t h = n / 2;
-  const int nd = reorth_dots_blocks(h), nu = reorth_update_blocks(h, (int)sizeof(cplx<S>));
+  const int nd = reorth_dots_blocks(h, (int)sizeof(cplx<S>)),
+            nu = reorth_update_blocks(h, (int)sizeof(cplx<S>));
   double* dp = reinterpret_cast<double*>(ws);
   double* up = reinterpret_cast<double*>(ws + reorth_ws_part(n, ncol, 1));
   double* scr = reinterpret_cast<double*>(ws + reorth_ws_part(n, ncol, 2));
