@@ -489,6 +489,13 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   Pinned pin;
   const size_t pin_doubles = 16 + CG_NSLOTS + 3 * (size_t)m + 3 * (size_t)nev;
   JL_HIP(ctx, hipHostMalloc((void**)&pin.p, sizeof(double) * pin_doubles, hipHostMallocDefault));
+  // Every return waits for the stream first (an error can leave queued work,
+  // such as the next step's speculative apply); declared after `pin`, so the
+  // wait comes before the pinned scalars are freed.
+  struct StreamWait {
+    hipStream_t s;
+    ~StreamWait() { (void)hipStreamSynchronize(s); }
+  } stream_wait{st};
   double* hs = pin.p;                    // [16] scalars
   double* h_cg = pin.p + 16;             // [CG_NSLOTS] CG scalars
   double* h_lam = h_cg + CG_NSLOTS;      // [m]
