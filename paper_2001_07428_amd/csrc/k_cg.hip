@@ -25,8 +25,10 @@ namespace jl {
 namespace {
 
 constexpr int kCgThreads = 256;
-// At most 256 workgroups, one per CU: every workgroup of the fused step counts
-// itself on one shared counter, and fewer workgroups contend less for it.
+// At most 256 workgroups, one per CU, each thread with four chunks whose loads
+// are in flight together (and 256 partial sums for the last workgroup): at
+// 16^4 the fused step took 9 us less than with 1024 workgroups of one chunk
+// per thread, whether those counted on one counter or on eight.
 constexpr int kCgMaxBlocks = 256;
 constexpr int kCgUnroll = 4;   // chunks per thread loaded together in the fused step
 
