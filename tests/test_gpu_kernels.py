@@ -57,6 +57,27 @@ def test_stencil_apply_large(ctx, L, mixed):
     assert _rel(y, jsym.stencil_apply(U, B, L, x[0])) < (2e-6 if mixed else 1e-14)
 
 
+_LINKS32 = {}
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_stencil_apply_32(ctx, mixed):
+    """The 32^4 lattice of the headline configuration (n = 8388608), every
+    output, in the launch configuration the solver uses."""
+    from paper_2001_07428_amd import jlanczos as J
+    L = (32, 32, 32, 32)
+    say("stencil_apply 32^4", mixed)
+    if not _LINKS32:
+        _LINKS32["UB"] = inputs.stencil_links(5, L)
+    U, B = _LINKS32["UB"]
+    n = 2 * int(np.prod(L)) * 4
+    x = inputs.cn(np.random.default_rng(11), (1, n))
+    dt = cdt(mixed)
+    op = J.jl_op_create_stencil(ctx, L, to_dev(U, dt), to_dev(B, dt))
+    y = to_np(J.jl_op_apply(op, to_dev(x, dt)))[0]
+    assert _rel(y, jsym.stencil_apply(U, B, L, x[0])) < (2e-6 if mixed else 1e-14)
+
+
 @pytest.mark.parametrize("h", [100, 33, 1, 1500, 2053])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_dense_apply(ctx, h, mixed):
@@ -88,14 +109,16 @@ def test_pair_vectors(ctx, mixed):
 
 # ----------------------------------------------------------- reorthogonalisation
 @pytest.mark.parametrize("h,ncol", [(1000, 7), (33, 5), (5000, 130), (4096, 1), (640, 0),
-                                    (40000, 77), (262144, 70), (300, 2047)])
+                                    (40000, 77), (262144, 70), (300, 2047),
+                                    (4194304, 6)])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_reorth_pass(ctx, h, ncol, mixed):
     """One block Gram-Schmidt pass against [V, W = J V^*] (Alg. 2).  The two
     long vectors take the inner-product reduction over 2 and 16 row slices
     (tiles of 64 sums, the last one ragged); the 262144-pair case's basis
-    (over 256 MB) is read with non-temporal loads; 2047 columns is the largest
-    basis a pass takes (its LDS accumulators and 128 reduction tiles)."""
+    (over 256 MB) is read with non-temporal loads, as is the 32^4-sized one
+    (4194304 pairs); 2047 columns is the largest basis a pass takes (its LDS
+    accumulators and 128 reduction tiles)."""
     from paper_2001_07428_amd import jlanczos as J
     say("reorth_pass", h, ncol, mixed)
     rng = np.random.default_rng(6)
