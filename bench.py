@@ -1,15 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the J-symmetric thick-restart Lanczos solver on one MI355X.
 
-A step is one complete solve (Algorithms 1 and 2: matvec, J-restricted
-reorthogonalisation, Rayleigh-Ritz, basis update, true-residual checks,
-partner-free output) on synthetic input already resident in HBM.  The same
-workload is solved in the mixed form (FP32 complex operator and basis, FP64
-reductions and Ritz problem) and in plain FP64; `value` is the mixed time to
-the nev converged pairs, the FP64 time is reported beside it.
+The default workload is the 32^4 J-stencil (n = 8388608, 200 lowest pairs,
+m = 500, mwin = 250).  For the stencil workloads a step is one outer
+iteration of Algorithm 1 (the Lanczos steps of Algorithm 2 with their
+J-restricted reorthogonalisation, the Rayleigh-Ritz step, the basis update
+and the true-residual checks): one mixed-precision solve (FP32 complex
+operator and basis, FP64 reductions and Ritz problem) runs to the nev
+converged pairs, its first W iterations are the warm-up and the next K are
+timed (the solver records the wall time at the end of every iteration, where
+the device is idle); `value` is the wall time of that whole solve, i.e. the
+mixed time to the nev converged pairs.  The plain FP64 solver runs the same
+W + K iterations on the same input, so the two precisions are compared on
+the same steps.  For the other workloads a step is one complete solve (or
+one replay of the batched graph).
 
     python bench.py [--steps K] [--warmup W]
-                    [--workload stencil16|stencil32|dense4096|batched512|casea|invert16|
+                    [--workload stencil32|stencil16|dense4096|batched512|casea|invert16|
                                 tek289|tek289inv]
 
 Prints one JSON line.  Only one GPU is used; --gpus N > 1 exits with a message.
@@ -34,9 +41,9 @@ HBM_PEAK_GBPS = 8000.0
 WORKLOADS = {
     # 4D J-stencil, d = 4, Haar links, complex normal B (seeded)
     "stencil16": dict(kind="stencil", L=(16, 16, 16, 16), seed=4, nev=100, m=300, mwin=150,
-                      tol=1e-5, tol_relative=False),
+                      tol=1e-5, tol_relative=False, step="cycle"),
     "stencil32": dict(kind="stencil", L=(32, 32, 32, 32), seed=5, nev=200, m=500, mwin=250,
-                      tol=1e-5, tol_relative=False),
+                      tol=1e-5, tol_relative=False, step="cycle"),
     # dense random Hermitian J-symmetric, n = 4096; the mixed tolerance is
     # relative to max|theta| (the FP32 matvec itself errs by ~2e-5 here)
     "dense4096": dict(kind="dense", h=2048, seed=2, nev=50, m=160, mwin=80, tol=1e-5,
@@ -133,6 +140,46 @@ def make_op(J, ctx, w, host, dtype):
     A11 = torch.from_numpy(host["A11"]).to("cuda:0", dtype)
     A12 = torch.from_numpy(host["A12"]).to("cuda:0", dtype)
     return J.jl_op_create_dense(ctx, A11, A12)
+
+
+def cycle_step_time(ct, warmup, steps):
+    """Mean wall time of outer iterations warmup+1 .. warmup+steps, from the
+    times ct[c] at the end of iteration c+1 (measured from the solve's start)."""
+    if steps < 1 or len(ct) < warmup + steps:
+        raise RuntimeError(f"the solve took {len(ct)} outer iterations, fewer than warmup + steps = "
+                           f"{warmup + steps}: lower --steps/--warmup")
+    start = ct[warmup - 1] if warmup > 0 else 0.0
+    return (ct[warmup + steps - 1] - start) / steps
+
+
+def run_cycles(J, ctx, w, host, mixed, steps, warmup, verbose, full):
+    """One event-timed solve with the wall time of every outer iteration.
+    full: run to the nev converged pairs (else stop after warmup + steps
+    iterations).  Returns the solve's wall time, the time per iteration over
+    iterations warmup+1 .. warmup+steps, and the solve's statistics."""
+    import torch
+    dtype = torch.complex64 if mixed else torch.complex128
+    op = make_op(J, ctx, w, host, dtype)
+    tol = w["tol"]
+    nb = J.jl_workspace_bytes(op, w["nev"], w["m"], w["mwin"], tol)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+    # loads the code objects and touches the workspace (a 4-step solve)
+    J.jl_solve(op, 2, 8, 4, tol, max_cycles=1, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = J.jl_solve(op, w["nev"], w["m"], w["mwin"], tol, timing=True, workspace=ws,
+                     verbose=verbose, max_cycles=0 if full else warmup + steps,
+                     cycle_times_cap=100000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ct = out.cycle_times
+    if full and out.status != J.JL_OK:
+        raise RuntimeError(f"solve did not converge: status {out.status}, stats {out.stats}")
+    res = dict(wall=wall, step=cycle_step_time(ct, warmup, steps), stats=dict(out.stats), last=out,
+               n=op.n, cycle_times=ct)
+    del ws, op
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_precision(J, ctx, w, host, mixed, steps, warmup, verbose):
@@ -315,6 +362,70 @@ def cpu_baseline_batched(w, host, budget_s):
                        f"mean time per problem scaled to {w['count']} (extrapolated)")
 
 
+def main_cycles(args, J, ctx, w, host):
+    """Stencil workloads: a step is one outer iteration of Algorithm 1.  The
+    mixed solve runs to convergence (value = its wall time); the FP64 solve
+    runs the same warmup + steps iterations."""
+    print(f"[bench] {describe(w)}: mixed solve (to {w['nev']} converged pairs)", file=sys.stderr,
+          flush=True)
+    mixed = run_cycles(J, ctx, w, host, True, args.steps, args.warmup, args.verbose, full=True)
+    st = mixed["stats"]
+    print(f"[bench] mixed: {mixed['wall']:.2f} s, {st['cycles']} iterations, {st['n_mv']} matvecs",
+          file=sys.stderr, flush=True)
+    rates = kernel_rates(st)
+    dom = max(("dots", "update"), key=lambda k: st[f"t_{k}"])
+    achieved = rates[dom]["gbps"]
+    mv_reorth = (st["bytes_matvec"] + st["bytes_dots"] + st["bytes_update"]) / (
+        st["t_matvec"] + st["t_dots"] + st["t_update"]) / 1e9
+    roof = dict(bound="hbm", kernel=f"reorth_{dom}", achieved=round(achieved, 1),
+                peak=HBM_PEAK_GBPS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBPS, 4),
+                traffic=traffic_for(dom, args.workload),
+                algorithmic_bytes_per_launch=rates[dom]["bytes_per_launch"],
+                avg_launch_us=round(rates[dom]["avg_us"], 2), launches=rates[dom]["launches"],
+                note="HIP events on the solver's stream around every launch of the mixed solve")
+    last = mixed["last"]
+    line = dict(
+        metric=METRIC, value=round(mixed["wall"], 3), unit="s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(mixed["step"] * 1e3, 2), higher_is_better=False,
+        scaling="weak", vs_baseline=None, dtype="fp32+fp64", data="synthetic",
+        config=dict(workload=describe(w), name=args.workload, n=mixed["n"], nev=w["nev"], m=w["m"],
+                    mwin=w["mwin"], parallelism="1 GPU",
+                    step=f"one outer iteration of Alg. 1 (iterations {args.warmup + 1}.."
+                         f"{args.warmup + args.steps} of the mixed solve timed; value: the wall "
+                         f"time of the whole mixed solve to {w['nev']} converged pairs)"),
+        mixed=dict(seconds=mixed["wall"], ms_per_iteration=round(mixed["step"] * 1e3, 2),
+                   cycles=st["cycles"], n_mv=st["n_mv"], gs_passes=st["gs_passes"],
+                   n_resid=st["n_resid"], res_max=float(last.res.max()), kernels=rates),
+        matvec_GBps=dict(mixed=round(rates["matvec"]["gbps"], 1)),
+        matvec_plus_reorth_GBps=dict(mixed=round(mv_reorth, 1),
+                                     frac=round(mv_reorth / HBM_PEAK_GBPS, 4)),
+        roofline=roof,
+    )
+    del last
+    mixed["last"] = None
+    if not args.no_fp64:
+        print(f"[bench] fp64 solve: the first {args.warmup + args.steps} iterations",
+              file=sys.stderr, flush=True)
+        fp64 = run_cycles(J, ctx, w, host, False, args.steps, args.warmup, args.verbose,
+                          full=False)
+        s64 = fp64["stats"]
+        r64 = kernel_rates(s64)
+        line["fp64"] = dict(ms_per_iteration=round(fp64["step"] * 1e3, 2), cycles=s64["cycles"],
+                            n_mv=s64["n_mv"], gs_passes=s64["gs_passes"], kernels=r64,
+                            seconds_for_iterations=round(fp64["wall"], 3))
+        line["matvec_GBps"]["fp64"] = round(r64["matvec"]["gbps"], 1)
+        line["speedup_mixed_vs_fp64"] = round(fp64["step"] / mixed["step"], 3)
+        # the same iterations in both precisions: matvecs up to the last timed one
+        nc = args.warmup + args.steps
+        line["same_iterations_check"] = dict(
+            iterations=nc, mixed_seconds=round(float(mixed["cycle_times"][nc - 1]), 3),
+            fp64_seconds=round(float(fp64["cycle_times"][nc - 1]), 3))
+    if not args.no_cpu:
+        print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, host, st, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
 def kernel_rates(stats):
     out = {}
     for k in ("matvec", "dots", "update"):
@@ -436,9 +547,11 @@ def probe(w, reps=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="stencil16", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 10 outer iterations for the stencils, else 2)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="warm-up steps (default: 2 outer iterations for the stencils, else 1)")
+    ap.add_argument("--workload", default="stencil32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -451,6 +564,13 @@ def main():
               "sharding of this solver is a design, not a build.", file=sys.stderr)
         sys.exit(2)
     w = WORKLOADS[args.workload]
+    cyc = w.get("step") == "cycle"
+    if args.steps is None:
+        args.steps = 10 if cyc else 2
+    if args.warmup is None:
+        args.warmup = 2 if cyc else 1
+    if args.steps < (1 if cyc else 0) or args.warmup < 0:
+        ap.error("--steps must be >= 1 for the stencil workloads (>= 0 otherwise), --warmup >= 0")
     # host inputs first: the Case A recipe runs in worker processes, forked
     # before anything in this process touches the GPU
     host = None if args.probe else make_host_inputs(w)
@@ -469,6 +589,9 @@ def main():
         return
     if w["kind"] == "casea":
         main_casea(args, J, ctx, w, host)
+        return
+    if w.get("step") == "cycle":
+        main_cycles(args, J, ctx, w, host)
         return
     print(f"[bench] {describe(w)}: mixed solves", file=sys.stderr, flush=True)
     mixed = run_precision(J, ctx, w, host, True, args.steps, args.warmup, args.verbose)

@@ -169,6 +169,26 @@ typedef struct {
   int32_t cg_maxit;     /* CG iterations per solve cap (<= 0: 10000)            */
   double cg_tol;        /* CG stops once ||v_j - A u|| <= cg_tol ||v_j|| on the
                            recursively updated residual (<= 0: tol)           */
+  int32_t b0_rule;      /* the norm b0 the first sqrt(2) test of Alg. 2 compares
+                           against: 0 (default) after the local three-term step
+                           u - t_jj v_j - beta_{j-1} v_{j-1}; 1 after
+                           u - t_jj v_j alone, as Alg. 2 prints it (the first
+                           pass then also removes the beta_{j-1} v_{j-1} part,
+                           so about every other step takes a second pass)      */
+  int32_t basis_cycle;  /* > 0: export the Lanczos decomposition of this outer
+                           iteration (1-based), taken after its last Lanczos
+                           step and before its Rayleigh-Ritz step:            */
+  void* basis_out;      /*   device n x (m + 1), leading dimension n, op dtype:
+                           columns 0 .. m_eff of V (m_eff = m unless the
+                           iteration broke down); may be NULL               */
+  double* T_out;        /*   host (m + 1) x m column-major FP64: the projected
+                           matrix Tbar (lower triangle: t_jj, t_{j+1,j} and the
+                           restart row t_{k+1,i}; the rest zero); may be NULL */
+  int32_t cycle_times_cap;  /* entries of cycle_times                        */
+  double* cycle_times;  /* host [cycle_times_cap] or NULL: wall time [s] from the
+                           start of jl_solve to the end of outer iteration c
+                           (its convergence check done, the device idle), at
+                           cycle_times[c - 1]                                */
 } jl_params;
 
 typedef struct {
@@ -206,7 +226,11 @@ jl_status jl_workspace_bytes(jl_op op, const jl_params* p, size_t* bytes);
  * (t_jj alone on the first step after a restart) before the iterated
  * Gram-Schmidt against [V_j, J V_j^*] of Alg. 2; the loop stops when
  * sqrt(2) * (norm after a pass) > (norm before it), the norm before the first
- * pass being the one after the local step.
+ * pass being the one after the local step (params.b0_rule = 0) or the one
+ * after subtracting t_jj v_j alone (b0_rule = 1).  The basis update of the
+ * restart computes only the Ritz vectors the next iteration keeps: first the
+ * nev candidates (rounded up to the GEMM tile), then, once the convergence
+ * check has fixed k = min(icnv + mwin, m - 1), the rest up to k.
  *  v1      device start vector (n, op dtype) or NULL for the all-ones vector
  *          the paper uses; it is normalised internally.
  *  ws      device workspace of ws_bytes >= jl_workspace_bytes.

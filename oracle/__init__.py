@@ -13,7 +13,11 @@ jsym     the J-structure: J, partner vectors, block-form operators (dense and
          4D stencil), dense materialisation, brute-force spectra, and the
          Fourier closed form of the constant-link stencil.
 trlan    Algorithms 1 and 2 of the paper, in plain complex128 NumPy.
-casea    the paper's known-spectrum generator of Sec. 4.1 (Case A).
+cg       conjugate gradients for the invert mode.
+tek      the Case B operator of Sec. 4.2 written from its definition.
+
+The known-spectrum matrices of Sec. 4.1 (Case A) are an input recipe and live
+with the seeded input generators (paper_2001_07428_amd.inputs.known_spectrum).
 
 Every function is pinned by CPU tests against something other than itself
 (brute-force diagonalisation, closed forms, the paper's invariants).

@@ -30,7 +30,7 @@ with 0-based indices: V has columns v_0..v_m, the projected matrix Tbar is
   whose residual sits at the threshold could drop out of the converged set
   and never return.
 * min_passes > 1 takes the sqrt(2) test only from that pass on (default 1,
-  the paper's rule; the FP32-storage GPU solver uses 2).
+  the paper's rule).
 * The J-restriction uses w_i = J v_i^* (Alg. 2 builds W alongside V).  With
   jsym=False the W-projections are dropped, giving the standard TRLAN that the
   paper compares against (Sec. 3).

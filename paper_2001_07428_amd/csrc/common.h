@@ -135,8 +135,10 @@ hipError_t launch_tek_resid(const TekArgs<S>& a, const cplx<S>* X, int64_t ldx, 
 
 // ------------------------------------------------------- reorthogonalisation
 // Basis V: ncol columns of length n = 2h, column stride ldv.
-// dots: partial[blk][4*ncol + 1] = per block (Re, Im of v_i^H u, Re, Im of
-// w_i^H u) for each column, then ||u||^2.
+// dots: partial[blk][dots_stride(ncol)] = per block (Re, Im of v_i^H u, Re,
+// Im of w_i^H u) for each column, then ||u||^2, then (with the local step,
+// else zero) ||u - t v_jl||^2 before the beta term and the rounding.
+__host__ __device__ constexpr int dots_stride(int ncol) { return 4 * ncol + 2; }
 int reorth_dots_blocks(int64_t h, int es);   // partial rows written by dots; es: bytes per complex
 int reorth_update_blocks(int64_t h, int es);   // partial entries written by update (es: bytes per complex)
 constexpr int kReorthMaxCols = 2048;   // largest basis dots supports
@@ -170,12 +172,12 @@ int reorth_update_groups(int64_t h, int es);
 // out[c] = sum_b partial[b * stride + c] for c < ncols (deterministic order).
 hipError_t launch_reduce_cols(const double* partial, int nblk, int stride, int ncols, double* out,
                               hipStream_t st);
-// The same sum for many columns (the reorthogonalisation's 4*ncol + 1 inner
-// products), spread over reduce_wide_tiles(ncols) x reduce_wide_slices(nblk)
+// The same sum for many columns (the reorthogonalisation's dots_stride(ncol)
+// inner products and norms), spread over reduce_wide_tiles(ncols) x reduce_wide_slices(nblk)
 // workgroups.  scr: reduce_wide_scratch_doubles(nblk, ncols) doubles; cnt:
 // reduce_wide_tiles(ncols) counters, zero before the first launch and left
 // zero by every launch (launches that share them must not overlap).
-// last_out (optional) also receives out[ncols - 1].
+// last_out (optional) also receives out[ncols - 2], out[ncols - 1].
 int reduce_wide_slices(int nblk);
 int reduce_wide_tiles(int ncols);
 size_t reduce_wide_scratch_doubles(int nblk, int ncols);
@@ -232,6 +234,9 @@ hipError_t launch_norm2(const cplx<S>* x, int64_t n, double* part, hipStream_t s
 // C (M x N, ldc) = A (M x K, lda) * B (K x N, ldb), real, column-major; A
 // and C of storage type S, B and the MFMA accumulation of type T
 // (instantiated: <float,double>, <double,double>).
+// Column tile of the GEMM (a launch computing N columns covers
+// ceil(N / kGemmTileN) tiles per row panel).
+constexpr int kGemmTileN = 128;
 template <typename S, typename T>
 hipError_t launch_gemm_nn(const S* A, int64_t lda, const T* B, int64_t ldb, S* C, int64_t ldc,
                           int64_t M, int N, int K, hipStream_t st);

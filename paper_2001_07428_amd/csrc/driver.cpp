@@ -284,10 +284,10 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   L.V[0] = take((size_t)n * (m + 1) * es);
   L.V[1] = take((size_t)n * (m + 1) * es);
   L.apart = take(sizeof(double) * 2 * (size_t)op_apply_blocks(op));
-  L.dots_part = take(sizeof(double) * (size_t)reorth_dots_blocks(h, es) * (4 * (size_t)(m + 1) + 1));
+  L.dots_part = take(sizeof(double) * (size_t)reorth_dots_blocks(h, es) * (size_t)dots_stride(m + 1));
   L.upd_part = take(sizeof(double) * (size_t)std::max(reorth_update_blocks(h, es), 1));
   L.coef = take(sizeof(double) * (4 * (size_t)(m + 1) + 1));
-  const int wcols = 4 * (m + 1) + 1;   // the most inner products one pass reduces
+  const int wcols = dots_stride(m + 1);   // the most inner products one pass reduces
   L.wide_scr = take(sizeof(double) * reduce_wide_scratch_doubles(reorth_dots_blocks(h, es), wcols));
   L.wide_cnt = take(sizeof(unsigned) * ((size_t)reduce_wide_tiles(wcols) + 1));   // + update norm
   L.scal = take(sizeof(double) * 64);
@@ -472,7 +472,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   cplx<S>* dscr = gu > 1 ? reinterpret_cast<cplx<S>*>(base + L.rd) : nullptr;
 
   const int ndots = reorth_dots_blocks(h, es);
-  const int wtiles = reduce_wide_tiles(4 * (m + 1) + 1);
+  const int wtiles = reduce_wide_tiles(dots_stride(m + 1));
   unsigned* upd_cnt = wide_cnt + wtiles;
   JL_HIP(ctx, hipMemsetAsync(wide_cnt, 0, sizeof(unsigned) * ((size_t)wtiles + 1), st));
   const int napply = op_apply_blocks(op);
@@ -515,7 +515,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   } else {
     JL_HIP(ctx, hipMemcpyAsync(Vb[cur], v1, (size_t)n * es, hipMemcpyDeviceToDevice, st));
     JL_HIP(ctx, launch_reorth_dots<S>(Vb[cur], ldv, 0, Vb[cur], h, dots_part, ndots, st));
-    JL_HIP(ctx, launch_reduce_cols(dots_part, ndots, 1, 1, scal, st));
+    JL_HIP(ctx, launch_reduce_cols(dots_part, ndots, dots_stride(0), 1, scal, st));
     JL_HIP(ctx, hipMemcpyAsync(hs, scal, sizeof(double), hipMemcpyDeviceToHost, st));
     JL_HIP(ctx, hipStreamSynchronize(st));
     if (!(hs[0] > 0.0) || !std::isfinite(hs[0]))
@@ -610,7 +610,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       cplx<S>* vj = V + (int64_t)j * ldv;
       cplx<S>* u = V + (int64_t)(j + 1) * ldv;
       const int ncol = j + 1;
-      const int stride = 4 * ncol + 1;
+      const int stride = dots_stride(ncol);
       if (invert) {   // u = A^-1 v_j by CG, t_jj = v_j^H u into scal
         const jl_status cs = cg_solve(vj, u);
         if (cs != JL_OK) return cs;
@@ -627,7 +627,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st, scal, beta_prev, j,
                                         uloc, gd));
       tm.stop();
-      // the norm entering the loop (the last reduced column) also to scal[3]
+      // the norms entering the loop (the last two reduced columns: after the
+      // local step, after t_jj v_j alone) also to scal[3], scal[4]
       JL_HIP(ctx, launch_reduce_wide(dots_part, ndots, stride, stride, coef, wide_scr, wide_cnt, st,
                                      scal + 3));
       S_.n_dots_launch++;
@@ -638,7 +639,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       tm.stop();
       S_.n_update_launch++;
       S_.bytes_update += (double)(ncol + 2) * n * es;
-      JL_HIP(ctx, hipMemcpyAsync(hs, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+      JL_HIP(ctx, hipMemcpyAsync(hs, scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
       // speculative: v_{j+1} = u / ||u|| and A v_{j+1}, behind the copy
       const bool spec = !invert && j + 1 < m;
       if (spec) {
@@ -653,7 +654,9 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       const double alpha = hs[0];
       Tat(j, j) = alpha;
       maxT = std::max(maxT, std::fabs(alpha));
-      double b0 = std::sqrt(hs[3]);   // norm entering the Gram-Schmidt loop
+      // norm entering the Gram-Schmidt loop: after the local three-term step,
+      // or (b0_rule 1) after subtracting t_jj v_j alone, as Alg. 2 prints it
+      double b0 = std::sqrt(prm->b0_rule == 1 ? hs[4] : hs[3]);
       double b1 = std::sqrt(hs[2]);
       // u on the device holds (u / usc): usc = b1 after the speculative scaling
       const double usc = spec ? b1 : 1.0;
@@ -713,8 +716,30 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       }
       break;
     }
+    if (prm->basis_cycle == cycle + 1) {   // export the decomposition of this iteration
+      if (prm->basis_out)
+        JL_HIP(ctx, launch_copy_cols<S>(V, ldv, static_cast<cplx<S>*>(prm->basis_out), n, n,
+                                        broke ? meff : meff + 1, st));
+      if (prm->T_out) std::copy(T.begin(), T.end(), prm->T_out);
+    }
     // ================= Rayleigh-Ritz: T_m = Z Lambda Z^T, sort (Alg. 1)
     const int kcols = std::min(kmax, meff);
+    // Ritz vectors [c0, c1) of V_m Z (real GEMM on the interleaved basis)
+    auto basis_gemm = [&](int c0, int c1) -> jl_status {
+      if (c1 <= c0) return JL_OK;
+      tm.start(Timer::GEMM);
+      JL_HIP(ctx, (launch_gemm_nn<S, double>)(reinterpret_cast<const S*>(V), 2 * ldv,
+                                            Zs + (size_t)c0 * meff, meff,
+                                            reinterpret_cast<S*>(Vn + (int64_t)c0 * ldv), 2 * ldv,
+                                            2 * n, c1 - c0, meff, st));
+      tm.stop();
+      S_.n_gemm_launch++;
+      S_.flops_gemm += 2.0 * (double)(2 * n) * (c1 - c0) * meff;
+      return JL_OK;
+    };
+    // the nev candidates of the convergence check first (rounded up to the
+    // GEMM's column tile); the rest of the kept vectors once icnv is known
+    const int kfirst = std::min(kcols, (nev + kGemmTileN - 1) / kGemmTileN * kGemmTileN);
     tm.start(Timer::RITZ);
     if (meff <= dc_max_m()) {
       // restart structure: kept Ritz values and couplings, then this cycle's
@@ -743,13 +768,11 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     JL_HIP(ctx, hipMemcpyAsync(h_lam, lam_s, sizeof(double) * meff, hipMemcpyDeviceToHost, st));
     JL_HIP(ctx, hipMemcpyAsync(h_zl, zlast, sizeof(double) * meff, hipMemcpyDeviceToHost, st));
     tm.stop();
-    // ================= V_k := V_m Z[:, 0:kcols] (real GEMM on the interleaved basis)
-    tm.start(Timer::GEMM);
-    JL_HIP(ctx, (launch_gemm_nn<S, double>)(reinterpret_cast<const S*>(V), 2 * ldv, Zs, meff,
-                                          reinterpret_cast<S*>(Vn), 2 * ldv, 2 * n, kcols, meff, st));
-    tm.stop();
-    S_.n_gemm_launch++;
-    S_.flops_gemm += 2.0 * (double)(2 * n) * kcols * meff;
+    // ================= V_k := V_m Z[:, 0:k] (Alg. 1), candidates first
+    {
+      const jl_status gs = basis_gemm(0, kfirst);
+      if (gs != JL_OK) return gs;
+    }
     JL_HIP(ctx, hipStreamSynchronize(st));
     tm.resolve();
     const double beta_m = Tat(meff, meff - 1);
@@ -765,13 +788,13 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
         tm.start(Timer::RESID);
         JL_HIP(ctx, op_apply<S>(op, V + (int64_t)meff * ldv, cgv[2], ldv, 1, nullptr, st));
         JL_HIP(ctx, launch_norm2<S>(cgv[2], n, cg_part, st));
-        JL_HIP(ctx, launch_reduce_cols(cg_part, ncgb, 1, 1, scal + 4, st));
-        JL_HIP(ctx, hipMemcpyAsync(hs + 4, scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+        JL_HIP(ctx, launch_reduce_cols(cg_part, ncgb, 1, 1, scal + 5, st));
+        JL_HIP(ctx, hipMemcpyAsync(hs + 5, scal + 5, sizeof(double), hipMemcpyDeviceToHost, st));
         tm.stop();
         JL_HIP(ctx, hipStreamSynchronize(st));
         tm.resolve();
         S_.n_resid++;
-        c = std::sqrt(hs[4]);
+        c = std::sqrt(hs[5]);
       }
       tol_scale = std::max(tol_scale, c);
       for (int i = 0; i < meff; ++i) {
@@ -830,6 +853,9 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
               std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count());
       fflush(stderr);
     }
+    if (prm->cycle_times && cycle < prm->cycle_times_cap)   // the device is idle here
+      prm->cycle_times[cycle] =
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count();
     const bool last = (cycle + 1 == max_cycles);
     if (icnv == nev || broke || last) {
       status = icnv == nev ? JL_OK : (broke ? JL_BREAKDOWN : JL_NOT_CONVERGED);
@@ -838,6 +864,10 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     }
     // ================= shrink to k + 1 (eq. dynamicwin) and continue
     k = std::min(icnv + mwin, m - 1);
+    {
+      const jl_status gs = basis_gemm(kfirst, k);   // the kept vectors past the candidates
+      if (gs != JL_OK) return gs;
+    }
     std::fill(T.begin(), T.end(), 0.0);
     maxT = 0.0;
     for (int i = 0; i < k; ++i) {

@@ -31,7 +31,7 @@ template <> struct Mfma<double> {
   }
 };
 
-constexpr int BM = 128, BN = 128, PAD = 16, LDT = BM + PAD;
+constexpr int BM = 128, BN = kGemmTileN, PAD = 16, LDT = BM + PAD;
 constexpr int kThreads = 256;
 
 // S: storage type of A and C; T: MFMA (accumulation) type, also the type of B.

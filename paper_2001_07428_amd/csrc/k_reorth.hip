@@ -8,7 +8,8 @@
 // element p of the top half with element p of the bottom half.
 //
 // dots:   per block, FP64 partial sums of v_i^H u and w_i^H u for every
-//         column, plus ||u||^2; one wavefront per column (FP32: per two
+//         column, plus ||u||^2 (and, with the local three-term step, the
+//         squared norm after its first term alone); one wavefront per column (FP32: per two
 //         columns) at a time, u held in registers (converted to FP64), FP64
 //         products and accumulation; the partials are summed by
 //         k_reduce_wide (tiles of columns x slices of blocks).
@@ -155,10 +156,13 @@ __device__ __forceinline__ void col_dots(const cplx<S>* __restrict__ vt, int64_t
 
 // grid.x = blocks, each covering `chunks` consecutive chunks of
 // 64*E*kPairsPerLane pairs.  Column c is owned by wavefront c % 4 of every
-// block.  partial row stride = 4*ncol + 1.
+// block.  partial row stride = dots_stride(ncol) = 4*ncol + 2: the column
+// sums, ||u||^2, and a last slot (zero without LOCAL).
 // LOCAL: before the inner products apply the local three-term step
 // u <- u - t v_jl - beta v_{jl-1} (t read from the device), rounded once to
-// S and stored back by wavefront 0 after every wavefront has read the chunk.
+// S and stored back by wavefront 0 after every wavefront has read the chunk;
+// the last slot receives ||u - t v_jl||^2 (FP64, before the rounding): the
+// norm Alg. 2 measures after subtracting t_jj v_j alone.
 // Column groups (gridDim.y > 1, for vectors too short to fill the device):
 // block (x, g) takes the columns c with (c / 4) % G == g, every group
 // applies the local step in registers, and only group 0 stores it, to uout
@@ -174,11 +178,12 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
                                                          cplx<S>* __restrict__ uout) {
   constexpr int Q = kPairsPerLane / E;     // loads per half per lane per chunk
   constexpr int CH = 64 * E * Q;           // pairs per chunk
-  extern __shared__ double acc[];          // 4*ncol + 1 column accumulators
+  extern __shared__ double acc[];          // dots_stride(ncol) column accumulators
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  for (int i = threadIdx.x; i < 4 * ncol + 1; i += kReorthThreads) acc[i] = 0.0;
+  const int nout = dots_stride(ncol);
+  for (int i = threadIdx.x; i < nout; i += kReorthThreads) acc[i] = 0.0;
   __syncthreads();
-  double unorm = 0.0;
+  double unorm = 0.0, anorm = 0.0;
   for (int ch = 0; ch < chunks; ++ch) {
     const int64_t p0 = ((int64_t)blockIdx.x * chunks + ch) * CH;
     if (p0 >= h) break;
@@ -224,11 +229,17 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          // u - t v_j - beta v_{j-1}, rounded once to the storage type
-          utr[q][e] = (double)(S)(utr[q][e] - (t_re * tr[e] - t_im * ti[e]) - beta * mtr[e]);
-          uti[q][e] = (double)(S)(uti[q][e] - (t_re * ti[e] + t_im * tr[e]) - beta * mti[e]);
-          ubr[q][e] = (double)(S)(ubr[q][e] - (t_re * br[e] - t_im * bi[e]) - beta * mbr[e]);
-          ubi[q][e] = (double)(S)(ubi[q][e] - (t_re * bi[e] + t_im * br[e]) - beta * mbi[e]);
+          // u - t v_j (its norm: the alpha step alone), then - beta v_{j-1},
+          // rounded once to the storage type
+          const double atr = utr[q][e] - (t_re * tr[e] - t_im * ti[e]);
+          const double ati = uti[q][e] - (t_re * ti[e] + t_im * tr[e]);
+          const double abr = ubr[q][e] - (t_re * br[e] - t_im * bi[e]);
+          const double abi = ubi[q][e] - (t_re * bi[e] + t_im * br[e]);
+          anorm += atr * atr + ati * ati + abr * abr + abi * abi;
+          utr[q][e] = (double)(S)(atr - beta * mtr[e]);
+          uti[q][e] = (double)(S)(ati - beta * mti[e]);
+          ubr[q][e] = (double)(S)(abr - beta * mbr[e]);
+          ubi[q][e] = (double)(S)(abi - beta * mbi[e]);
         }
         if (wave == 0 && blockIdx.y == 0) {
 #pragma unroll
@@ -283,14 +294,18 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
   }
   if (wave == 0 && blockIdx.y == 0) {
     unorm = wave_sum(unorm);
-    if (lane == 0) acc[4 * ncol] = unorm;
+    if (LOCAL) anorm = wave_sum(anorm);
+    if (lane == 0) {
+      acc[4 * ncol] = unorm;
+      acc[4 * ncol + 1] = LOCAL ? anorm : 0.0;
+    }
   }
   __syncthreads();
-  // this group's columns (and, for group 0, the norm) of the block's row
-  double* out = partial + (int64_t)blockIdx.x * (4 * ncol + 1);
+  // this group's columns (and, for group 0, the norms) of the block's row
+  double* out = partial + (int64_t)blockIdx.x * nout;
   const int G = gridDim.y, g = blockIdx.y;
-  for (int i = threadIdx.x; i < 4 * ncol + 1; i += kReorthThreads)
-    if (i == 4 * ncol ? g == 0 : ((i / 16) % G == g)) out[i] = acc[i];
+  for (int i = threadIdx.x; i < nout; i += kReorthThreads)
+    if (i >= 4 * ncol ? g == 0 : ((i / 16) % G == g)) out[i] = acc[i];
 }
 
 // Stores this block's share of ||u||^2 (bsum, the same in every thread).
@@ -524,7 +539,8 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ 
 // columns (four wavefronts over interleaved rows, combined in LDS) into
 // scr[r * ncols + c]; the last slice of a tile to finish, found with the
 // per-tile counter cnt[t], sums the R slice values in order r = 0 .. R-1 and
-// resets the counter; last_out, if given, also receives out[ncols - 1].
+// resets the counter; last_out, if given, also receives out[ncols - 2] and
+// out[ncols - 1] (at last_out[0], last_out[1]; ncols >= 2).
 // The slice sums are agent-scope stores, complete before
 // the counter moves, and are read back with agent-scope loads (the per-XCD
 // L2s are not coherent with each other).  Deterministic for a given nblk.
@@ -555,7 +571,7 @@ __global__ __launch_bounds__(256) void k_reduce_wide(const double* __restrict__ 
   const double t = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
   if (R == 1) {
     if (c < ncols) out[c] = t;
-    if (last_out && c == ncols - 1) *last_out = t;
+    if (last_out && c >= ncols - 2 && c < ncols) last_out[c - (ncols - 2)] = t;
     return;
   }
   if (c < ncols)
@@ -571,7 +587,7 @@ __global__ __launch_bounds__(256) void k_reduce_wide(const double* __restrict__ 
       v += __hip_atomic_load(&scr[(int64_t)rr * ncols + c], __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     out[c] = v;
-    if (last_out && c == ncols - 1) *last_out = v;
+    if (last_out && c >= ncols - 2) last_out[c - (ncols - 2)] = v;
   }
   if (lane == 0) cnt[blockIdx.x] = 0u;   // ready for the next launch
 }
@@ -686,7 +702,7 @@ hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* 
   const unsigned grid = (unsigned)((nch + per - 1) / per);
   if ((int)grid != nblk) return hipErrorInvalidValue;
   const dim3 g2(grid, (unsigned)groups);
-  const size_t lds = sizeof(double) * (4 * (size_t)ncol + 1);
+  const size_t lds = sizeof(double) * (size_t)dots_stride(ncol);
   const bool e2 = sizeof(S) == 4 && h % 2 == 0;
   // FP32 only: the FP64 inner products measured slower with non-temporal
   // loads (16^4: 362 -> 388 us), the FP64 update faster (349 -> 323 us)
@@ -810,7 +826,7 @@ size_t reduce_wide_scratch_doubles(int nblk, int ncols) {
 
 hipError_t launch_reduce_wide(const double* partial, int nblk, int stride, int ncols, double* out,
                               double* scr, unsigned* cnt, hipStream_t st, double* last_out) {
-  if (ncols <= 0 || nblk <= 0) return hipErrorInvalidValue;
+  if (ncols <= 0 || nblk <= 0 || (last_out && ncols < 2)) return hipErrorInvalidValue;
   const int R = reduce_wide_slices(nblk);
   if (R > 1 && (!scr || !cnt)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce_wide, dim3((unsigned)reduce_wide_tiles(ncols), (unsigned)R), dim3(256),

@@ -16,7 +16,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // dots partials | update partials | wide-reduction slices | its tile counters
 size_t reorth_ws_part(int64_t n, int ncol, int which) {
   const int64_t h = n / 2;
-  const int nd = std::max(reorth_dots_blocks(h, 8), reorth_dots_blocks(h, 16)), stride = 4 * ncol + 1;
+  const int nd = std::max(reorth_dots_blocks(h, 8), reorth_dots_blocks(h, 16)), stride = dots_stride(ncol);
   const size_t sz[4] = {
       align_up(sizeof(double) * (size_t)nd * (size_t)stride),
       align_up(sizeof(double) *
@@ -39,7 +39,7 @@ hipError_t reorth_pass(int64_t n, int ncol, const cplx<S>* V, int64_t ldv, cplx<
   double* up = reinterpret_cast<double*>(ws + reorth_ws_part(n, ncol, 1));
   double* scr = reinterpret_cast<double*>(ws + reorth_ws_part(n, ncol, 2));
   unsigned* cnt = reinterpret_cast<unsigned*>(ws + reorth_ws_part(n, ncol, 3));
-  const int stride = 4 * ncol + 1;
+  const int stride = dots_stride(ncol);   // coef[4 ncol + 1] is then overwritten by the norm after
   hipError_t e;
   if ((e = hipMemsetAsync(cnt, 0, sizeof(unsigned) * (size_t)reduce_wide_tiles(stride), st)) !=
       hipSuccess)

@@ -48,7 +48,9 @@ class JlParams(ctypes.Structure):
         ("trace_cap", ctypes.c_int32),
         ("trace_ab", ctypes.POINTER(ctypes.c_double)), ("verbose", ctypes.c_int32),
         ("standard", ctypes.c_int32), ("invert", ctypes.c_int32), ("cg_maxit", ctypes.c_int32),
-        ("cg_tol", ctypes.c_double),
+        ("cg_tol", ctypes.c_double), ("b0_rule", ctypes.c_int32), ("basis_cycle", ctypes.c_int32),
+        ("basis_out", ctypes.c_void_p), ("T_out", ctypes.POINTER(ctypes.c_double)),
+        ("cycle_times_cap", ctypes.c_int32), ("cycle_times", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -278,12 +280,16 @@ class SolveResult:
     stats: dict
     trace_alpha: np.ndarray | None = None
     trace_beta: np.ndarray | None = None
+    basis: object = None              # torch tensor (m_eff + 1, n) of the exported iteration
+    T: np.ndarray | None = None       # its projected matrix Tbar ((m + 1) x m, lower triangle)
+    cycle_times: np.ndarray | None = None   # wall time [s] at the end of each outer iteration
 
 
 def _params(nev, m, mwin, tol, which, max_cycles, max_passes, timing, trace_buf, min_passes=0,
             tol_relative=False, verbose=False, standard=False, invert=False, cg_tol=0.0,
-            cg_maxit=0):
+            cg_maxit=0, b0_rule=0):
     p = JlParams()
+    p.b0_rule = int(b0_rule)
     p.standard = int(bool(standard))
     p.invert = int(bool(invert))
     p.cg_tol = float(cg_tol)
@@ -318,16 +324,31 @@ def jl_workspace_bytes(op: Operator, nev, m, mwin, tol=1e-10, which="lowest", st
 def jl_solve(op: Operator, nev, m, mwin, tol, which="lowest", v1=None, max_cycles=0,
              max_passes=0, min_passes=0, timing=False, trace_cap=0, workspace=None,
              tol_relative=False, verbose=False, standard=False, invert=False, cg_tol=0.0,
-             cg_maxit=0) -> SolveResult:
+             cg_maxit=0, b0_rule=0, basis_cycle=0, cycle_times_cap=0) -> SolveResult:
     """Thick-restart J-Lanczos for the nev lowest (or largest) pairs
     (standard=True: the standard thick-restart Lanczos without the
     J-restriction, which finds every pair twice; invert=True: the Lanczos
-    steps take A^-1 v_j by conjugate gradients, for positive definite A)."""
+    steps take A^-1 v_j by conjugate gradients, for positive definite A).
+    b0_rule=1 takes the first sqrt(2) test against the norm after t_jj v_j
+    alone (Alg. 2 as printed); basis_cycle=c > 0 returns the Lanczos basis
+    and Tbar of outer iteration c in .basis / .T; cycle_times_cap=C returns
+    the wall time at the end of each of the first C outer iterations."""
     torch = _torch()
     lib = load_library()
     trace_buf = np.zeros(2 * trace_cap) if trace_cap else None
     p = _params(nev, m, mwin, tol, which, max_cycles, max_passes, timing, trace_buf, min_passes,
-                tol_relative, verbose, standard, invert, cg_tol, cg_maxit)
+                tol_relative, verbose, standard, invert, cg_tol, cg_maxit, b0_rule)
+    basis = T_out = ctimes = None
+    if basis_cycle > 0:
+        basis = torch.zeros((m + 1, op.n), dtype=op.dtype, device=op.ctx.device)
+        T_out = np.zeros((m, m + 1))   # row j = column j of the column-major (m + 1) x m Tbar
+        p.basis_cycle = int(basis_cycle)
+        p.basis_out = ctypes.c_void_p(basis.data_ptr())
+        p.T_out = T_out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if cycle_times_cap > 0:
+        ctimes = np.full(cycle_times_cap, np.nan)
+        p.cycle_times_cap = int(cycle_times_cap)
+        p.cycle_times = ctimes.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     nb = ctypes.c_size_t()
     _check(lib.jl_workspace_bytes(op.handle, ctypes.byref(p), ctypes.byref(nb)), op.ctx.handle)
     if workspace is None or workspace.numel() < nb.value:
@@ -348,6 +369,10 @@ def jl_solve(op: Operator, nev, m, mwin, tol, which="lowest", v1=None, max_cycle
                           res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st))
     _check(status, op.ctx.handle)
     out = SolveResult(status, evals, X, res, st.to_dict())
+    if basis is not None:
+        out.basis, out.T = basis, T_out.T.copy()
+    if ctimes is not None:
+        out.cycle_times = ctimes[:min(cycle_times_cap, out.stats["cycles"])]
     if trace_buf is not None:
         out.trace_alpha = trace_buf[:trace_cap].copy()
         out.trace_beta = trace_buf[trace_cap:].copy()

@@ -22,6 +22,16 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert "one GPU" in r.stderr
 
 
+def test_cycle_step_time():
+    ct = [1.0, 3.0, 6.0, 10.0, 15.0]        # end of iterations 1..5
+    assert bench.cycle_step_time(ct, 0, 2) == pytest.approx(1.5)    # iterations 1, 2
+    assert bench.cycle_step_time(ct, 2, 3) == pytest.approx(4.0)    # iterations 3, 4, 5
+    with pytest.raises(RuntimeError):
+        bench.cycle_step_time(ct, 3, 3)      # the solve ended before the last timed iteration
+    with pytest.raises(RuntimeError):
+        bench.cycle_step_time(ct, 0, 0)
+
+
 def test_kernel_rates_arithmetic():
     stats = dict(t_matvec=2.0, n_matvec_launch=4, bytes_matvec=8e9,
                  t_dots=1.0, n_dots_launch=2, bytes_dots=5e9,

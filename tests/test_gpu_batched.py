@@ -23,10 +23,15 @@ def _check_problem(A11, A12, ev, X, res, tol_res, gate, nev):
     ref, _ = jsym.brute(A)
     assert np.abs(ev - ref[:nev]).max() < gate * np.abs(ref).max()
     Xc = X.astype(np.complex128)
+    # the kernel's residual is an FP64-accumulated apply of the stored
+    # operator: it differs from the FP64 operator's by at most
+    # ||A - fl(A)||_2 <= ||A - fl(A)||_F (x is the stored vector itself)
+    As = jsym.dense_from_blocks(A11.astype(X.dtype), A12.astype(X.dtype)).astype(np.complex128)
+    dres = np.linalg.norm(A - As) + 1e-13 * np.linalg.norm(A)
     for i in range(nev):
         r = np.linalg.norm(A @ Xc[i] - ev[i] * Xc[i])
-        assert r < tol_res
-        assert abs(r - res[i]) < 1e-3 * tol_res + 1e-6 * r or r < tol_res
+        assert r < tol_res + dres
+        assert abs(r - res[i]) <= dres
     UU = np.concatenate([Xc.T, jsym.partner(Xc.T)], axis=1)
     assert np.abs(UU.conj().T @ UU - np.eye(2 * nev)).max() < (1e-5 if X.dtype == np.complex64 else 1e-12)
 
@@ -108,8 +113,11 @@ def test_batched_512_full_size(ctx):
         X = to_np(b.X[i]).astype(np.complex128)
         A = jsym.dense_from_blocks(A11, A12)
         anorm = np.abs(ev[i]).max()
-        R = A @ X.T - X.T * ev[i][None, :]
-        assert np.linalg.norm(R, axis=0).max() < 1e-5 * 1.3 * max(anorm, 1.0) + 1e-4
+        r = np.linalg.norm(A @ X.T - X.T * ev[i][None, :], axis=0)
+        As = jsym.dense_from_blocks(A11.astype(np.complex64), A12.astype(np.complex64))
+        dres = np.linalg.norm(A - As.astype(np.complex128)) + 1e-13 * np.linalg.norm(A)
+        assert (r < 1e-5 * 1.3 * max(anorm, 1.0) + dres).all()   # tol relative to max|theta|
+        assert np.abs(r - res[i]).max() <= dres
         if i % 16 == 0:
             ref, _ = jsym.brute(A)
             assert np.abs(ev[i] - ref[:8]).max() < 1e-5 * np.abs(ref).max()

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2001_07428_amd import inputs
-from oracle import casea, cg, jsym, trlan
+from oracle import cg, jsym, trlan
 
 from gpu_util import cdt, say, to_dev, to_np
 
@@ -42,7 +42,7 @@ def test_invert_dense_casea_fp64(ctx):
     mwin=20, tol 1e-11 (absolute), FP64."""
     from paper_2001_07428_amd import jlanczos as J
     say("invert dense casea n400 fp64")
-    A11, A12, lam, _ = casea.known_spectrum(8, 400)
+    A11, A12, lam, _ = inputs.known_spectrum(8, 400)
     A = jsym.dense_from_blocks(A11, A12)
     f = lambda v: A @ v
     ref = trlan.trlan_jsym(f, 400, 10, 20, 50, 1e-11, mode="invert", solve=_cg_solve(f))
@@ -98,7 +98,7 @@ def test_invert_stencil_mixed(ctx):
 def test_invert_standard_mode_finds_pairs_twice(ctx):
     from paper_2001_07428_amd import jlanczos as J
     say("invert standard dense casea n200")
-    A11, A12, lam, _ = casea.known_spectrum(21, 200)
+    A11, A12, lam, _ = inputs.known_spectrum(21, 200)
     A = jsym.dense_from_blocks(A11, A12)
     op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(False)), to_dev(A12, cdt(False)))
     out = J.jl_solve(op, 8, 40, 16, 1e-11, invert=True, standard=True, cg_tol=1e-14)
@@ -110,7 +110,7 @@ def test_invert_rejects_negative_definite(ctx):
     """p^H A p < 0 at the first CG step: an error, every kernel exits."""
     from paper_2001_07428_amd import jlanczos as J
     say("invert negative definite")
-    A11, A12, _, _ = casea.known_spectrum(22, 100, -np.linspace(0.5, 1.0, 50))
+    A11, A12, _, _ = inputs.known_spectrum(22, 100, -np.linspace(0.5, 1.0, 50))
     op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(False)), to_dev(A12, cdt(False)))
     with pytest.raises(J.JLError, match="positive definite"):
         J.jl_solve(op, 2, 10, 4, 1e-10, invert=True)
@@ -119,7 +119,7 @@ def test_invert_rejects_negative_definite(ctx):
 def test_invert_cg_cap_is_reported(ctx):
     from paper_2001_07428_amd import jlanczos as J
     say("invert cg cap")
-    A11, A12, _, _ = casea.known_spectrum(23, 200, np.linspace(1e-3, 1.0, 100))
+    A11, A12, _, _ = inputs.known_spectrum(23, 200, np.linspace(1e-3, 1.0, 100))
     op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(False)), to_dev(A12, cdt(False)))
     out = J.jl_solve(op, 4, 20, 8, 1e-12, invert=True, cg_maxit=3, max_cycles=2)
     assert out.stats["cg_max_iters"] == 3

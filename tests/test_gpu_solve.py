@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from paper_2001_07428_amd import inputs
-from oracle import casea, jsym, trlan
+from oracle import jsym, trlan
 
 from gpu_util import cdt, say, to_dev, to_np
 
@@ -55,6 +55,62 @@ def test_dense_n200_fp64_vs_oracle(ctx):
     _check_pairs(lambda v: A @ v, X, out.evals, 1e-10, 1e-12)
     bf, _ = jsym.brute(A)
     assert _releig(out.evals, bf[:10]) < 1e-10
+    # the returned residuals are the FP64 norms ||A x_i - lambda_i x_i||
+    r = np.linalg.norm(A @ X.T - X.T * out.evals[None, :], axis=0)
+    assert np.abs(r - out.res).max() < 1e-13 * np.linalg.norm(A, 2)
+
+
+def test_b0_rule_as_printed_matches_oracle(ctx):
+    """With b0_rule = 1 the first sqrt(2) test of Alg. 2 compares against the
+    norm after t_jj v_j alone, as the oracle (and the paper) does: the GPU then
+    takes the same reorthogonalisation decisions as the oracle's literal
+    Alg. 2 on the same v_1 (n = 200, FP64; a decision can only differ where
+    sqrt(2) b1 and b0 agree to rounding), and the same cycles and matvecs."""
+    from paper_2001_07428_amd import jlanczos as J
+    say("b0 rule as printed")
+    A11, A12 = inputs.dense_jsym(1, 100)
+    A = jsym.dense_from_blocks(A11, A12)
+    ref = trlan.trlan_jsym(lambda v: A @ v, 200, 10, 20, 40, 1e-10)
+    op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(False)), to_dev(A12, cdt(False)))
+    out = J.jl_solve(op, 10, 40, 20, 1e-10, b0_rule=1)
+    base = J.jl_solve(op, 10, 40, 20, 1e-10)
+    print(f"  passes: GPU as printed {out.stats['gs_passes']}, oracle {ref['gs_passes']}, "
+          f"GPU after the local step {base.stats['gs_passes']} (matvecs {out.stats['n_mv']})",
+          flush=True)
+    assert out.status == J.JL_OK
+    assert out.stats["cycles"] == ref["n_conv"] and out.stats["n_mv"] == ref["n_mv"]
+    assert abs(out.stats["gs_passes"] - ref["gs_passes"]) <= 2
+    assert base.stats["gs_passes"] < out.stats["gs_passes"]
+    assert _releig(out.evals, ref["ev"]) < 1e-10
+
+
+def test_not_converged_contract(ctx):
+    """max_cycles reached before all pairs converge: JL_NOT_CONVERGED, and the
+    first stats.icnv returned pairs are converged (true residual below tol,
+    eigenvalues of A), the others carry residuals >= tol (or inf when their
+    estimate never asked for a check)."""
+    from paper_2001_07428_amd import jlanczos as J
+    L = (4, 4, 4, 4)
+    say("not converged", L)
+    U, B = inputs.stencil_links(4, L)
+    n = 2 * 256 * 4
+    f = lambda v: jsym.stencil_apply(U, B, L, v)
+    hist = trlan.trlan_jsym(f, n, 8, 16, 48, 1e-10, record_history=True)["history"]
+    partial = [i for i, h in enumerate(hist) if 0 < h["icnv"] < 8]
+    cut = partial[len(partial) // 2] + 1   # an iteration in the middle of the partial ones
+    op = J.jl_op_create_stencil(ctx, L, to_dev(U, cdt(False)), to_dev(B, cdt(False)))
+    out = J.jl_solve(op, 8, 48, 16, 1e-10, max_cycles=cut)
+    icnv = out.stats["icnv"]
+    print(f"  cut after {cut} cycles: icnv {icnv} (oracle {hist[cut - 1]['icnv']})", flush=True)
+    assert out.status == J.JL_NOT_CONVERGED and out.stats["status"] == J.JL_NOT_CONVERGED
+    assert out.stats["cycles"] == cut and 0 < icnv < 8
+    bf, _ = jsym.brute(jsym.stencil_dense(U, B, L))
+    X = to_np(out.X)
+    for i in range(icnv):
+        r = np.linalg.norm(f(X[i]) - out.evals[i] * X[i])
+        assert r < 1e-10 and abs(r - out.res[i]) < 1e-13
+        assert np.abs(bf - out.evals[i]).min() < 1e-10
+    assert (out.res[icnv:] >= 1e-10).all()
 
 
 @pytest.mark.parametrize("mixed", [False, True])
@@ -171,7 +227,7 @@ def test_casea_largest(ctx):
     """Known spectrum (Case A recipe), largest end."""
     from paper_2001_07428_amd import jlanczos as J
     say("casea largest")
-    A11, A12, lam, _ = casea.known_spectrum(8, 400)
+    A11, A12, lam, _ = inputs.known_spectrum(8, 400)
     op = J.jl_op_create_dense(ctx, to_dev(A11, cdt(False)), to_dev(A12, cdt(False)))
     out = J.jl_solve(op, 10, 50, 20, 1e-12, which="largest")
     assert out.status == J.JL_OK

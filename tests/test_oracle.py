@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2001_07428_amd import inputs
-from oracle import casea, jsym, trlan
+from oracle import jsym, trlan
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -91,7 +91,7 @@ def test_exact_double_degeneracy(case):
         U, B = inputs.stencil_links(4, 3)
         A = jsym.stencil_dense(U, B, 3)
     else:
-        A11, A12, _, _ = casea.known_spectrum(8, 200)
+        A11, A12, _, _ = inputs.known_spectrum(8, 200)
         A = jsym.dense_from_blocks(A11, A12)
     _, gap = jsym.brute(A)
     assert gap < 1e-12 * np.linalg.norm(A, 2)
@@ -101,7 +101,7 @@ def test_known_spectrum_generator():
     """Case A recipe: A = [X, JX*] diag(L, L) [X, JX*]^H with the constraints
     X1^H X1 + X2^H X2 = I and X1^T X2 - X2^T X1 = 0 (eq. diagblockform)."""
     n = 160
-    A11, A12, lam, Q = casea.known_spectrum(8, n)
+    A11, A12, lam, Q = inputs.known_spectrum(8, n)
     h = n // 2
     X1, X2 = Q[:h], Q[h:]
     assert np.abs(X1.conj().T @ X1 + X2.conj().T @ X2 - np.eye(h)).max() < 1e-13
@@ -109,6 +109,25 @@ def test_known_spectrum_generator():
     A = jsym.dense_from_blocks(A11, A12)
     assert np.abs(np.linalg.eigvalsh(A) - np.sort(np.concatenate([lam, lam]))).max() < 1e-13
     assert np.abs(A11 - A11.conj().T).max() < 1e-15 and np.abs(A12 + A12.T).max() == 0.0
+
+
+@pytest.mark.parametrize("which", ["lowest", "largest"])
+def test_pair_eigenvalues_known_spectrum(which):
+    """brute() on a Case A matrix returns the planted Lambda, once per pair,
+    ascending for the lowest end and descending for the largest end; the
+    in-pair gap is at rounding level.  A spectrum with one planted value
+    repeated in two pairs keeps both copies."""
+    A11, A12, lam, _ = inputs.known_spectrum(8, 200)
+    pairs, gap = jsym.brute(jsym.dense_from_blocks(A11, A12), which)
+    want = lam if which == "lowest" else lam[::-1]
+    assert np.abs(pairs - want).max() < 1e-13
+    assert gap < 1e-13
+    lam2 = np.linspace(0.1, 0.9, 50)
+    lam2[7] = lam2[8]   # two distinct pairs with one eigenvalue (multiplicity 4)
+    A11, A12, l2, _ = inputs.known_spectrum(9, 100, lam=lam2)
+    pairs, _ = jsym.brute(jsym.dense_from_blocks(A11, A12), which)
+    want = np.sort(lam2) if which == "lowest" else np.sort(lam2)[::-1]
+    assert np.abs(pairs - want).max() < 1e-13
 
 
 # ---------------------------------------------------------------- TRLAN-JSYM
@@ -138,7 +157,7 @@ def test_trlan_dense_c1_vs_brute():
 
 
 def test_trlan_casea_largest_known_spectrum():
-    A11, A12, lam, _ = casea.known_spectrum(8, 400)
+    A11, A12, lam, _ = inputs.known_spectrum(8, 400)
     A = jsym.dense_from_blocks(A11, A12)
     out = trlan.trlan_jsym(lambda v: A @ v, 400, 10, 20, 50, 1e-12, which="largest")
     assert out["status"] == "ok"
@@ -300,7 +319,7 @@ def test_table1_caseA_counts_in_published_range():
     rows = json.load(open(os.path.join(GOLDEN, "table1_caseA.json")))["rows"]
     row = [r for r in rows if r[0] == "TRLAN-JSYM" and r[1:4] == [10, 20, 50]][0]
     for seed in (11,):
-        A11, A12, lam, _ = casea.known_spectrum(seed, 2000)
+        A11, A12, lam, _ = inputs.known_spectrum(seed, 2000)
         A = jsym.dense_from_blocks(A11, A12)
         out = trlan.trlan_jsym(lambda v: A @ v, 2000, 10, 20, 50, 1e-13, which="largest")
         assert out["status"] == "ok"
@@ -315,7 +334,7 @@ def test_standard_trlan_can_miss_partners():
     direction per eigenspace for a single start vector, up to rounding), and
     returns ten distinct eigenvalues; the J-restricted method returns the five
     largest pairs once each, which is what it is built to do (Sec. 3)."""
-    A11, A12, lam, _ = casea.known_spectrum(12, 2000)
+    A11, A12, lam, _ = inputs.known_spectrum(12, 2000)
     A = jsym.dense_from_blocks(A11, A12)
     std = trlan.trlan_jsym(lambda v: A @ v, 2000, 10, 20, 200, 1e-13, which="largest", jsym=False)
     top = lam[::-1]

@@ -6,11 +6,11 @@ import numpy as np
 import pytest
 
 from paper_2001_07428_amd import inputs
-from oracle import casea, cg, jsym, trlan
+from oracle import cg, jsym, trlan
 
 
 def _casea(seed, n, lam=None):
-    A11, A12, lam, _ = casea.known_spectrum(seed, n, lam)
+    A11, A12, lam, _ = inputs.known_spectrum(seed, n, lam)
     return jsym.dense_from_blocks(A11, A12), lam
 
 
