@@ -33,9 +33,16 @@
  *  - All GPU work is ordered after the context's stream.  Calls that return
  *    host results (jl_solve) wait for their own work before returning.
  *  - The solver's scratch space is the caller's workspace (size from
- *    jl_workspace_bytes).  The only device memory the library allocates is
- *    the stencil operator's copy of its links (jl_op_create_stencil); a
- *    batch also holds pinned host memory for its results (jl_batch_create).
+ *    jl_workspace_bytes).  Device memory the library itself holds:
+ *      . the stencil operator's site-fastest copy of its links, 64 V complex
+ *        elements (twice that with per-site B), jl_op_create_stencil until
+ *        jl_op_destroy;
+ *      . the Case B operator's padded links, product matrices, projection
+ *        tables and product jobs, about 56 Np^2 complex elements
+ *        (Np = N rounded up to 64), jl_op_create_tek until jl_op_destroy;
+ *      . HIP events, streams and the batch's captured graph.
+ *    Pinned host memory: a few scalars per jl_solve call, and a batch's
+ *    results (jl_batch_create until jl_batch_destroy).
  */
 #ifndef JLANCZOS_H
 #define JLANCZOS_H
@@ -147,7 +154,12 @@ typedef struct {
   int32_t max_cycles;   /* outer-iteration cap (<= 0: 10000)                   */
   int32_t max_passes;   /* reorthogonalisation passes per step cap (<= 0: 16)  */
   int32_t min_passes;   /* passes before the sqrt(2) test applies (<= 0: 1)    */
-  int32_t timing;       /* nonzero: time each kernel class with HIP events     */
+  int32_t timing;       /* 1: time each kernel class with HIP events; s > 1:
+                           the operator applies and reorthogonalisation
+                           kernels only at every s-th Lanczos step (the other
+                           classes at every launch), and then t_matvec,
+                           t_dots, t_update, n_*_launch and bytes_* of those
+                           three classes cover the timed launches only      */
   int32_t trace_cap;    /* record alpha_j, beta_j of the first trace_cap steps */
   double* trace_ab;     /* host [2 * trace_cap]: alpha then beta (may be NULL) */
   int32_t verbose;      /* nonzero: one progress line per cycle on stderr      */
@@ -200,7 +212,9 @@ typedef struct {
   int32_t status;       /* same as the return value of jl_solve                 */
   int64_t sum_ncol;     /* sum over Lanczos steps of the basis width j + 1      */
   /* Per kernel class (only with params.timing): accumulated GPU time [s],
-   * launch count and algorithmic bytes (or flops for the GEMM). */
+   * launch count and algorithmic bytes (or flops for the GEMM); with
+   * params.timing = s > 1 the matvec, dots and update figures are those of
+   * the timed launches. */
   double t_total;       /* wall time of jl_solve [s] (always set)               */
   double t_matvec, t_dots, t_update, t_gemm, t_ritz, t_resid;
   int64_t n_matvec_launch, n_dots_launch, n_update_launch, n_gemm_launch;

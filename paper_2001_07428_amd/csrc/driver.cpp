@@ -338,10 +338,25 @@ jl_status check_params(jl_ctx ctx, const jl_op_s* op, const jl_params* p) {
 }
 
 // Accumulates GPU time of kernel classes from HIP event pairs; pairs are
-// resolved at the driver's synchronisation points.
+// resolved at the driver's synchronisation points.  With stride > 1 the
+// per-step classes (operator apply, inner products, update) are timed only
+// while `sample` is set (every stride-th Lanczos step), and count()/tcnt/
+// tbytes keep the launches and bytes of the timed launches.
 struct Timer {
   enum { MATVEC, DOTS, UPDATE, GEMM, RITZ, RESID, CG, NCLS };
   bool on = false;
+  int stride = 1;
+  bool sample = true;
+  int64_t tcnt[NCLS] = {};
+  double tbytes[NCLS] = {};
+  static bool per_step(int cls) { return cls == MATVEC || cls == DOTS || cls == UPDATE; }
+  bool timed(int cls) const { return on && (sample || !per_step(cls)); }
+  void count(int cls, double bytes) {
+    if (timed(cls)) {
+      tcnt[cls]++;
+      tbytes[cls] += bytes;
+    }
+  }
   hipStream_t st = nullptr;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
@@ -359,7 +374,10 @@ struct Timer {
     return e;
   }
   void start(int cls) {
-    if (!on) return;
+    if (!timed(cls)) {
+      cur_start = nullptr;
+      return;
+    }
     cur = cls;
     cur_start = get();
     if (cur_start) hipEventRecord(cur_start, st);
@@ -506,6 +524,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
 
   Timer tm;
   tm.on = prm->timing != 0;
+  tm.stride = prm->timing > 1 ? prm->timing : 1;
   tm.st = st;
 
   // ---- start vector (Alg. 1: v_1 = ones / ||ones||, or the caller's)
@@ -603,6 +622,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       if (e == hipSuccess) e = launch_reduce_cols(apart, napply, 2, 2, scal, st);
       S_.n_matvec_launch++;
       S_.bytes_matvec += op_bytes(op, es);
+      tm.count(Timer::MATVEC, op_bytes(op, es));
       return e;
     };
     // ================= Algorithm 2: Lanczos steps j = k .. m-1
@@ -618,6 +638,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
         JL_HIP(ctx, queue_apply(vj, u));
       }
       applied = false;
+      tm.sample = S_.n_mv % tm.stride == 0;   // this step's (and the next queued apply's) events
       S_.n_mv++;
       S_.sum_ncol += ncol;
       // local three-term step u -= t_jj v_j + beta_{j-1} v_{j-1} fused into the
@@ -633,12 +654,14 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
                                      scal + 3));
       S_.n_dots_launch++;
       S_.bytes_dots += (double)(ncol + 1) * n * es;
+      tm.count(Timer::DOTS, (double)(ncol + 1) * n * es);
       tm.start(Timer::UPDATE);
       JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st, jsym,
                                           uloc ? uloc : u, gu, dscr, scal + 2, upd_cnt));
       tm.stop();
       S_.n_update_launch++;
       S_.bytes_update += (double)(ncol + 2) * n * es;
+      tm.count(Timer::UPDATE, (double)(ncol + 2) * n * es);
       JL_HIP(ctx, hipMemcpyAsync(hs, scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
       // speculative: v_{j+1} = u / ||u|| and A v_{j+1}, behind the copy
       const bool spec = !invert && j + 1 < m;
@@ -672,12 +695,14 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
         JL_HIP(ctx, launch_reduce_wide(dots_part, ndots, stride, stride, coef, wide_scr, wide_cnt, st));
         S_.n_dots_launch++;
         S_.bytes_dots += (double)(ncol + 1) * n * es;
+        tm.count(Timer::DOTS, (double)(ncol + 1) * n * es);
         tm.start(Timer::UPDATE);
         JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st, jsym,
                                             u, gu, dscr, scal + 2, upd_cnt));
         tm.stop();
         S_.n_update_launch++;
         S_.bytes_update += (double)(ncol + 2) * n * es;
+        tm.count(Timer::UPDATE, (double)(ncol + 2) * n * es);
         JL_HIP(ctx, hipMemcpyAsync(hs + 2, scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
         JL_HIP(ctx, hipStreamSynchronize(st));
         tm.resolve();
@@ -897,6 +922,14 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   tm.resolve();
   S_.icnv = icnv;
   S_.status = status;
+  if (tm.on && tm.stride > 1) {   // the per-step classes report their timed launches only
+    S_.n_matvec_launch = tm.tcnt[Timer::MATVEC];
+    S_.bytes_matvec = tm.tbytes[Timer::MATVEC];
+    S_.n_dots_launch = tm.tcnt[Timer::DOTS];
+    S_.bytes_dots = tm.tbytes[Timer::DOTS];
+    S_.n_update_launch = tm.tcnt[Timer::UPDATE];
+    S_.bytes_update = tm.tbytes[Timer::UPDATE];
+  }
   S_.t_matvec = tm.t[Timer::MATVEC];
   S_.t_dots = tm.t[Timer::DOTS];
   S_.t_update = tm.t[Timer::UPDATE];

@@ -183,7 +183,11 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
   const int nout = dots_stride(ncol);
   for (int i = threadIdx.x; i < nout; i += kReorthThreads) acc[i] = 0.0;
   __syncthreads();
-  double unorm = 0.0, anorm = 0.0;
+  // wavefront 0 of group 0 sums ||u||^2 (into acc[4 ncol] at the end) and,
+  // with LOCAL, the norm after t v_jl alone (per chunk into acc[4 ncol + 1]:
+  // no second accumulator stays live across the column loop)
+  const bool nw = wave == 0 && blockIdx.y == 0;
+  double unorm = 0.0;
   for (int ch = 0; ch < chunks; ++ch) {
     const int64_t p0 = ((int64_t)blockIdx.x * chunks + ch) * CH;
     if (p0 >= h) break;
@@ -209,6 +213,7 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
     }
     if constexpr (LOCAL) {
       __syncthreads();   // every wavefront holds the raw chunk before it is overwritten
+      double anorm = 0.0;
       const double t_re = tloc[0], t_im = tloc[1];
       const cplx<S>* vj = V + (int64_t)jl * ldv;
       const cplx<S>* vm = vj - ldv;
@@ -252,8 +257,12 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
           }
         }
       }
+      if (nw) {
+        anorm = wave_sum(anorm);
+        if (lane == 0) acc[4 * ncol + 1] += anorm;
+      }
     }
-    if (wave == 0 && blockIdx.y == 0) {
+    if (nw) {
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -292,13 +301,9 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
       }
     }
   }
-  if (wave == 0 && blockIdx.y == 0) {
+  if (nw) {
     unorm = wave_sum(unorm);
-    if (LOCAL) anorm = wave_sum(anorm);
-    if (lane == 0) {
-      acc[4 * ncol] = unorm;
-      acc[4 * ncol + 1] = LOCAL ? anorm : 0.0;
-    }
+    if (lane == 0) acc[4 * ncol] = unorm;
   }
   __syncthreads();
   // this group's columns (and, for group 0, the norms) of the block's row

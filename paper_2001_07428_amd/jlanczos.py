@@ -302,7 +302,7 @@ def _params(nev, m, mwin, tol, which, max_cycles, max_passes, timing, trace_buf,
     p.max_cycles = int(max_cycles)
     p.max_passes = int(max_passes)
     p.min_passes = int(min_passes)
-    p.timing = int(bool(timing))
+    p.timing = int(timing) if not isinstance(timing, bool) else int(timing)
     if trace_buf is not None:
         p.trace_cap = len(trace_buf) // 2
         p.trace_ab = trace_buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
