@@ -40,6 +40,8 @@
  *      . the Case B operator's padded links, product matrices, projection
  *        tables and product jobs, about 56 Np^2 complex elements
  *        (Np = N rounded up to 64), jl_op_create_tek until jl_op_destroy;
+ *      . a static 17.5 MB scratch array per GPU for the allocation-free
+ *        entry point (jlanczos_kernels.h), part of the loaded library;
  *      . HIP events, streams and the batch's captured graph.
  *    Pinned host memory: a few scalars per jl_solve call, and a batch's
  *    results (jl_batch_create until jl_batch_destroy).

@@ -28,6 +28,20 @@ jl_status jl_reorth_pass_workspace_bytes(int64_t n, int32_t ncol, size_t* bytes)
 jl_status jl_reorth_pass(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t ncol, const void* V,
                          int64_t ldv, void* u, double* coef, void* ws, size_t ws_bytes);
 
+/* The same pass as jl_reorth_pass for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops): no workspace argument, no
+ * device allocation, no memset.  Its scratch (partial sums and counters) is
+ * a static device array of the library, 17.5 MB per GPU, held from the first
+ * jl_ctx_create on that GPU until the process ends; every call on one GPU
+ * shares it, so calls that overlap on one GPU (other streams, other
+ * contexts, other threads) race and must be ordered by the caller.  Same
+ * arguments and results as jl_reorth_pass.  Errors: JL_EINVAL as
+ * jl_reorth_pass, and for ncol > 256 or n beyond the scratch (more than
+ * 65536 update blocks: n above about 2.7e8 in FP32); JL_EHIP if the scratch
+ * could not be located on the context's device. */
+jl_status jl_reorth_pass_noalloc(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t ncol,
+                                 const void* V, int64_t ldv, void* u, double* coef);
+
 /* Rayleigh-Ritz step of Alg. 1: T = Z diag(lam) Z^T for a real symmetric
  * m x m FP64 matrix T (device, column-major, leading dimension m), with the
  * eigenpairs sorted ascending (which = JL_LOWEST) or descending

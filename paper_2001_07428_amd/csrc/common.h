@@ -190,6 +190,8 @@ hipError_t launch_scale(cplx<S>* u, int64_t n, double scale, hipStream_t st);
 // u *= 1 / sqrt(*nrm2), nrm2 read on the device (n complex).
 template <typename S>
 hipError_t launch_scale_dev(cplx<S>* u, int64_t n, const double* nrm2, hipStream_t st);
+// p[0 .. n) = 0 by a kernel (no memset node when the caller captures a graph).
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 // fill with a constant real value (n complex).
 template <typename S>
 hipError_t launch_fill(cplx<S>* u, int64_t n, double value, hipStream_t st);

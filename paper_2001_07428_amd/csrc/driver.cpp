@@ -1081,6 +1081,14 @@ jl_status jl_ctx_create(jl_ctx* out, int32_t device, void* hip_stream) {
   jl_ctx c = new jl_ctx_s();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  {   // the allocation-free entry points' scratch on this device (with it current)
+    DeviceGuard g(device);
+    const hipError_t se = noalloc_scratch_address(device, &c->na_scratch);
+    if (se != hipSuccess) {
+      c->na_scratch = nullptr;
+      c->na_err = std::string("hipGetSymbolAddress of the static scratch: ") + hipGetErrorString(se);
+    }
+  }
   *out = c;
   return JL_OK;
 }

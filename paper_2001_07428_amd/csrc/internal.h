@@ -13,6 +13,8 @@ struct jl_ctx_s {
   hipStream_t stream = nullptr;   // caller's stream (borrowed; NULL = legacy default stream)
   hipStream_t work = nullptr;     // owned non-blocking stream for jl_solve's launch sequence
   hipEvent_t order = nullptr;     // orders `work` after `stream`
+  void* na_scratch = nullptr;     // device address of this device's allocation-free scratch
+  std::string na_err;             // why na_scratch could not be set up (if it could not)
   std::string err;
   ~jl_ctx_s() {
     if (order) (void)hipEventDestroy(order);
@@ -27,6 +29,11 @@ namespace jl {
 // stream.  A solve issues thousands of small launches; on the legacy default
 // stream each one also synchronises with the other blocking streams.
 hipError_t work_stream(jl_ctx ctx, hipStream_t* out);
+
+// Device address of the library's static scratch array on `device` (the
+// current device), looked up once per device and cached; used by the
+// allocation-free entry points.
+hipError_t noalloc_scratch_address(int device, void** out);
 
 // Records the message for jl_last_error(ctx) (and the calling thread) and
 // returns `code`.

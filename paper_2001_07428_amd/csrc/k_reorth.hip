@@ -619,6 +619,11 @@ __global__ void k_scale_dev(cplx<S>* __restrict__ u, int64_t n, const double* __
   }
 }
 
+__global__ void k_zero_u32(unsigned* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 template <typename S>
 __global__ void k_fill(cplx<S>* __restrict__ u, int64_t n, S val) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -848,6 +853,12 @@ hipError_t launch_scale(cplx<S>* u, int64_t n, double scale, hipStream_t st) {
 template <typename S>
 hipError_t launch_scale_dev(cplx<S>* u, int64_t n, const double* nrm2, hipStream_t st) {
   hipLaunchKernelGGL(k_scale_dev<S>, dim3(blocks_for(n, 256)), dim3(256), 0, st, u, n, nrm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/jlanczos_kernels.h"
@@ -29,28 +30,73 @@ size_t reorth_ws_part(int64_t n, int ncol, int which) {
 }
 size_t reorth_ws(int64_t n, int ncol) { return reorth_ws_part(n, ncol, 4); }
 
+// One pass with the scratch at dp (dots partials), up (update partials), scr
+// (wide-reduction slices) and cnt (its tile counters, cleared here by a
+// kernel, so the sequence holds no memset node when a caller captures it).
 template <typename S>
-hipError_t reorth_pass(int64_t n, int ncol, const cplx<S>* V, int64_t ldv, cplx<S>* u, double* coef,
-                       char* ws, hipStream_t st) {
+hipError_t reorth_pass_on(int64_t n, int ncol, const cplx<S>* V, int64_t ldv, cplx<S>* u,
+                          double* coef, double* dp, double* up, double* scr, unsigned* cnt,
+                          hipStream_t st) {
   const int64_t h = n / 2;
   const int nd = reorth_dots_blocks(h, (int)sizeof(cplx<S>)),
             nu = reorth_update_blocks(h, (int)sizeof(cplx<S>));
-  double* dp = reinterpret_cast<double*>(ws);
-  double* up = reinterpret_cast<double*>(ws + reorth_ws_part(n, ncol, 1));
-  double* scr = reinterpret_cast<double*>(ws + reorth_ws_part(n, ncol, 2));
-  unsigned* cnt = reinterpret_cast<unsigned*>(ws + reorth_ws_part(n, ncol, 3));
   const int stride = dots_stride(ncol);   // coef[4 ncol + 1] is then overwritten by the norm after
   hipError_t e;
-  if ((e = hipMemsetAsync(cnt, 0, sizeof(unsigned) * (size_t)reduce_wide_tiles(stride), st)) !=
-      hipSuccess)
-    return e;
+  if ((e = launch_zero_u32(cnt, reduce_wide_tiles(stride), st)) != hipSuccess) return e;
   if ((e = launch_reorth_dots<S>(V, ldv, ncol, u, h, dp, nd, st)) != hipSuccess) return e;
   if ((e = launch_reduce_wide(dp, nd, stride, stride, coef, scr, cnt, st)) != hipSuccess) return e;
   if ((e = launch_reorth_update<S>(V, ldv, ncol, u, h, coef, up, nu, st)) != hipSuccess) return e;
   return launch_reduce_cols(up, nu, 1, 1, coef + 4 * ncol + 1, st);
 }
 
+template <typename S>
+hipError_t reorth_pass(int64_t n, int ncol, const cplx<S>* V, int64_t ldv, cplx<S>* u, double* coef,
+                       char* ws, hipStream_t st) {
+  return reorth_pass_on<S>(n, ncol, V, ldv, u, coef, reinterpret_cast<double*>(ws),
+                           reinterpret_cast<double*>(ws + reorth_ws_part(n, ncol, 1)),
+                           reinterpret_cast<double*>(ws + reorth_ws_part(n, ncol, 2)),
+                           reinterpret_cast<unsigned*>(ws + reorth_ws_part(n, ncol, 3)), st);
+}
+
+// ---------------------------------------------------- allocation-free pass
+// The scratch of jl_reorth_pass_noalloc lives in a static device array (one
+// copy per GPU, held until the process ends), sized for at most
+// kNaMaxCols basis columns and kNaMaxUpdBlocks update blocks: the dots
+// partials of at most 2048 blocks (reorth_dots_blocks never exceeds it), the
+// update partials, the wide-reduction slices (at most 16) and the counters.
+constexpr int kNaMaxCols = 256;
+constexpr int kNaMaxDotsBlocks = 2048;
+constexpr int kNaMaxUpdBlocks = 65536;
+constexpr size_t na_up(size_t d) { return (d + 31) / 32 * 32; }   // 256-byte segments
+constexpr size_t kNaDots = na_up((size_t)kNaMaxDotsBlocks * dots_stride(kNaMaxCols));
+constexpr size_t kNaUpd = na_up(kNaMaxUpdBlocks);
+constexpr size_t kNaWide = na_up((size_t)16 * dots_stride(kNaMaxCols));
+constexpr size_t kNaCnt = na_up(((size_t)dots_stride(kNaMaxCols) + 63) / 64);   // unsigned fit in doubles
+constexpr size_t kNaDoubles = kNaDots + kNaUpd + kNaWide + kNaCnt;   // 17.5 MB
+
 }  // namespace
+
+static __device__ __align__(256) double scratch[kNaDoubles];
+
+namespace jl {
+
+hipError_t noalloc_scratch_address(int device, void** out) {
+  constexpr int kMaxDevices = 256;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
+
+}  // namespace jl
 
 extern "C" {
 
@@ -78,6 +124,39 @@ jl_status jl_reorth_pass(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t ncol, co
                                     static_cast<double2*>(u), coef, static_cast<char*>(ws), ctx->stream));
   else
     return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
+  return JL_OK;
+}
+
+jl_status jl_reorth_pass_noalloc(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t ncol,
+                                 const void* V, int64_t ldv, void* u, double* coef) {
+  if (!ctx) return set_err(nullptr, JL_EINVAL, "ctx is NULL");
+  if (n <= 0 || n % 2 || ncol < 0 || ldv < n || !u || !coef || (ncol > 0 && !V))
+    return set_err(ctx, JL_EINVAL, "invalid reorth_pass_noalloc arguments");
+  if (dtype != JL_C64 && dtype != JL_C128)
+    return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
+  const int64_t h = n / 2;
+  const int es = dtype == JL_C64 ? 8 : 16;
+  if (ncol > kNaMaxCols)
+    return set_err(ctx, JL_EINVAL, "reorth_pass_noalloc: ncol = %d exceeds the static scratch limit %d",
+                   ncol, kNaMaxCols);
+  if (reorth_update_blocks(h, es) > kNaMaxUpdBlocks || reorth_dots_blocks(h, es) > kNaMaxDotsBlocks)
+    return set_err(ctx, JL_EINVAL,
+                   "reorth_pass_noalloc: n = %lld exceeds the static scratch limit", (long long)n);
+  if (!ctx->na_scratch)
+    return set_err(ctx, JL_EHIP, "reorth_pass_noalloc: no static scratch on device %d (%s)",
+                   ctx->device, ctx->na_err.c_str());
+  double* base = static_cast<double*>(ctx->na_scratch);
+  double* dp = base;
+  double* up = dp + kNaDots;
+  double* scr = up + kNaUpd;
+  unsigned* cnt = reinterpret_cast<unsigned*>(scr + kNaWide);
+  DeviceGuard g(ctx->device);
+  if (dtype == JL_C64)
+    JL_HIP(ctx, reorth_pass_on<float>(n, ncol, static_cast<const float2*>(V), ldv,
+                                      static_cast<float2*>(u), coef, dp, up, scr, cnt, ctx->stream));
+  else
+    JL_HIP(ctx, reorth_pass_on<double>(n, ncol, static_cast<const double2*>(V), ldv,
+                                       static_cast<double2*>(u), coef, dp, up, scr, cnt, ctx->stream));
   return JL_OK;
 }
 

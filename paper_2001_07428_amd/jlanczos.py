@@ -32,7 +32,8 @@ EXPORTS = (
     "jl_ctx_create", "jl_ctx_destroy", "jl_last_error", "jl_status_string",
     "jl_op_create_dense", "jl_op_create_stencil", "jl_op_create_tek", "jl_op_destroy", "jl_op_dim",
     "jl_op_apply", "jl_workspace_bytes", "jl_solve", "jl_pair_vectors",
-    "jl_reorth_pass_workspace_bytes", "jl_reorth_pass", "jl_ritz_workspace_bytes", "jl_ritz",
+    "jl_reorth_pass_workspace_bytes", "jl_reorth_pass", "jl_reorth_pass_noalloc",
+    "jl_ritz_workspace_bytes", "jl_ritz",
     "jl_ritz_restart_workspace_bytes", "jl_ritz_restart",
     "jl_basis_update", "jl_batch_workspace_bytes", "jl_batch_create", "jl_batch_run",
     "jl_batch_destroy",
@@ -109,6 +110,7 @@ def load_library(path: str = LIB_PATH):
         "jl_pair_vectors": (i32, [vp, i64, i32, i32, vp, i64, vp, i64]),
         "jl_reorth_pass_workspace_bytes": (i32, [i64, i32, ctypes.POINTER(ctypes.c_size_t)]),
         "jl_reorth_pass": (i32, [vp, i32, i64, i32, vp, i64, vp, vp, vp, ctypes.c_size_t]),
+        "jl_reorth_pass_noalloc": (i32, [vp, i32, i64, i32, vp, i64, vp, vp]),
         "jl_ritz_workspace_bytes": (i32, [i32, ctypes.POINTER(ctypes.c_size_t)]),
         "jl_ritz": (i32, [vp, i32, vp, i32, vp, vp, vp, ctypes.c_size_t]),
         "jl_ritz_restart_workspace_bytes": (i32, [i32, ctypes.POINTER(ctypes.c_size_t)]),
@@ -410,6 +412,22 @@ def jl_reorth_pass(ctx: Context, V, u):
                               ctypes.c_void_p(V.data_ptr()) if ncol else None, n,
                               ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(coef.data_ptr()),
                               ctypes.c_void_p(ws.data_ptr()), nb.value), ctx.handle)
+    return coef
+
+
+def jl_reorth_pass_noalloc(ctx: Context, V, u, coef):
+    """As jl_reorth_pass, with the library's static scratch (no workspace,
+    no device allocation): coef is the caller's FP64 device tensor of at least
+    4*ncol + 2 entries, filled as jl_reorth_pass returns it."""
+    lib = load_library()
+    n = u.shape[-1]
+    ncol = 0 if V is None else V.shape[0]
+    if coef.dtype != _torch().float64 or coef.numel() < 4 * ncol + 2 or not coef.is_contiguous():
+        raise ValueError("coef must be a contiguous float64 tensor of >= 4*ncol + 2 entries")
+    _check(lib.jl_reorth_pass_noalloc(ctx.handle, _dtype_code(u), n, ncol,
+                                      ctypes.c_void_p(V.data_ptr()) if ncol else None, n,
+                                      ctypes.c_void_p(u.data_ptr()),
+                                      ctypes.c_void_p(coef.data_ptr())), ctx.handle)
     return coef
 
 
