@@ -560,7 +560,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--verbose", action="store_true", help="per-cycle progress on stderr")
+    ap.add_argument("--verbose", action="store_true",
+                    help="per-iteration progress on stderr (always on for the stencil workloads, "
+                         "whose solves take minutes, unless --quiet)")
+    ap.add_argument("--quiet", action="store_true", help="no per-iteration progress")
     ap.add_argument("--probe", action="store_true",
                     help="run the counter probe (copy + apply + reorth pass) instead")
     args = ap.parse_args()
@@ -574,6 +577,8 @@ def main():
         args.steps = 10 if cyc else 2
     if args.warmup is None:
         args.warmup = 2 if cyc else 1
+    if cyc and not args.quiet:
+        args.verbose = True
     if args.steps < (1 if cyc else 0) or args.warmup < 0:
         ap.error("--steps must be >= 1 for the stencil workloads (>= 0 otherwise), --warmup >= 0")
     # host inputs first: the Case A recipe runs in worker processes, forked
