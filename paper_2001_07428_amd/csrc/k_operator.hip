@@ -295,36 +295,119 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {   // result 
   return r;
 }
 
-// ||A x_c - lam_c x_c||^2 per block in FP64 (x stored as S).
+// True residuals ||A x_c - lam_c x_c||^2 of many columns x_c = X + cols[c]*ldx
+// with the links read once for all of them: sixteen threads per site, thread
+// (mu, r) computes the hops in direction mu of row r of both halves of
+// (A x_c)(s) and keeps the link entries it multiplies in registers for every
+// column (row r of U_mu(s), column r of U_mu(s - mu)); the four directions of
+// a row are summed across lanes.  The site-independent B sits in LDS (per-site
+// B is read per use).  FP64 products and accumulation on the stored vectors.
+// partial[blk * ncols + c] = the block's share of column c
+// (stencil_resid_blocks blocks).
+constexpr int kResidSites = kStencilThreads / 16;   // sites per block
+
 template <typename S, bool BSITE>
 __global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S> a,
                                                                    const cplx<S>* __restrict__ X,
                                                                    int64_t ldx,
                                                                    const int* __restrict__ cols,
                                                                    const double* __restrict__ lam,
+                                                                   int ncols,
                                                                    double* __restrict__ partial) {
-  __shared__ double sh[kStencilThreads / 64];
-  const int64_t s = (int64_t)blockIdx.x * kStencilThreads + threadIdx.x;
-  const int c = blockIdx.y;
-  const int64_t h = a.V * 4;
-  double acc = 0.0;
-  if (s < a.V) {
-    const cplx<S>* xc = X + (int64_t)cols[c] * ldx;
-    cx<double> top[4], bot[4];
-    stencil_site<S, double, BSITE>(a, Operand<S, false>{xc}, h, s, top, bot);
-    double a0r[4], a0i[4], b0r[4], b0i[4];
-    load_site<S, double>(xc + s * 4, a0r, a0i);
-    load_site<S, double>(xc + h + s * 4, b0r, b0i);
-    const double l = lam[c];
+  __shared__ cplx<S> Bs[64];
+  __shared__ double red[2][kStencilThreads / 64];
+  const int r = threadIdx.x & 3, mu = (threadIdx.x >> 2) & 3;
+  const int64_t s_raw = (int64_t)blockIdx.x * kResidSites + (threadIdx.x >> 4);
+  const bool ok = s_raw < a.V;
+  const int64_t s = ok ? s_raw : a.V - 1;   // in-bounds loads; the contribution is dropped
+  const int64_t V = a.V, h = V * 4;
+  if (!BSITE && threadIdx.x < 64) Bs[threadIdx.x] = a.B[threadIdx.x];
+  const unsigned Ls[4] = {(unsigned)a.L[0], (unsigned)a.L[1], (unsigned)a.L[2], (unsigned)a.L[3]};
+  const unsigned st[4] = {Ls[1] * Ls[2] * Ls[3], Ls[2] * Ls[3], Ls[3], 1u};
+  unsigned xm;   // coordinate of s in direction mu
+  {
+    unsigned t = (unsigned)s, xc[4];
+    xc[0] = t / st[0]; t -= xc[0] * st[0];
+    xc[1] = t / st[1]; t -= xc[1] * st[1];
+    xc[2] = t / st[2]; t -= xc[2] * st[2];
+    xc[3] = t;
+    xm = xc[mu];
+  }
+  const unsigned Lm = Ls[mu], sm = st[mu];
+  const int64_t sf = (xm == Lm - 1) ? s - (int64_t)((Lm - 1) * sm) : s + sm;
+  const int64_t sb = (xm == 0) ? s + (int64_t)((Lm - 1) * sm) : s - sm;
+  const cplx<S>* Um = a.U + (int64_t)mu * 16 * V;
+  cplx<S> uf[4], ub[4];   // uf[c] = U_mu(s)[r][c], ub[c] = U_mu(s - mu)[c][r]
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double tr = top[r].re - l * a0r[r], ti = top[r].im - l * a0i[r];
-      const double br = bot[r].re - l * b0r[r], bi = bot[r].im - l * b0i[r];
-      acc += tr * tr + ti * ti + br * br + bi * bi;
+  for (int c = 0; c < 4; ++c) {
+    uf[c] = Um[(int64_t)(4 * r + c) * V + s];
+    ub[c] = Um[(int64_t)(4 * c + r) * V + sb];
+  }
+  __syncthreads();   // Bs
+  const cplx<S>* Bm = BSITE ? a.B + (int64_t)mu * 16 * V : Bs + mu * 16;
+  const double dg = a.diag, sc = a.scale;
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  for (int col = 0; col < ncols; ++col) {
+    const cplx<S>* x = X + (int64_t)cols[col] * ldx;
+    double tr = 0.0, ti = 0.0, br = 0.0, bi = 0.0;   // row r, direction mu
+    if (mu == 0) {   // (diag - l) x(s), once per row
+      const double l = lam[col];
+      const cplx<S> xa = x[s * 4 + r], xb = x[h + s * 4 + r];
+      tr = (dg - l) * (double)xa.x; ti = (dg - l) * (double)xa.y;
+      br = (dg - l) * (double)xb.x; bi = (dg - l) * (double)xb.y;
+    }
+    {   // forward: U(s) a(s+mu), conj(U(s)) b(s+mu), B b(s+mu), conj(B) a(s+mu)
+      double ar[4], ai[4], vr[4], vi[4];
+      load_site<S, double>(x + sf * 4, ar, ai);
+      load_site<S, double>(x + h + sf * 4, vr, vi);
+      cx<double> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const cplx<S> wv = BSITE ? Bm[(int64_t)(4 * r + c) * V + s] : Bm[4 * r + c];
+        const double ur = uf[c].x, ui = uf[c].y, wr = wv.x, wi = wv.y;
+        mac(t, ur, ui, ar[c], ai[c]);
+        mac_conj_a(q, ur, ui, vr[c], vi[c]);
+        mac(tb, wr, wi, vr[c], vi[c]);
+        mac_conj_a(qb, wr, wi, ar[c], ai[c]);
+      }
+      tr += sc * tb.re - t.re; ti += sc * tb.im - t.im;
+      br -= q.re + sc * qb.re; bi -= q.im + sc * qb.im;
+    }
+    {   // backward: U(s-mu)^H a, U(s-mu)^T b, B(s-mu)^T b, B(s-mu)^H a at s - mu
+      double ar[4], ai[4], vr[4], vi[4];
+      load_site<S, double>(x + sb * 4, ar, ai);
+      load_site<S, double>(x + h + sb * 4, vr, vi);
+      cx<double> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const cplx<S> wv = BSITE ? Bm[(int64_t)(4 * c + r) * V + sb] : Bm[4 * c + r];
+        const double ur = ub[c].x, ui = ub[c].y, wr = wv.x, wi = wv.y;
+        mac_conj_a(t, ur, ui, ar[c], ai[c]);
+        mac(q, ur, ui, vr[c], vi[c]);
+        mac(tb, wr, wi, vr[c], vi[c]);
+        mac_conj_a(qb, wr, wi, ar[c], ai[c]);
+      }
+      tr -= t.re + sc * tb.re; ti -= t.im + sc * tb.im;
+      br += sc * qb.re - q.re; bi += sc * qb.im - q.im;
+    }
+    // the four directions of row r: lanes that differ in bits 2 and 3
+#pragma unroll
+    for (int o = 4; o <= 8; o <<= 1) {
+      tr += __shfl_xor(tr, o); ti += __shfl_xor(ti, o);
+      br += __shfl_xor(br, o); bi += __shfl_xor(bi, o);
+    }
+    double acc = (ok && mu == 0) ? tr * tr + ti * ti + br * br + bi * bi : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) red[col & 1][w] = acc;
+    __syncthreads();   // red[col & 1] is next written two columns on, after another barrier
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+#pragma unroll
+      for (int k = 0; k < kStencilThreads / 64; ++k) tot += red[col & 1][k];
+      partial[(int64_t)blockIdx.x * ncols + col] = tot;
     }
   }
-  const double tot = block_sum<kStencilThreads>(acc, sh);
-  if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * gridDim.y + c] = tot;
 }
 
 // Links from the caller's [mu][V][16] (site-major) layout into the
@@ -526,8 +609,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_resid(DenseArgs<S> a,
 
 }  // namespace
 
-int stencil_resid_blocks(int64_t V) { return (int)((V + kStencilThreads - 1) / kStencilThreads); }
-int stencil_apply_blocks(int64_t V) { return stencil_resid_blocks(V); }
+int stencil_resid_blocks(int64_t V) { return (int)((V + kResidSites - 1) / kResidSites); }
+int stencil_apply_blocks(int64_t V) { return (int)((V + kStencilThreads - 1) / kStencilThreads); }
 int dense_apply_blocks(int64_t h) { return (int)((h + kDenseRows - 1) / kDenseRows); }
 int dense_resid_blocks(int64_t h) { return (int)((h + kDenseThreads / 64 - 1) / (kDenseThreads / 64)); }
 
@@ -565,12 +648,13 @@ hipError_t launch_stencil_resid(const StencilArgs<S>& a, const cplx<S>* X, int64
                                 int* nblk, hipStream_t st) {
   const int nb = stencil_resid_blocks(a.V);
   *nblk = nb;
+  if (ncols <= 0) return hipSuccess;
   if (a.b_per_site)
-    hipLaunchKernelGGL((k_stencil_resid<S, true>), dim3((unsigned)nb, (unsigned)ncols),
-                       dim3(kStencilThreads), 0, st, a, X, ldx, cols, lam, partial);
+    hipLaunchKernelGGL((k_stencil_resid<S, true>), dim3((unsigned)nb), dim3(kStencilThreads), 0, st,
+                       a, X, ldx, cols, lam, ncols, partial);
   else
-    hipLaunchKernelGGL((k_stencil_resid<S, false>), dim3((unsigned)nb, (unsigned)ncols),
-                       dim3(kStencilThreads), 0, st, a, X, ldx, cols, lam, partial);
+    hipLaunchKernelGGL((k_stencil_resid<S, false>), dim3((unsigned)nb), dim3(kStencilThreads), 0, st,
+                       a, X, ldx, cols, lam, ncols, partial);
   return hipGetLastError();
 }
 
