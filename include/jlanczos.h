@@ -284,8 +284,8 @@ jl_status jl_pair_vectors(jl_ctx ctx, int64_t n, int32_t k, jl_dtype dtype, cons
  * Limits: m + (m mod 2) <= 60, 2 <= n_i, m <= n_i / 2, nev <= mwin < m;
  * normal mode, J-restricted only (p->standard and p->invert must be 0, else
  * JL_EUNSUPPORTED).
- * threads: workgroup size (128, 256 or 512; 0 = 256); blocks: persistent
- * workgroups (0 = min(count, 2 x compute units)); both are tuning knobs.
+ * The launch shape (jl_batch_shape, NULL for the defaults) holds the tuning
+ * knobs the autotuner picks per batch.
  * X[i] (device, n_i x nev column-major, leading dimension n_i) receives the
  * eigenvectors of problem i; the operator and X pointers are borrowed until
  * jl_batch_destroy.  Errors: JL_EINVAL, JL_ENOMEM, JL_EHIP.
@@ -293,19 +293,35 @@ jl_status jl_pair_vectors(jl_ctx ctx, int64_t n, int32_t k, jl_dtype dtype, cons
 typedef struct jl_batch_s* jl_batch;
 
 typedef struct {
+  int32_t threads;          /* workgroup size: 128, 256 or 512 (0: 256)                */
+  int32_t blocks;           /* persistent workgroups (0: min(count, 2 x compute units)) */
+  int32_t rows_per_wave;    /* rows of [A11 A12] a wavefront applies at once: 1 or 2
+                               (0: 1)                                                  */
+  int32_t unroll;           /* column steps whose loads each lane issues together:
+                               4 or 8 (0: 4)                                          */
+  int32_t lds_matrix_bytes; /* LDS bytes per workgroup for a problem's whole
+                               [A11 A12] (2 h^2 complex elements): a problem that fits
+                               is read from LDS for its whole solve (0: none; a
+                               multiple of 16, within the device's per-workgroup LDS
+                               with the solver's own use)                         */
+} jl_batch_shape;
+
+typedef struct {
   int32_t cycles;       /* outer iterations                                     */
   int32_t n_mv;         /* Lanczos matvecs                                      */
   int32_t gs_passes;    /* reorthogonalisation passes                           */
   int32_t icnv;         /* converged pairs                                      */
+  int32_t n_resid;      /* operator applies spent on true-residual checks       */
 } jl_batch_stats;
 
 jl_status jl_batch_workspace_bytes(int32_t count, const int64_t* n, jl_dtype dtype,
-                                   const jl_params* p, int32_t threads, int32_t blocks,
-                                   size_t* bytes);
+                                   const jl_params* p, const jl_batch_shape* shape, size_t* bytes);
 jl_status jl_batch_create(jl_ctx ctx, int32_t count, const int64_t* n, const void* const* A11,
                           const void* const* A12, jl_dtype dtype, const jl_params* p,
-                          void* const* X, void* ws, size_t ws_bytes, int32_t threads,
-                          int32_t blocks, jl_batch* out);
+                          void* const* X, void* ws, size_t ws_bytes, const jl_batch_shape* shape,
+                          jl_batch* out);
+/* The launch shape the batch uses, with the defaults resolved. */
+jl_status jl_batch_shape_used(jl_batch b, jl_batch_shape* shape);
 /* Runs the captured graph and waits for it.  evals, res: host [count * nev]
  * (problem-major, converged pairs first); status: host [count] (JL_OK,
  * JL_NOT_CONVERGED or JL_BREAKDOWN per problem); stats: host [count] or NULL.

@@ -14,6 +14,7 @@ using namespace jl;
 struct jl_batch_s {
   jl_ctx ctx = nullptr;
   int count = 0, nev = 0;
+  jl_batch_shape shape{};    // the launch shape in use (defaults resolved)
   hipStream_t stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -28,17 +29,25 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 struct BLayout {
   size_t table, order, queue, evals, res, status, stats, slots, total;
   size_t slot_bytes;
-  int blocks, threads;
+  jl_batch_shape shape;
   int64_t hmax;
 };
 
 jl_status batch_layout(jl_ctx ctx, int count, const int64_t* n, jl_dtype dtype, const jl_params* p,
-                       int threads, int blocks, BLayout* L) {
+                       const jl_batch_shape* shp, BLayout* L) {
   if (count < 1 || !n || !p) return set_err(ctx, JL_EINVAL, "count >= 1, n and params are required");
   if (dtype != JL_C64 && dtype != JL_C128) return set_err(ctx, JL_EINVAL, "dtype must be JL_C64 or JL_C128");
-  if (threads == 0) threads = 256;
-  if (threads != 128 && threads != 256 && threads != 512)
+  jl_batch_shape sh = shp ? *shp : jl_batch_shape{};
+  if (sh.threads == 0) sh.threads = 256;
+  if (sh.rows_per_wave == 0) sh.rows_per_wave = 1;
+  if (sh.unroll == 0) sh.unroll = 4;
+  if (sh.threads != 128 && sh.threads != 256 && sh.threads != 512)
     return set_err(ctx, JL_EINVAL, "threads must be 128, 256 or 512");
+  if (sh.rows_per_wave != 1 && sh.rows_per_wave != 2)
+    return set_err(ctx, JL_EINVAL, "rows_per_wave must be 1 or 2");
+  if (sh.unroll != 4 && sh.unroll != 8) return set_err(ctx, JL_EINVAL, "unroll must be 4 or 8");
+  if (sh.lds_matrix_bytes < 0 || sh.lds_matrix_bytes % 16)
+    return set_err(ctx, JL_EINVAL, "lds_matrix_bytes must be a non-negative multiple of 16");
   if (p->nev < 1 || p->mwin < p->nev || p->m <= p->mwin)
     return set_err(ctx, JL_EINVAL, "need 1 <= nev <= mwin < m");
   if (p->m + (p->m & 1) > 60) return set_err(ctx, JL_EINVAL, "batched solver supports m <= 59 (got %d)", p->m);
@@ -53,17 +62,19 @@ jl_status batch_layout(jl_ctx ctx, int count, const int64_t* n, jl_dtype dtype, 
     hmax = std::max(hmax, n[i] / 2);
   }
   const int es = dtype == JL_C64 ? 8 : 16;
-  if (batched_lds_bytes(hmax, p->m, es) > 160 * 1024)
-    return set_err(ctx, JL_EINVAL, "largest problem (n = %lld) exceeds the LDS budget", (long long)(2 * hmax));
-  if (blocks <= 0) {
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      ncu = 256;
-    blocks = std::min(count, 2 * ncu);
-  }
-  L->threads = threads;
-  L->blocks = blocks;
+  int dev = 0, ncu = 0, lds_max = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    ncu = 256;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      lds_max <= 0)
+    lds_max = 64 * 1024;
+  if (batched_lds_bytes(hmax, p->m, es) + (size_t)sh.lds_matrix_bytes > (size_t)lds_max)
+    return set_err(ctx, JL_EINVAL,
+                   "largest problem (n = %lld) with %d bytes for a resident matrix exceeds the %d bytes "
+                   "of LDS a workgroup may use", (long long)(2 * hmax), sh.lds_matrix_bytes, lds_max);
+  if (sh.blocks <= 0) sh.blocks = std::min(count, 2 * ncu);
+  L->shape = sh;
   L->hmax = hmax;
   L->slot_bytes = batched_slot_bytes(hmax, p->m, es);
   size_t off = 0;
@@ -74,8 +85,8 @@ jl_status batch_layout(jl_ctx ctx, int count, const int64_t* n, jl_dtype dtype, 
   L->evals = take(sizeof(double) * (size_t)count * p->nev);
   L->res = take(sizeof(double) * (size_t)count * p->nev);
   L->status = take(sizeof(int) * count);
-  L->stats = take(sizeof(int) * 4 * (size_t)count);
-  L->slots = take(L->slot_bytes * (size_t)blocks);
+  L->stats = take(sizeof(int) * kBatchStats * (size_t)count);
+  L->slots = take(L->slot_bytes * (size_t)sh.blocks);
   L->total = off;
   return JL_OK;
 }
@@ -85,11 +96,10 @@ jl_status batch_layout(jl_ctx ctx, int count, const int64_t* n, jl_dtype dtype, 
 extern "C" {
 
 jl_status jl_batch_workspace_bytes(int32_t count, const int64_t* n, jl_dtype dtype,
-                                   const jl_params* p, int32_t threads, int32_t blocks,
-                                   size_t* bytes) {
+                                   const jl_params* p, const jl_batch_shape* shape, size_t* bytes) {
   if (!bytes) return set_err(nullptr, JL_EINVAL, "bytes is NULL");
   BLayout L;
-  jl_status s = batch_layout(nullptr, count, n, dtype, p, threads, blocks, &L);
+  jl_status s = batch_layout(nullptr, count, n, dtype, p, shape, &L);
   if (s != JL_OK) return s;
   *bytes = L.total;
   return JL_OK;
@@ -97,13 +107,13 @@ jl_status jl_batch_workspace_bytes(int32_t count, const int64_t* n, jl_dtype dty
 
 jl_status jl_batch_create(jl_ctx ctx, int32_t count, const int64_t* n, const void* const* A11,
                           const void* const* A12, jl_dtype dtype, const jl_params* p,
-                          void* const* X, void* ws, size_t ws_bytes, int32_t threads,
-                          int32_t blocks, jl_batch* out) {
+                          void* const* X, void* ws, size_t ws_bytes, const jl_batch_shape* shape,
+                          jl_batch* out) {
   if (!ctx || !out) return set_err(ctx, JL_EINVAL, "ctx and out are required");
   if (!A11 || !A12 || !X) return set_err(ctx, JL_EINVAL, "A11, A12 and X arrays are required");
   DeviceGuard g(ctx->device);
   BLayout L;
-  jl_status s = batch_layout(ctx, count, n, dtype, p, threads, blocks, &L);
+  jl_status s = batch_layout(ctx, count, n, dtype, p, shape, &L);
   if (s != JL_OK) return s;
   if (!ws || ws_bytes < L.total)
     return set_err(ctx, JL_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, L.total);
@@ -135,12 +145,14 @@ jl_status jl_batch_create(jl_ctx ctx, int32_t count, const int64_t* n, const voi
   P.max_passes = p->max_passes > 0 ? p->max_passes : 16;
   P.min_passes = std::min(p->min_passes > 0 ? p->min_passes : 1, P.max_passes);
   P.tol_relative = p->tol_relative;
+  P.lds_mat = L.shape.lds_matrix_bytes;
   P.tol = p->tol;
 
   jl_batch b = new jl_batch_s();
   b->ctx = ctx;
   b->count = count;
   b->nev = p->nev;
+  b->shape = L.shape;
   auto fail = [&](jl_status code) {
     jl_batch_destroy(b);
     return code;
@@ -151,7 +163,8 @@ jl_status jl_batch_create(jl_ctx ctx, int32_t count, const int64_t* n, const voi
     return fail(set_err(ctx, JL_EHIP, "%s failed: %s", #expr, hipGetErrorString(e)));
   BCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   BCHK(hipEventCreateWithFlags(&b->ready, hipEventDisableTiming));
-  const size_t nout = 2 * (size_t)count * p->nev + 3 * (size_t)count;   // doubles
+  // doubles: evals, res, then the ints status [count] and stats [count][kBatchStats]
+  const size_t nout = 2 * (size_t)count * p->nev + ((size_t)(1 + kBatchStats) * count + 1) / 2;
   BCHK(hipHostMalloc((void**)&b->h_out, sizeof(double) * nout, hipHostMallocDefault));
   // table and order are uploaded once (synchronously: the host vectors die here)
   BCHK(hipMemcpyAsync(d_table, table.data(), sizeof(BatchProblem) * count, hipMemcpyHostToDevice, b->stream));
@@ -165,10 +178,13 @@ jl_status jl_batch_create(jl_ctx ctx, int32_t count, const int64_t* n, const voi
   BCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipError_t ce = launch_batched_init(d_queue, b->stream);
   if (ce == hipSuccess)
-    ce = dtype == JL_C64 ? launch_batched<float>(d_table, d_order, count, P, d_queue, slots, L.slot_bytes,
-                                                 L.hmax, o, L.threads, L.blocks, b->stream)
-                         : launch_batched<double>(d_table, d_order, count, P, d_queue, slots, L.slot_bytes,
-                                                  L.hmax, o, L.threads, L.blocks, b->stream);
+    ce = dtype == JL_C64
+             ? launch_batched<float>(d_table, d_order, count, P, d_queue, slots, L.slot_bytes, L.hmax, o,
+                                     L.shape.threads, L.shape.rows_per_wave, L.shape.unroll,
+                                     L.shape.blocks, b->stream)
+             : launch_batched<double>(d_table, d_order, count, P, d_queue, slots, L.slot_bytes, L.hmax, o,
+                                      L.shape.threads, L.shape.rows_per_wave, L.shape.unroll,
+                                      L.shape.blocks, b->stream);
   if (ce == hipSuccess)
     ce = hipMemcpyAsync(h_evals, o.evals, sizeof(double) * (size_t)count * p->nev, hipMemcpyDeviceToHost, b->stream);
   if (ce == hipSuccess)
@@ -176,13 +192,20 @@ jl_status jl_batch_create(jl_ctx ctx, int32_t count, const int64_t* n, const voi
   if (ce == hipSuccess)
     ce = hipMemcpyAsync(h_status, o.status, sizeof(int) * count, hipMemcpyDeviceToHost, b->stream);
   if (ce == hipSuccess)
-    ce = hipMemcpyAsync(h_stats, o.stats, sizeof(int) * 4 * (size_t)count, hipMemcpyDeviceToHost, b->stream);
+    ce = hipMemcpyAsync(h_stats, o.stats, sizeof(int) * kBatchStats * (size_t)count, hipMemcpyDeviceToHost,
+                        b->stream);
   hipError_t ee = hipStreamEndCapture(b->stream, &b->graph);
   if (ce != hipSuccess) return fail(set_err(ctx, JL_EHIP, "batched capture failed: %s", hipGetErrorString(ce)));
   if (ee != hipSuccess) return fail(set_err(ctx, JL_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ee)));
   BCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
 #undef BCHK
   *out = b;
+  return JL_OK;
+}
+
+jl_status jl_batch_shape_used(jl_batch b, jl_batch_shape* shape) {
+  if (!b || !shape) return set_err(b ? b->ctx : nullptr, JL_EINVAL, "batch and shape are required");
+  *shape = b->shape;
   return JL_OK;
 }
 
@@ -209,10 +232,11 @@ jl_status jl_batch_run(jl_batch b, double* evals, double* res, int32_t* status,
     status[i] = h_status[i] == 0 ? JL_OK : (h_status[i] == 2 ? JL_BREAKDOWN : JL_NOT_CONVERGED);
     all = all && h_status[i] == 0;
     if (stats) {
-      stats[i].cycles = h_stats[4 * i];
-      stats[i].n_mv = h_stats[4 * i + 1];
-      stats[i].gs_passes = h_stats[4 * i + 2];
-      stats[i].icnv = h_stats[4 * i + 3];
+      stats[i].cycles = h_stats[kBatchStats * i];
+      stats[i].n_mv = h_stats[kBatchStats * i + 1];
+      stats[i].gs_passes = h_stats[kBatchStats * i + 2];
+      stats[i].icnv = h_stats[kBatchStats * i + 3];
+      stats[i].n_resid = h_stats[kBatchStats * i + 4];
     }
   }
   return all ? JL_OK : JL_NOT_CONVERGED;

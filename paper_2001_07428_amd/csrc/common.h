@@ -199,6 +199,10 @@ hipError_t launch_fill(cplx<S>* u, int64_t n, double value, hipStream_t st);
 template <typename S>
 hipError_t launch_pair(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t ldy, int64_t h, int k,
                        hipStream_t st);
+// Y[:, pairs[2 i]] = X[:, pairs[2 i + 1]] for i < npairs (pairs on the device).
+template <typename S>
+hipError_t launch_copy_pairs(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t ldy, int64_t n,
+                             const int* pairs, int npairs, hipStream_t st);
 // copy k columns of length n between column-major blocks.
 template <typename S>
 hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t ldy, int64_t n,
@@ -235,13 +239,14 @@ hipError_t launch_norm2(const cplx<S>* x, int64_t n, double* part, hipStream_t s
 // ------------------------------------------------------------ restart GEMM
 // C (M x N, ldc) = A (M x K, lda) * B (K x N, ldb), real, column-major; A
 // and C of storage type S, B and the MFMA accumulation of type T
-// (instantiated: <float,double>, <double,double>).
+// (instantiated: <float,double>, <double,double>).  With cmap (device, N
+// ints) column c of the product is stored to column cmap[c] of C.
 // Column tile of the GEMM (a launch computing N columns covers
 // ceil(N / kGemmTileN) tiles per row panel).
 constexpr int kGemmTileN = 128;
 template <typename S, typename T>
 hipError_t launch_gemm_nn(const S* A, int64_t lda, const T* B, int64_t ldb, S* C, int64_t ldc,
-                          int64_t M, int N, int K, hipStream_t st);
+                          int64_t M, int N, int K, hipStream_t st, const int* cmap = nullptr);
 
 // ------------------------------------------------------- Ritz eigenproblem
 // Symmetric eigen-decomposition of an m x m FP64 matrix by parallel cyclic
@@ -290,23 +295,28 @@ struct BatchProblem {
 };
 struct BatchParams {
   int nev, m, mwin, which, max_cycles, max_passes, min_passes, tol_relative;
+  int lds_mat;        // LDS bytes per workgroup for a resident [A11 A12] (0: none)
   double tol;
 };
+constexpr int kBatchStats = 5;   // per-problem counters of the batched solve
 struct BatchOut {
   double* evals;      // [count][nev]
   double* res;        // [count][nev]
   int* status;        // [count]
-  int* stats;         // [count][4]: cycles, n_mv, gs_passes, icnv
+  int* stats;         // [count][kBatchStats]: cycles, n_mv, gs_passes, icnv, n_resid
 };
-size_t batched_lds_bytes(int64_t hmax, int m, int es);
+size_t batched_lds_bytes(int64_t hmax, int m, int es);   // without the resident-matrix budget
 size_t batched_slot_bytes(int64_t hmax, int m, int es);
 hipError_t launch_batched_init(int* queue, hipStream_t st);
 // One persistent launch of `blocks` workgroups of `threads` (128/256/512)
 // threads; each pops ids (in the given order) from *queue and solves them.
+// rpw (1, 2) rows per wavefront and unr (4, 8) column steps in flight in the
+// operator apply; P.lds_mat bytes of LDS per workgroup hold the matrix of a
+// problem that fits.
 template <typename S>
 hipError_t launch_batched(const BatchProblem* probs, const int* order, int count,
                           const BatchParams& P, int* queue, char* slots, size_t slot_bytes,
-                          int64_t hmax, const BatchOut& out, int threads, int blocks,
-                          hipStream_t st);
+                          int64_t hmax, const BatchOut& out, int threads, int rpw, int unr,
+                          int blocks, hipStream_t st);
 
 }  // namespace jl

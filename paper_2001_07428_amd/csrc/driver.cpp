@@ -264,7 +264,7 @@ double op_bytes(const jl_op_s* op, int es) {
 
 // ----------------------------------------------------------- workspace layout
 struct Layout {
-  size_t V[2], apart, dots_part, upd_part, coef, scal, Tdev, ritz, lam_s, Zs, zlast, res_part,
+  size_t V[2], apart, dots_part, upd_part, coef, scal, Tdev, ritz, lam_s, Zs, Zg, gmap, zlast, res_part,
       res_out, res_lam, res_cols, cg_vec[5], cg_part, cg_s, rloc, rd, wide_scr, wide_cnt, total;
 };
 
@@ -295,6 +295,8 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   L.ritz = take(sizeof(double) * ritz_scratch_doubles(m));
   L.lam_s = take(sizeof(double) * m);
   L.Zs = take(sizeof(double) * (size_t)m * m);
+  L.Zg = take(sizeof(double) * (size_t)m * m);          // gathered columns of Z for the basis update
+  L.gmap = take(sizeof(int) * 3 * (size_t)m);           // its output columns, then copy pairs
   L.zlast = take(sizeof(double) * m);
   L.res_part = take(sizeof(double) * (size_t)op_resid_blocks(op) * p->nev);
   L.res_out = take(sizeof(double) * p->nev);
@@ -470,6 +472,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   double* ritz_scr = reinterpret_cast<double*>(base + L.ritz);
   double* lam_s = reinterpret_cast<double*>(base + L.lam_s);
   double* Zs = reinterpret_cast<double*>(base + L.Zs);
+  double* Zg = reinterpret_cast<double*>(base + L.Zg);
+  int* gmap = reinterpret_cast<int*>(base + L.gmap);
   double* zlast = reinterpret_cast<double*>(base + L.zlast);
   double* res_part = reinterpret_cast<double*>(base + L.res_part);
   double* res_dev = reinterpret_cast<double*>(base + L.res_out);
@@ -505,7 +509,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   } ev_copy;
   JL_HIP(ctx, hipEventCreateWithFlags(&ev_copy.e, hipEventDisableTiming));
   Pinned pin;
-  const size_t pin_doubles = 16 + CG_NSLOTS + 3 * (size_t)m + 3 * (size_t)nev;
+  const size_t pin_doubles = 16 + CG_NSLOTS + 3 * (size_t)m + 3 * (size_t)nev + 2 * (size_t)m * m +
+                             2 * (size_t)m;
   JL_HIP(ctx, hipHostMalloc((void**)&pin.p, sizeof(double) * pin_doubles, hipHostMallocDefault));
   // Every return waits for the stream first (an error can leave queued work,
   // such as the next step's speculative apply); declared after `pin`, so the
@@ -521,6 +526,9 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   double* h_res = h_zl + m;              // [nev]
   double* h_rlam = h_res + nev;          // [nev]
   int* h_rcols = reinterpret_cast<int*>(h_rlam + nev);   // [nev] ints (fits in nev doubles)
+  double* h_Z = h_rlam + 2 * (size_t)nev;                 // [m * m] the sorted Z of the cycle
+  double* h_Zg = h_Z + (size_t)m * m;                     // [m * m] its gathered columns
+  int* h_gmap = reinterpret_cast<int*>(h_Zg + (size_t)m * m);   // [3 m] ints
 
   Timer tm;
   tm.on = prm->timing != 0;
@@ -556,6 +564,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   const double sqrt2 = std::sqrt(2.0);
   jl_status status = JL_NOT_CONVERGED;
   int icnv = 0;
+  int64_t n_locked = 0;   // Ritz vectors copied rather than formed by the GEMM
   std::vector<int> out_order;
 
   // Invert mode: u = A^-1 b by CG on the device, then t_jj = b^H u into
@@ -749,17 +758,55 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     }
     // ================= Rayleigh-Ritz: T_m = Z Lambda Z^T, sort (Alg. 1)
     const int kcols = std::min(kmax, meff);
-    // Ritz vectors [c0, c1) of V_m Z (real GEMM on the interleaved basis)
+    // Ritz vectors [c0, c1) of V_m Z (real GEMM on the interleaved basis).  A
+    // column of Z that is exactly a unit vector e_i (a converged pair locked by
+    // its zero coupling, deflated exactly by the Ritz step) gives v_i itself:
+    // it is copied (the product would produce the same bits).  The other
+    // columns go through the GEMM, gathered when some are left out.
     auto basis_gemm = [&](int c0, int c1) -> jl_status {
       if (c1 <= c0) return JL_OK;
+      int ng = 0, np = 0;
+      int* pairs = h_gmap + m;
+      for (int c = c0; c < c1; ++c) {
+        const double* z = h_Z + (size_t)c * meff;
+        int src = -1;
+        for (int i = 0; i < meff && src != -2; ++i)
+          if (z[i] != 0.0) src = (src == -1 && z[i] == 1.0) ? i : -2;
+        if (src >= 0) {
+          pairs[2 * np] = c;
+          pairs[2 * np + 1] = src;
+          ++np;
+        } else {
+          h_gmap[ng++] = c;
+        }
+      }
       tm.start(Timer::GEMM);
-      JL_HIP(ctx, (launch_gemm_nn<S, double>)(reinterpret_cast<const S*>(V), 2 * ldv,
-                                            Zs + (size_t)c0 * meff, meff,
-                                            reinterpret_cast<S*>(Vn + (int64_t)c0 * ldv), 2 * ldv,
-                                            2 * n, c1 - c0, meff, st));
+      if (ng == c1 - c0) {   // no locked column: the contiguous product
+        JL_HIP(ctx, (launch_gemm_nn<S, double>)(reinterpret_cast<const S*>(V), 2 * ldv,
+                                              Zs + (size_t)c0 * meff, meff, reinterpret_cast<S*>(Vn + (int64_t)c0 * ldv),
+                                              2 * ldv, 2 * n, ng, meff, st));
+      } else {
+        const int goff = c0;   // the two calls of a cycle use disjoint parts of the scratch
+        double* hz = h_Zg + (size_t)goff * meff;
+        for (int j = 0; j < ng; ++j)
+          std::copy(h_Z + (size_t)h_gmap[j] * meff, h_Z + (size_t)(h_gmap[j] + 1) * meff,
+                    hz + (size_t)j * meff);
+        if (ng > 0) {
+          JL_HIP(ctx, hipMemcpyAsync(Zg + (size_t)goff * meff, hz, sizeof(double) * (size_t)ng * meff,
+                                     hipMemcpyHostToDevice, st));
+          JL_HIP(ctx, hipMemcpyAsync(gmap + goff, h_gmap, sizeof(int) * ng, hipMemcpyHostToDevice, st));
+          JL_HIP(ctx, (launch_gemm_nn<S, double>)(reinterpret_cast<const S*>(V), 2 * ldv,
+                                                Zg + (size_t)goff * meff, meff, reinterpret_cast<S*>(Vn),
+                                                2 * ldv, 2 * n, ng, meff, st, gmap + goff));
+        }
+        JL_HIP(ctx, hipMemcpyAsync(gmap + m + 2 * goff, pairs, sizeof(int) * 2 * np,
+                                   hipMemcpyHostToDevice, st));
+        JL_HIP(ctx, launch_copy_pairs<S>(V, ldv, Vn, ldv, n, gmap + m + 2 * goff, np, st));
+      }
       tm.stop();
       S_.n_gemm_launch++;
-      S_.flops_gemm += 2.0 * (double)(2 * n) * (c1 - c0) * meff;
+      S_.flops_gemm += 2.0 * (double)(2 * n) * ng * meff;
+      n_locked += np;
       return JL_OK;
     };
     // the nev candidates of the convergence check first (rounded up to the
@@ -793,6 +840,9 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     JL_HIP(ctx, hipMemcpyAsync(h_lam, lam_s, sizeof(double) * meff, hipMemcpyDeviceToHost, st));
     JL_HIP(ctx, hipMemcpyAsync(h_zl, zlast, sizeof(double) * meff, hipMemcpyDeviceToHost, st));
     tm.stop();
+    // the kept columns of Z, to find the locked ones before the basis update
+    JL_HIP(ctx, hipMemcpyAsync(h_Z, Zs, sizeof(double) * (size_t)meff * kcols, hipMemcpyDeviceToHost, st));
+    JL_HIP(ctx, hipStreamSynchronize(st));
     // ================= V_k := V_m Z[:, 0:k] (Alg. 1), candidates first
     {
       const jl_status gs = basis_gemm(0, kfirst);
@@ -873,8 +923,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     if (prm->verbose) {
       double worst = 0.0;
       for (int i = 0; i < nev; ++i) worst = std::max(worst, est[i]);
-      fprintf(stderr, "[jlanczos] cycle %d k %d m %d icnv %d/%d max res_est %.2e n_mv %d t %.2fs\n",
-              cycle + 1, k, meff, icnv, nev, worst, S_.n_mv,
+      fprintf(stderr, "[jlanczos] cycle %d k %d m %d icnv %d/%d max res_est %.2e n_mv %d locked %lld t %.2fs\n",
+              cycle + 1, k, meff, icnv, nev, worst, S_.n_mv, (long long)n_locked,
               std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count());
       fflush(stderr);
     }

@@ -11,7 +11,7 @@
 //                   sqrt(2) test on the norms, as in the stand-alone solver;
 //   Rayleigh-Ritz   parallel cyclic Jacobi on T in LDS (FP64) and a rank sort;
 //   restart         V Z[:, :k] with FP64 accumulation;
-//   residuals       FP64-accumulated apply of each candidate.
+//   residuals       FP64-accumulated applies, two candidates per pass over A.
 // The basis lives in a per-workgroup slot of the workspace; vectors being
 // worked on, T, the Jacobi matrices and all scalars live in LDS.  Control
 // decisions are taken by every thread from the same LDS values, so the
@@ -56,11 +56,12 @@ template <typename S> struct Lds {
   double* rc; double* rs; double* rt;   // mp/2 rotations
   double* red;      // 16
   double* resv;     // m
-  double* misc;     // 16 scalars
+  double* misc;     // 32 scalars
   int* perm;        // mp
   int* pq;          // mp (pair table of a Jacobi round)
   int* conv;        // m
   int* order;       // m
+  cplx<S>* mat;     // [A11 A12] of a problem that fits BatchParams::lds_mat bytes (h x h each)
 };
 
 template <typename S>
@@ -69,7 +70,7 @@ __host__ __device__ inline size_t lds_bytes(int64_t hmax, int m) {
   size_t b = 0;
   b += 2 * 2 * (size_t)hmax * sizeof(cplx<S>);
   b += sizeof(double) * ((size_t)(m + 1) * m + 2 * (size_t)mp * mp + 4 * (m + 1) + 2 + 2 * mp +
-                         3 * (mp / 2) + 16 + m + 16);
+                         3 * (mp / 2) + 16 + m + 32);
   b += sizeof(int) * (2 * (size_t)mp + 2 * m);
   return b + 64;
 }
@@ -92,20 +93,23 @@ __device__ inline Lds<S> carve(char* base, int64_t hmax, int m) {
   L.rt = d; d += mp / 2;
   L.red = d; d += 16;
   L.resv = d; d += m;
-  L.misc = d; d += 16;
+  L.misc = d; d += 32;
   int* ip = reinterpret_cast<int*>(d);
   L.perm = ip; ip += mp;
   L.pq = ip; ip += mp;
   L.conv = ip; ip += m;
   L.order = ip;
+  L.mat = reinterpret_cast<cplx<S>*>(base + ((lds_bytes<S>(hmax, m) + 15) & ~size_t(15)));
   return L;
 }
 
-// y = A x (RESID = false; returns t = x^H y in *t_re, *t_im) or the squared
-// residual ||A x - lam x||^2 (RESID = true; C should be double).
-template <typename S, typename C, int NT, bool RESID>
+// y = A x; returns t = x^H y in *t_re, *t_im.  Each wavefront takes RPW
+// rows at a time (they share the operand reads from LDS) and every lane
+// issues the matrix loads of UNR column steps before their products (the
+// tile knobs the autotuner picks per batch).
+template <typename S, typename C, int NT, int RPW, int UNR>
 __device__ void wg_apply(const BatchProblem& pb, const cplx<S>* __restrict__ x, cplx<S>* __restrict__ y,
-                         const Lds<S>& L, double lamv, double* t_re, double* t_im) {
+                         const Lds<S>& L, double* t_re, double* t_im) {
   const int64_t h = pb.h;
   const cplx<S>* A11 = static_cast<const cplx<S>*>(pb.A11);
   const cplx<S>* A12 = static_cast<const cplx<S>*>(pb.A12);
@@ -113,51 +117,71 @@ __device__ void wg_apply(const BatchProblem& pb, const cplx<S>* __restrict__ x, 
   __syncthreads();
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   double are = 0.0, aim = 0.0;
-  for (int64_t r = w; r < h; r += NT / 64) {
-    const cplx<S>* r11 = A11 + r * pb.ld;
-    const cplx<S>* r12 = A12 + r * pb.ld;
-    cx2<C> p{0, 0}, q{0, 0};
-    auto acc = [&](const cplx<S>& m11, const cplx<S>& m12, int64_t c) {
-      const cplx<S> a = L.sv[c], b = L.sv[h + c];
+  for (int64_t r0 = (int64_t)w * RPW; r0 < h; r0 += (int64_t)(NT / 64) * RPW) {
+    const cplx<S>* r11[RPW];
+    const cplx<S>* r12[RPW];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {   // rows past the end repeat the last row; not stored
+      const int64_t r = r0 + k < h ? r0 + k : h - 1;
+      r11[k] = A11 + r * pb.ld;
+      r12[k] = A12 + r * pb.ld;
+    }
+    cx2<C> p[RPW], q[RPW];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) p[k] = q[k] = cx2<C>{0, 0};
+    auto acc = [&](const cplx<S>& m11, const cplx<S>& m12, const cplx<S>& a, const cplx<S>& b,
+                   cx2<C>& pp, cx2<C>& qq) {
       const C m11r = m11.x, m11i = m11.y, m12r = m12.x, m12i = m12.y;
       const C ar = a.x, ai = a.y, br = b.x, bi = b.y;
       // p += A11 a + A12 b
-      p.re += m11r * ar - m11i * ai + m12r * br - m12i * bi;
-      p.im += m11r * ai + m11i * ar + m12r * bi + m12i * br;
+      pp.re += m11r * ar - m11i * ai + m12r * br - m12i * bi;
+      pp.im += m11r * ai + m11i * ar + m12r * bi + m12i * br;
       // q += A11 conj(b) - A12 conj(a)
-      q.re += m11r * br + m11i * bi - m12r * ar - m12i * ai;
-      q.im += -m11r * bi + m11i * br + m12r * ai - m12i * ar;
+      qq.re += m11r * br + m11i * bi - m12r * ar - m12i * ai;
+      qq.im += -m11r * bi + m11i * br + m12r * ai - m12i * ar;
     };
     int64_t c = lane;
-    for (; c + 3 * 64 < h; c += 4 * 64) {   // four steps' loads in flight together
-      cplx<S> m11[4], m12[4];
+    for (; c + (UNR - 1) * 64 < h; c += UNR * 64) {   // UNR steps' loads in flight together
+      cplx<S> m11[RPW][UNR], m12[RPW][UNR];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        m11[k] = r11[c + 64 * k];
-        m12[k] = r12[c + 64 * k];
-      }
+      for (int k = 0; k < RPW; ++k)
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          m11[k][u] = r11[k][c + 64 * u];
+          m12[k][u] = r12[k][c + 64 * u];
+        }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc(m11[k], m12[k], c + 64 * k);
-    }
-    for (; c < h; c += 64) acc(r11[c], r12[c], c);
+      for (int u = 0; u < UNR; ++u) {
+        const cplx<S> a = L.sv[c + 64 * u], b = L.sv[h + c + 64 * u];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      p.re += __shfl_xor(p.re, o);
-      p.im += __shfl_xor(p.im, o);
-      q.re += __shfl_xor(q.re, o);
-      q.im += __shfl_xor(q.im, o);
+        for (int k = 0; k < RPW; ++k) acc(m11[k][u], m12[k][u], a, b, p[k], q[k]);
+      }
+    }
+    for (; c < h; c += 64) {
+      const cplx<S> a = L.sv[c], b = L.sv[h + c];
+#pragma unroll
+      for (int k = 0; k < RPW; ++k) acc(r11[k][c], r12[k][c], a, b, p[k], q[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        p[k].re += __shfl_xor(p[k].re, o);
+        p[k].im += __shfl_xor(p[k].im, o);
+        q[k].re += __shfl_xor(q[k].re, o);
+        q[k].im += __shfl_xor(q[k].im, o);
+      }
     }
     if (lane == 0) {
-      const cplx<S> xt = L.sv[r], xb = L.sv[h + r];
-      if constexpr (RESID) {
-        const double tr = (double)p.re - lamv * xt.x, ti = (double)p.im - lamv * xt.y;
-        const double br2 = (double)q.re - lamv * xb.x, bi2 = -(double)q.im - lamv * xb.y;
-        are += tr * tr + ti * ti + br2 * br2 + bi2 * bi2;
-      } else {
+#pragma unroll
+      for (int k = 0; k < RPW; ++k) {
+        const int64_t r = r0 + k;
+        if (r >= h) break;
+        const cplx<S> xt = L.sv[r], xb = L.sv[h + r];
         cplx<S> ut, ub;
-        ut.x = (S)p.re; ut.y = (S)p.im;
-        ub.x = (S)q.re; ub.y = (S)(-q.im);   // u_bot = conj(q)
+        ut.x = (S)p[k].re; ut.y = (S)p[k].im;
+        ub.x = (S)q[k].re; ub.y = (S)(-q[k].im);   // u_bot = conj(q)
         y[r] = ut;
         y[h + r] = ub;
         are += (double)xt.x * ut.x + (double)xt.y * ut.y + (double)xb.x * ub.x + (double)xb.y * ub.y;
@@ -166,7 +190,88 @@ __device__ void wg_apply(const BatchProblem& pb, const cplx<S>* __restrict__ x, 
     }
   }
   *t_re = wg_sum<NT>(are, L.red);
-  if (!RESID) *t_im = wg_sum<NT>(aim, L.red);
+  *t_im = wg_sum<NT>(aim, L.red);
+}
+
+// Squared true residuals ||A x_k - lam_k x_k||^2 of nc <= kResRhs candidates
+// x_k = X + idx[k] * n in one pass over [A11 A12] (the operator is read once
+// per kResRhs candidates, not once per candidate): the lanes of a wavefront
+// split as 4 rows x 16 column groups (128 contiguous bytes of a row per load
+// in FP32), each lane applies its row's entries to every candidate (the
+// candidates are read through the caches, the 4 row lanes of a column group at
+// one address), FP64 products and accumulation; the column groups are summed
+// by four butterfly steps.  r2[k] (LDS) receives the sums.  Two candidates
+// per pass keep the solver's register count (and so its occupancy) where it
+// was: four cost 50 more registers.
+constexpr int kResRhs = 2;
+template <typename S, int NT>
+__device__ void wg_resid_multi(const BatchProblem& pb, const cplx<S>* __restrict__ X, int64_t n,
+                               const int* idx, const double* lamv, int nc, const Lds<S>& L,
+                               double* r2) {
+  const int64_t h = pb.h;
+  const cplx<S>* A11 = static_cast<const cplx<S>*>(pb.A11);
+  const cplx<S>* A12 = static_cast<const cplx<S>*>(pb.A12);
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64, ri = lane >> 4, g = lane & 15;
+  const cplx<S>* xk[kResRhs];
+  double lk[kResRhs];
+#pragma unroll
+  for (int k = 0; k < kResRhs; ++k) {
+    xk[k] = X + (int64_t)idx[k < nc ? k : 0] * n;
+    lk[k] = k < nc ? lamv[k] : 0.0;
+  }
+  double acc[kResRhs];
+#pragma unroll
+  for (int k = 0; k < kResRhs; ++k) acc[k] = 0.0;
+  for (int64_t rb = (int64_t)w * 4; rb < h; rb += (int64_t)(NT / 64) * 4) {
+    const int64_t r = rb + ri;
+    const bool rok = r < h;
+    const cplx<S>* r11 = A11 + (rok ? r : h - 1) * pb.ld;
+    const cplx<S>* r12 = A12 + (rok ? r : h - 1) * pb.ld;
+    double pr[kResRhs], pi[kResRhs], qr[kResRhs], qi[kResRhs];
+#pragma unroll
+    for (int k = 0; k < kResRhs; ++k) pr[k] = pi[k] = qr[k] = qi[k] = 0.0;
+    for (int64_t c = g; c < h; c += 16) {
+      const cplx<S> m11 = r11[c], m12 = r12[c];
+      const double m11r = m11.x, m11i = m11.y, m12r = m12.x, m12i = m12.y;
+#pragma unroll
+      for (int k = 0; k < kResRhs; ++k) {
+        if (k >= nc) break;   // uniform
+        const cplx<S> a = xk[k][c], b = xk[k][h + c];
+        const double ar = a.x, ai = a.y, br = b.x, bi = b.y;
+        // p += A11 a + A12 b;  q += A11 conj(b) - A12 conj(a)
+        pr[k] += m11r * ar - m11i * ai + m12r * br - m12i * bi;
+        pi[k] += m11r * ai + m11i * ar + m12r * bi + m12i * br;
+        qr[k] += m11r * br + m11i * bi - m12r * ar - m12i * ai;
+        qi[k] += -m11r * bi + m11i * br + m12r * ai - m12i * ar;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kResRhs; ++k) {
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        pr[k] += __shfl_xor(pr[k], o); pi[k] += __shfl_xor(pi[k], o);
+        qr[k] += __shfl_xor(qr[k], o); qi[k] += __shfl_xor(qi[k], o);
+      }
+    }
+    if (g == 0 && rok) {
+#pragma unroll
+      for (int k = 0; k < kResRhs; ++k) {
+        if (k >= nc) break;
+        const cplx<S> xt = xk[k][r], xb = xk[k][h + r];
+        const double tr = pr[k] - lk[k] * xt.x, ti = pi[k] - lk[k] * xt.y;
+        const double br = qr[k] - lk[k] * xb.x, bi = -qi[k] - lk[k] * xb.y;   // u_bot = conj(q)
+        acc[k] += tr * tr + ti * ti + br * br + bi * bi;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kResRhs; ++k) {
+    if (k < nc) {   // uniform
+      const double t = wg_sum<NT>(acc[k], L.red);
+      if (threadIdx.x == 0) r2[k] = t;
+    }
+  }
+  __syncthreads();
 }
 
 // First half of a Gram-Schmidt pass: optional local step on u (stored back),
@@ -275,11 +380,26 @@ __device__ double wg_update(const cplx<S>* __restrict__ V, int64_t n, int ncol,
   return wg_sum<NT>(nrm, L.red);
 }
 
-template <typename S, int NT>
-__device__ void solve_one(const BatchProblem& pb, int pid, const BatchParams& P, char* slot,
+template <typename S, int NT, int RPW, int UNR>
+__device__ void solve_one(const BatchProblem& pg, int pid, const BatchParams& P, char* slot,
                           const Lds<S>& L, const BatchOut& out) {
-  const int64_t h = pb.h, n = 2 * h;
+  const int64_t h = pg.h, n = 2 * h;
   const int m = P.m, nev = P.nev, mwin = P.mwin, tid = threadIdx.x;
+  // a matrix that fits the launch's LDS budget is read from LDS for the whole solve
+  BatchProblem pb = pg;
+  if ((size_t)2 * h * h * sizeof(cplx<S>) <= (size_t)P.lds_mat) {
+    const cplx<S>* A11 = static_cast<const cplx<S>*>(pg.A11);
+    const cplx<S>* A12 = static_cast<const cplx<S>*>(pg.A12);
+    for (int64_t i = tid; i < h * h; i += NT) {
+      const int64_t r = i / h, c = i - r * h;
+      L.mat[i] = A11[r * pg.ld + c];
+      L.mat[h * h + i] = A12[r * pg.ld + c];
+    }
+    pb.A11 = L.mat;
+    pb.A12 = L.mat + h * h;
+    pb.ld = h;
+    __syncthreads();
+  }
   const int kmax = min(nev + mwin, m - 1);
   const double uround = sizeof(S) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
   cplx<S>* Vb[2] = {reinterpret_cast<cplx<S>*>(slot), reinterpret_cast<cplx<S>*>(slot) + (size_t)(m + 1) * n};
@@ -295,7 +415,7 @@ __device__ void solve_one(const BatchProblem& pb, int pid, const BatchParams& P,
   for (int i = tid; i < (m + 1) * m; i += NT) L.T[i] = 0.0;
   __syncthreads();
   auto Tat = [&](int i, int j) -> double& { return L.T[i + j * (m + 1)]; };
-  int k = 0, icnv = 0, status = 1, n_mv = 0, passes_tot = 0, cycles = 0;
+  int k = 0, icnv = 0, status = 1, n_mv = 0, passes_tot = 0, cycles = 0, n_resid = 0;
   double maxT = 0.0, tol_scale = 0.0;
   const double sqrt2 = 1.4142135623730951;
   for (int cycle = 0; cycle < P.max_cycles; ++cycle) {
@@ -307,7 +427,7 @@ __device__ void solve_one(const BatchProblem& pb, int pid, const BatchParams& P,
     for (int j = k; j < m; ++j) {
       cplx<S>* u = V + (int64_t)(j + 1) * n;
       double tre, tim;
-      wg_apply<S, S, NT, false>(pb, V + (int64_t)j * n, u, L, 0.0, &tre, &tim);
+      wg_apply<S, S, NT, RPW, UNR>(pb, V + (int64_t)j * n, u, L, &tre, &tim);
       ++n_mv;
       const double beta_prev = (j > k) ? Tat(j, j - 1) : 0.0;
       wg_dots<S, NT>(V, n, j + 1, u, h, L, true, tre, tim, beta_prev, j);
@@ -374,40 +494,70 @@ __device__ void solve_one(const BatchProblem& pb, int pid, const BatchParams& P,
       L.svec[r] = beta_m * L.JZ[(meff - 1) + src * mp];
     }
     __syncthreads();
-    // ---- V_k := V_m Z[:, perm[0:kcols]], FP64 accumulation
+    // ---- V_k := V_m Z[:, perm[0:kcols]], FP64 accumulation, four output
+    // columns per read of V
     const int kcols = min(kmax, meff);
+    constexpr int CB = 4;
     for (int64_t e = tid; e < n; e += NT) {
-      for (int c = 0; c < kcols; ++c) {
-        const int src = L.perm[c];
-        double ar = 0.0, ai = 0.0;
+      for (int c0 = 0; c0 < kcols; c0 += CB) {
+        double ar[CB], ai[CB];
+        int src[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          ar[c] = ai[c] = 0.0;
+          src[c] = L.perm[c0 + c < kcols ? c0 + c : c0];
+        }
         for (int i = 0; i < meff; ++i) {
           const cplx<S> v = V[(int64_t)i * n + e];
-          const double z = L.JZ[i + src * mp];
-          ar += (double)v.x * z;
-          ai += (double)v.y * z;
+          const double vr = v.x, vi = v.y;
+#pragma unroll
+          for (int c = 0; c < CB; ++c) {
+            const double z = L.JZ[i + src[c] * mp];
+            ar[c] += vr * z;
+            ai[c] += vi * z;
+          }
         }
-        cplx<S> o;
-        o.x = (S)ar; o.y = (S)ai;
-        Vn[(int64_t)c * n + e] = o;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          if (c0 + c < kcols) {
+            cplx<S> o;
+            o.x = (S)ar[c]; o.y = (S)ai[c];
+            Vn[(int64_t)(c0 + c) * n + e] = o;
+          }
+        }
       }
     }
     __syncthreads();
     // ---- true residuals of the candidates
     tol_scale = fmax(tol_scale, fmax(fabs(L.lam[0]), fabs(L.lam[meff - 1])));
     const double tolc = P.tol_relative ? P.tol * tol_scale : P.tol;
-    for (int i = 0; i < nev; ++i) {
-      double r2 = INFINITY;
-      if (fabs(L.svec[i]) < tolc) {
-        double dummy;
-        wg_apply<S, double, NT, true>(pb, Vn + (int64_t)i * n, nullptr, L, L.lam[i], &r2, &dummy);
-        r2 = sqrt(r2);
+    // candidates (est < tol) in chunks of kResRhs, each chunk one pass over A
+    if (tid == 0) {
+      int nc = 0;
+      for (int i = 0; i < nev; ++i) {
+        L.resv[i] = INFINITY;
+        L.conv[i] = 0;
+        if (fabs(L.svec[i]) < tolc) L.order[nc++] = i;   // L.order: candidate list for now
       }
-      if (tid == 0) {
-        L.resv[i] = r2;
-        L.conv[i] = r2 < tolc ? 1 : 0;
-      }
+      L.misc[0] = nc;
     }
     __syncthreads();
+    const int ncand = (int)L.misc[0];
+    n_resid += ncand;
+    for (int c0 = 0; c0 < ncand; c0 += kResRhs) {
+      const int nc = min(kResRhs, ncand - c0);
+      double* r2 = L.misc + 16;   // kResRhs scalars
+      if (tid < nc) L.misc[1 + tid] = L.lam[L.order[c0 + tid]];   // slots 1..kResRhs
+      __syncthreads();
+      wg_resid_multi<S, NT>(pb, Vn, n, L.order + c0, L.misc + 1, nc, L, r2);
+      if (tid < nc) {
+        const int i = L.order[c0 + tid];
+        const double r = sqrt(r2[tid]);
+        L.resv[i] = r;
+        L.conv[i] = r < tolc ? 1 : 0;
+      }
+      __syncthreads();
+    }
     icnv = 0;
     for (int i = 0; i < nev; ++i) icnv += L.conv[i];
     if (tid == 0) {
@@ -460,16 +610,25 @@ __device__ void solve_one(const BatchProblem& pb, int pid, const BatchParams& P,
   }
   if (tid == 0) {
     out.status[pid] = status == 0 ? 0 : (status == 2 ? 2 : 1);
-    out.stats[4 * pid + 0] = cycles;
-    out.stats[4 * pid + 1] = n_mv;
-    out.stats[4 * pid + 2] = passes_tot;
-    out.stats[4 * pid + 3] = icnv;
+    out.stats[kBatchStats * pid + 0] = cycles;
+    out.stats[kBatchStats * pid + 1] = n_mv;
+    out.stats[kBatchStats * pid + 2] = passes_tot;
+    out.stats[kBatchStats * pid + 3] = icnv;
+    out.stats[kBatchStats * pid + 4] = n_resid;
   }
   __syncthreads();
 }
 
-template <typename S, int NT>
-__global__ __launch_bounds__(NT) void k_batched(const BatchProblem* __restrict__ probs,
+// Launch bounds: with 256 threads and the smallest apply tile, three
+// workgroups (three wavefronts per SIMD) per compute unit; the FP64 solver's
+// register count sits just above that limit otherwise.  The larger tiles keep
+// their registers.
+template <int NT, int RPW, int UNR> constexpr int batched_min_blocks() {
+  return (NT == 256 && RPW * UNR == 4) ? 3 : 1;
+}
+
+template <typename S, int NT, int RPW, int UNR>
+__global__ __launch_bounds__(NT, (batched_min_blocks<NT, RPW, UNR>())) void k_batched(const BatchProblem* __restrict__ probs,
                                                 const int* __restrict__ order, int count,
                                                 BatchParams P, int* queue, char* slots,
                                                 size_t slot_bytes, int64_t hmax, BatchOut out) {
@@ -484,7 +643,7 @@ __global__ __launch_bounds__(NT) void k_batched(const BatchProblem* __restrict__
     __syncthreads();
     if (q >= count) break;
     const int pid = order[q];
-    solve_one<S, NT>(probs[pid], pid, P, slot, L, out);
+    solve_one<S, NT, RPW, UNR>(probs[pid], pid, P, slot, L, out);
   }
 }
 
@@ -492,20 +651,35 @@ __global__ void k_batched_init(int* queue) {
   if (threadIdx.x == 0) queue[0] = 0;
 }
 
-template <typename S, int NT>
+template <typename S, int NT, int RPW, int UNR>
 hipError_t launch_nt(const BatchProblem* probs, const int* order, int count, const BatchParams& P,
                      int* queue, char* slots, size_t slot_bytes, int64_t hmax, const BatchOut& out,
                      int blocks, hipStream_t st) {
-  const size_t lds = lds_bytes<S>(hmax, P.m);
-  hipLaunchKernelGGL((k_batched<S, NT>), dim3(blocks), dim3(NT), lds, st, probs, order, count, P,
-                     queue, slots, slot_bytes, hmax, out);
+  const size_t lds = ((lds_bytes<S>(hmax, P.m) + 15) & ~size_t(15)) + (size_t)P.lds_mat;
+  hipLaunchKernelGGL((k_batched<S, NT, RPW, UNR>), dim3(blocks), dim3(NT), lds, st, probs, order, count,
+                     P, queue, slots, slot_bytes, hmax, out);
   return hipGetLastError();
+}
+
+template <typename S, int NT>
+hipError_t launch_tile(const BatchProblem* probs, const int* order, int count, const BatchParams& P,
+                       int* queue, char* slots, size_t slot_bytes, int64_t hmax, const BatchOut& out,
+                       int rpw, int unr, int blocks, hipStream_t st) {
+  if (rpw == 1 && unr == 4)
+    return launch_nt<S, NT, 1, 4>(probs, order, count, P, queue, slots, slot_bytes, hmax, out, blocks, st);
+  if (rpw == 1 && unr == 8)
+    return launch_nt<S, NT, 1, 8>(probs, order, count, P, queue, slots, slot_bytes, hmax, out, blocks, st);
+  if (rpw == 2 && unr == 4)
+    return launch_nt<S, NT, 2, 4>(probs, order, count, P, queue, slots, slot_bytes, hmax, out, blocks, st);
+  if (rpw == 2 && unr == 8)
+    return launch_nt<S, NT, 2, 8>(probs, order, count, P, queue, slots, slot_bytes, hmax, out, blocks, st);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 size_t batched_lds_bytes(int64_t hmax, int m, int es) {
-  return es == 8 ? lds_bytes<float>(hmax, m) : lds_bytes<double>(hmax, m);
+  return ((es == 8 ? lds_bytes<float>(hmax, m) : lds_bytes<double>(hmax, m)) + 15) & ~size_t(15);
 }
 
 size_t batched_slot_bytes(int64_t hmax, int m, int es) {
@@ -520,22 +694,22 @@ hipError_t launch_batched_init(int* queue, hipStream_t st) {
 template <typename S>
 hipError_t launch_batched(const BatchProblem* probs, const int* order, int count,
                           const BatchParams& P, int* queue, char* slots, size_t slot_bytes,
-                          int64_t hmax, const BatchOut& out, int threads, int blocks,
-                          hipStream_t st) {
+                          int64_t hmax, const BatchOut& out, int threads, int rpw, int unr,
+                          int blocks, hipStream_t st) {
   if (P.m + (P.m & 1) > kJacobiLdsMaxMp) return hipErrorInvalidValue;
   switch (threads) {
-    case 128: return launch_nt<S, 128>(probs, order, count, P, queue, slots, slot_bytes, hmax, out, blocks, st);
-    case 256: return launch_nt<S, 256>(probs, order, count, P, queue, slots, slot_bytes, hmax, out, blocks, st);
-    case 512: return launch_nt<S, 512>(probs, order, count, P, queue, slots, slot_bytes, hmax, out, blocks, st);
+    case 128: return launch_tile<S, 128>(probs, order, count, P, queue, slots, slot_bytes, hmax, out, rpw, unr, blocks, st);
+    case 256: return launch_tile<S, 256>(probs, order, count, P, queue, slots, slot_bytes, hmax, out, rpw, unr, blocks, st);
+    case 512: return launch_tile<S, 512>(probs, order, count, P, queue, slots, slot_bytes, hmax, out, rpw, unr, blocks, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template hipError_t launch_batched<float>(const BatchProblem*, const int*, int, const BatchParams&,
                                           int*, char*, size_t, int64_t, const BatchOut&, int, int,
-                                          hipStream_t);
+                                          int, int, hipStream_t);
 template hipError_t launch_batched<double>(const BatchProblem*, const int*, int,
                                            const BatchParams&, int*, char*, size_t, int64_t,
-                                           const BatchOut&, int, int, hipStream_t);
+                                           const BatchOut&, int, int, int, int, hipStream_t);
 
 }  // namespace jl

@@ -39,7 +39,8 @@ template <typename S, typename T>
 __global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A, int64_t lda,
                                                       const T* __restrict__ B, int64_t ldb,
                                                       S* __restrict__ C, int64_t ldc, int64_t M,
-                                                      int N, int K, int64_t tiles_m, int tiles_n) {
+                                                      int N, int K, int64_t tiles_m, int tiles_n,
+                                                      const int* __restrict__ cmap) {
   using MF = Mfma<T>;
   constexpr int BK = MF::BK;
   constexpr int AV = 16 / sizeof(S);                    // elements per 16-byte load
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int col = n0 + wn * 64 + j * 16 + 4 * r + lane / 16;
-        if (col < N) C[(int64_t)col * ldc + row] = (S)acc[i][j][r];
+        if (col < N) C[(int64_t)(cmap ? cmap[col] : col) * ldc + row] = (S)acc[i][j][r];
       }
     }
   }
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A
 
 template <typename S, typename T>
 hipError_t launch_gemm_nn(const S* A, int64_t lda, const T* B, int64_t ldb, S* C, int64_t ldc,
-                          int64_t M, int N, int K, hipStream_t st) {
+                          int64_t M, int N, int K, hipStream_t st, const int* cmap) {
   if (M <= 0 || N <= 0) return hipSuccess;
   // 16-byte vector loads/stores of A and C columns need 4-element (FP32) or
   // 2-element (FP64) alignment of every column start.
@@ -187,14 +188,15 @@ hipError_t launch_gemm_nn(const S* A, int64_t lda, const T* B, int64_t ldb, S* C
   nblk = (nblk + 7) / 8 * 8;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_gemm_nn<S, T>), dim3((unsigned)nblk), dim3(kThreads), 0, st, A, lda, B, ldb,
-                     C, ldc, M, N, K, tm, tn);
+                     C, ldc, M, N, K, tm, tn, cmap);
   return hipGetLastError();
 }
 
 template hipError_t launch_gemm_nn<float, double>(const float*, int64_t, const double*, int64_t,
-                                                  float*, int64_t, int64_t, int, int, hipStream_t);
+                                                  float*, int64_t, int64_t, int, int, hipStream_t,
+                                                  const int*);
 template hipError_t launch_gemm_nn<double, double>(const double*, int64_t, const double*, int64_t,
                                                    double*, int64_t, int64_t, int, int,
-                                                   hipStream_t);
+                                                   hipStream_t, const int*);
 
 }  // namespace jl

@@ -296,15 +296,18 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {   // result 
 }
 
 // True residuals ||A x_c - lam_c x_c||^2 of many columns x_c = X + cols[c]*ldx
-// with the links read once for all of them: sixteen threads per site, thread
+// with the links read once per group of columns: sixteen threads per site, thread
 // (mu, r) computes the hops in direction mu of row r of both halves of
 // (A x_c)(s) and keeps the link entries it multiplies in registers for every
 // column (row r of U_mu(s), column r of U_mu(s - mu)); the four directions of
 // a row are summed across lanes.  The site-independent B sits in LDS (per-site
 // B is read per use).  FP64 products and accumulation on the stored vectors.
-// partial[blk * ncols + c] = the block's share of column c
+// The columns are split into groups of kResidCols over gridDim.y (the links
+// are read once per group; a block walks its group's columns in turn).
+// partial[blk * ncols + c] = the share of column c of site block blk
 // (stencil_resid_blocks blocks).
 constexpr int kResidSites = kStencilThreads / 16;   // sites per block
+constexpr int kResidCols = 16;                       // columns per block
 
 template <typename S, bool BSITE>
 __global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S> a,
@@ -315,7 +318,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S
                                                                    int ncols,
                                                                    double* __restrict__ partial) {
   __shared__ cplx<S> Bs[64];
-  __shared__ double red[2][kStencilThreads / 64];
+  __shared__ double red[kStencilThreads / 64][kResidCols];   // per-wavefront column sums
   const int r = threadIdx.x & 3, mu = (threadIdx.x >> 2) & 3;
   const int64_t s_raw = (int64_t)blockIdx.x * kResidSites + (threadIdx.x >> 4);
   const bool ok = s_raw < a.V;
@@ -347,7 +350,9 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S
   const cplx<S>* Bm = BSITE ? a.B + (int64_t)mu * 16 * V : Bs + mu * 16;
   const double dg = a.diag, sc = a.scale;
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-  for (int col = 0; col < ncols; ++col) {
+  const int col0 = (int)blockIdx.y * kResidCols, col1 = min(ncols, col0 + kResidCols);
+  for (int col = col0; col < col1; ++col) {
+    const int cc = col - col0;
     const cplx<S>* x = X + (int64_t)cols[col] * ldx;
     double tr = 0.0, ti = 0.0, br = 0.0, bi = 0.0;   // row r, direction mu
     if (mu == 0) {   // (diag - l) x(s), once per row
@@ -399,14 +404,14 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S
     double acc = (ok && mu == 0) ? tr * tr + ti * ti + br * br + bi * bi : 0.0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (lane == 0) red[col & 1][w] = acc;
-    __syncthreads();   // red[col & 1] is next written two columns on, after another barrier
-    if (threadIdx.x == 0) {
-      double tot = 0.0;
+    if (lane == 0) red[w][cc] = acc;   // only this wavefront writes red[w]: no barrier per column
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; col0 + i < col1; i += kStencilThreads) {
+    double tot = 0.0;
 #pragma unroll
-      for (int k = 0; k < kStencilThreads / 64; ++k) tot += red[col & 1][k];
-      partial[(int64_t)blockIdx.x * ncols + col] = tot;
-    }
+    for (int k = 0; k < kStencilThreads / 64; ++k) tot += red[k][i];
+    partial[(int64_t)blockIdx.x * ncols + col0 + i] = tot;
   }
 }
 
@@ -649,12 +654,13 @@ hipError_t launch_stencil_resid(const StencilArgs<S>& a, const cplx<S>* X, int64
   const int nb = stencil_resid_blocks(a.V);
   *nblk = nb;
   if (ncols <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nb, (unsigned)((ncols + kResidCols - 1) / kResidCols));
   if (a.b_per_site)
-    hipLaunchKernelGGL((k_stencil_resid<S, true>), dim3((unsigned)nb), dim3(kStencilThreads), 0, st,
-                       a, X, ldx, cols, lam, ncols, partial);
+    hipLaunchKernelGGL((k_stencil_resid<S, true>), grid, dim3(kStencilThreads), 0, st, a, X, ldx,
+                       cols, lam, ncols, partial);
   else
-    hipLaunchKernelGGL((k_stencil_resid<S, false>), dim3((unsigned)nb), dim3(kStencilThreads), 0, st,
-                       a, X, ldx, cols, lam, ncols, partial);
+    hipLaunchKernelGGL((k_stencil_resid<S, false>), grid, dim3(kStencilThreads), 0, st, a, X, ldx,
+                       cols, lam, ncols, partial);
   return hipGetLastError();
 }
 

@@ -657,6 +657,16 @@ __global__ void k_copy_cols(const cplx<S>* __restrict__ X, int64_t ldx, cplx<S>*
   if (i < n) Y[(int64_t)blockIdx.y * ldy + i] = X[(int64_t)blockIdx.y * ldx + i];
 }
 
+template <typename S>
+__global__ void k_copy_pairs(const cplx<S>* __restrict__ X, int64_t ldx, cplx<S>* __restrict__ Y,
+                             int64_t ldy, int64_t n, const int* __restrict__ pairs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int dst = pairs[2 * blockIdx.y], src = pairs[2 * blockIdx.y + 1];
+    Y[(int64_t)dst * ldy + i] = X[(int64_t)src * ldx + i];
+  }
+}
+
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -886,6 +896,15 @@ hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t l
   return hipGetLastError();
 }
 
+template <typename S>
+hipError_t launch_copy_pairs(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t ldy, int64_t n,
+                             const int* pairs, int npairs, hipStream_t st) {
+  if (npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_pairs<S>, dim3(blocks_for(n, 256), (unsigned)npairs), dim3(256), 0, st, X,
+                     ldx, Y, ldy, n, pairs);
+  return hipGetLastError();
+}
+
 #define JL_INST(S)                                                                                \
   template hipError_t launch_reorth_dots<S>(const cplx<S>*, int64_t, int, cplx<S>*, int64_t,       \
                                             double*, int, hipStream_t, const double*, double,     \
@@ -899,7 +918,9 @@ hipError_t launch_copy_cols(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t l
   template hipError_t launch_pair<S>(const cplx<S>*, int64_t, cplx<S>*, int64_t, int64_t, int,    \
                                      hipStream_t);                                                \
   template hipError_t launch_copy_cols<S>(const cplx<S>*, int64_t, cplx<S>*, int64_t, int64_t,    \
-                                          int, hipStream_t);
+                                          int, hipStream_t);                                      \
+  template hipError_t launch_copy_pairs<S>(const cplx<S>*, int64_t, cplx<S>*, int64_t, int64_t,   \
+                                           const int*, int, hipStream_t);
 JL_INST(float)
 JL_INST(double)
 #undef JL_INST

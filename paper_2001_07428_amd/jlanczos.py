@@ -35,8 +35,8 @@ EXPORTS = (
     "jl_reorth_pass_workspace_bytes", "jl_reorth_pass", "jl_reorth_pass_noalloc",
     "jl_ritz_workspace_bytes", "jl_ritz",
     "jl_ritz_restart_workspace_bytes", "jl_ritz_restart",
-    "jl_basis_update", "jl_batch_workspace_bytes", "jl_batch_create", "jl_batch_run",
-    "jl_batch_destroy",
+    "jl_basis_update", "jl_batch_workspace_bytes", "jl_batch_create", "jl_batch_shape_used",
+    "jl_batch_run", "jl_batch_destroy",
 )
 
 
@@ -75,9 +75,19 @@ class JlStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class JlBatchShape(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("rows_per_wave", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("lds_matrix_bytes", ctypes.c_int32)]
+
+    def to_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class JlBatchStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int32), ("n_mv", ctypes.c_int32),
-                ("gs_passes", ctypes.c_int32), ("icnv", ctypes.c_int32)]
+                ("gs_passes", ctypes.c_int32), ("icnv", ctypes.c_int32),
+                ("n_resid", ctypes.c_int32)]
 
 
 _lib = None
@@ -118,10 +128,12 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.c_size_t]),
         "jl_basis_update": (i32, [vp, i32, i64, i32, i32, vp, i64, vp, i64, vp, i64]),
         "jl_batch_workspace_bytes": (i32, [i32, ctypes.POINTER(i64), i32, ctypes.POINTER(JlParams),
-                                           i32, i32, ctypes.POINTER(ctypes.c_size_t)]),
+                                           ctypes.POINTER(JlBatchShape),
+                                           ctypes.POINTER(ctypes.c_size_t)]),
         "jl_batch_create": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   i32, ctypes.POINTER(JlParams), ctypes.POINTER(vp), vp,
-                                  ctypes.c_size_t, i32, i32, ctypes.POINTER(vp)]),
+                                  ctypes.c_size_t, ctypes.POINTER(JlBatchShape), ctypes.POINTER(vp)]),
+        "jl_batch_shape_used": (i32, [vp, ctypes.POINTER(JlBatchShape)]),
         "jl_batch_run": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(i32),
                                ctypes.POINTER(JlBatchStats)]),
         "jl_batch_destroy": (i32, [vp]),
@@ -496,8 +508,10 @@ class Batch:
     dtype); eigenvectors land in self.X[i] (nev, n_i)."""
 
     def __init__(self, ctx: Context, A11s, A12s, nev, m, mwin, tol, which="lowest",
-                 tol_relative=False, max_cycles=0, threads=0, blocks=0, standard=False,
-                 invert=False):
+                 tol_relative=False, max_cycles=0, shape=None, standard=False, invert=False):
+        """shape: dict of jl_batch_shape knobs (threads, blocks, rows_per_wave,
+        unroll, lds_matrix_bytes); None takes the autotuner's cached shape for
+        this batch and device, or the library defaults (with a warning)."""
         torch = _torch()
         lib = load_library()
         count = len(A11s)
@@ -510,19 +524,25 @@ class Batch:
                 raise ValueError("every A11/A12 must be a contiguous square tensor of one dtype")
         self.ctx, self.count, self.nev = ctx, count, nev
         self.n = np.array([2 * a.shape[0] for a in A11s], dtype=np.int64)
-        if threads == 0 and blocks == 0:   # shape from the autotuner's cache, if any
+        self.tuned = False
+        if shape is None:   # shape from the autotuner's cache, if any
             from . import tune
-            hit = tune.lookup(self.n, nev, m, "c64" if dt == torch.complex64 else "c128")
-            if hit is not None:
-                threads, blocks = hit
-        self.threads, self.blocks = threads, blocks
+            shape = tune.lookup(self.n, nev, m, "c64" if dt == torch.complex64 else "c128")
+            if shape is not None:
+                self.tuned = True
+            else:
+                import warnings
+                warnings.warn("no tuned launch shape for this batch and device "
+                              "(python -m paper_2001_07428_amd.tune): library defaults")
+                shape = {}
+        self._shape = JlBatchShape(**{k: int(v) for k, v in shape.items()})
         self.p = _params(nev, m, mwin, tol, which, max_cycles, 0, 0, None, 0, tol_relative, False,
                          standard, invert)
         code = _dtype_code(A11s[0])
         nb = ctypes.c_size_t()
         n_c = self.n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
-        _check(lib.jl_batch_workspace_bytes(count, n_c, code, ctypes.byref(self.p), threads, blocks,
-                                            ctypes.byref(nb)), ctx.handle)
+        _check(lib.jl_batch_workspace_bytes(count, n_c, code, ctypes.byref(self.p),
+                                            ctypes.byref(self._shape), ctypes.byref(nb)), ctx.handle)
         self.ws = torch.empty(nb.value, dtype=torch.uint8, device=ctx.device)
         self.X = [torch.empty((nev, int(ni)), dtype=dt, device=ctx.device) for ni in self.n]
         vp = ctypes.c_void_p
@@ -532,9 +552,13 @@ class Batch:
         self._keep = (A11s, A12s)
         h = vp()
         _check(lib.jl_batch_create(ctx.handle, count, n_c, a11, a12, code, ctypes.byref(self.p), xs,
-                                   vp(self.ws.data_ptr()), nb.value, threads, blocks, ctypes.byref(h)),
-               ctx.handle)
+                                   vp(self.ws.data_ptr()), nb.value, ctypes.byref(self._shape),
+                                   ctypes.byref(h)), ctx.handle)
         self.handle = h
+        used = JlBatchShape()
+        _check(lib.jl_batch_shape_used(h, ctypes.byref(used)), ctx.handle)
+        self.shape = used.to_dict()   # the launch shape in use, defaults resolved
+        self.threads, self.blocks = used.threads, used.blocks
 
     def run(self):
         """Replays the graph; returns (status, evals (count, nev), res, per-problem
