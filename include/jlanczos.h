@@ -34,7 +34,7 @@
  *    host results (jl_solve) wait for their own work before returning.
  *  - The solver's scratch space is the caller's workspace (size from
  *    jl_workspace_bytes).  Device memory the library itself holds:
- *      . the stencil operator's site-fastest copy of its links, 64 V complex
+ *      . the stencil operator's tiled copy of its links, 64 V complex
  *        elements (twice that with per-site B), jl_op_create_stencil until
  *        jl_op_destroy;
  *      . the Case B operator's padded links, product matrices, projection
@@ -98,9 +98,10 @@ jl_status jl_op_create_dense(jl_ctx ctx, int64_t n, const void* A11, const void*
  * (T_mu a)(x) = a(x + mu_hat) periodic.  U: device [4][V][d][d] row-major
  * complex links (unitarity not required); B: device [4][d][d] (b_per_site =
  * 0) or [4][V][d][d] (b_per_site = 1).  The result is Hermitian J-symmetric
- * by construction.  The operator keeps its own device copy of U and B with
- * the lattice site as the fastest index (64 V complex elements of the dtype,
- * twice that with per-site B; freed by jl_op_destroy), made on the ctx
+ * by construction.  The operator keeps its own device copy of U and B in
+ * tiles of 64 sites (within a tile the site is the fastest index; 64 V
+ * complex elements of the dtype, V rounded up to 64, twice that with
+ * per-site B; freed by jl_op_destroy), made on the ctx
  * stream before the call returns: U and B are not referenced afterwards.
  * Vectors passed to this operator must be 16-byte aligned.  Errors:
  * JL_EINVAL for L[i] < 2, 2^31 sites or more, or NULL pointers;

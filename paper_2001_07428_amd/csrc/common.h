@@ -24,9 +24,18 @@ constexpr int kWave = 64;
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `st` and returns the launch error (if any).
 
-// Stencil operator data.  U: links in site-fastest order, entry e of U_mu(s)
-// at U[(mu * 16 + e) * V + s]; B: the 4 direction matrices [mu][16], or with
+// Stencil operator data.  U: links in tiles of 64 sites, entry e of U_mu(s)
+// at U[link_index(s, mu, e)] (the 64 sites of a tile fastest, then the entry
+// mu * 16 + e, then the tile); B: the 4 direction matrices [mu][16], or with
 // b_per_site the layout of U.
+constexpr int kLinkTile = 64;
+__host__ __device__ inline int64_t link_index(int64_t s, int mu, int e) {   // s >= 0
+  const uint64_t u = (uint64_t)s;
+  return (int64_t)((((u >> 6) * 64 + (uint64_t)(mu * 16 + e)) << 6) | (u & 63));
+}
+static_assert(kLinkTile == 64, "link_index assumes tiles of 64 sites");
+// Elements of the tiled link copy for V sites (the last tile padded).
+__host__ __device__ inline int64_t link_elems(int64_t V) { return (V + kLinkTile - 1) / kLinkTile * kLinkTile * 64; }
 template <typename S> struct StencilArgs {
   const cplx<S>* U;
   const cplx<S>* B;
@@ -58,9 +67,10 @@ hipError_t launch_stencil_apply_dir(const StencilArgs<S>& a, const cplx<S>* r, c
 // Per-block partial sums of ||A x_c - lam_c x_c||^2 (FP64 compute) for ncols
 // columns x_c = X + cols[c]*ldx (cols, lam on the device); partial layout
 // [blk][c]; *nblk = blocks per column.
-// dst[(mu * 16 + e) * V + s] = src[(mu * V + s) * 16 + e] for 4 directions.
+// dst[link_index(s, mu, e)] = src[(mu * V + s) * 16 + e] for 4 directions
+// (dst holds link_elems(V) elements; the padding is zeroed).
 template <typename S>
-hipError_t launch_links_site_fastest(const cplx<S>* src, cplx<S>* dst, int64_t V, hipStream_t st);
+hipError_t launch_links_tiled(const cplx<S>* src, cplx<S>* dst, int64_t V, hipStream_t st);
 
 template <typename S>
 hipError_t launch_stencil_resid(const StencilArgs<S>& a, const cplx<S>* X, int64_t ldx,
@@ -147,12 +157,14 @@ constexpr int kReorthMaxCols = 2048;   // largest basis dots supports
 // beta = 0 skips the second term), rounds u once to S, stores it, and then
 // takes the inner products of the new u.
 // groups > 1 splits the columns over gridDim.y (reorth_dots_groups); with
-// tloc the locally updated u then goes to uout, which must not be u.
+// tloc the locally updated u then goes to uout, which must not be u.  With
+// beta2 (device) the second term uses beta = sqrt(*beta2) instead of `beta`.
 template <typename S>
 hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
                               double* partial, int nblk, hipStream_t st,
                               const double* tloc = nullptr, double beta = 0.0, int jl = 0,
-                              cplx<S>* uout = nullptr, int groups = 1);
+                              cplx<S>* uout = nullptr, int groups = 1,
+                              const double* beta2 = nullptr);
 int reorth_dots_groups(int64_t h, int es);
 // update: u -= V c_v + W c_w (W = J V^*), coef = [4*ncol] FP64 (Re cv, Im cv,
 // Re cw, Im cw per column); partial[blk] = ||u_new||^2 per block.

@@ -506,8 +506,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     ~Ev() {
       if (e) hipEventDestroy(e);
     }
-  } ev_copy;
-  JL_HIP(ctx, hipEventCreateWithFlags(&ev_copy.e, hipEventDisableTiming));
+  } ev_copy[2];   // the scalar copies of two consecutive steps
+  for (auto& ev : ev_copy) JL_HIP(ctx, hipEventCreateWithFlags(&ev.e, hipEventDisableTiming));
   Pinned pin;
   const size_t pin_doubles = 16 + CG_NSLOTS + 3 * (size_t)m + 3 * (size_t)nev + 2 * (size_t)m * m +
                              2 * (size_t)m;
@@ -520,6 +520,8 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     ~StreamWait() { (void)hipStreamSynchronize(s); }
   } stream_wait{st};
   double* hs = pin.p;                    // [16] scalars
+  double* hslot[2] = {pin.p, pin.p + 8};   // a step's scalars: slot 0 = hs[0..4], slot 1 = hs[8..12]
+  int64_t n_queued = 0;                    // Lanczos steps queued (for the timing sample)
   double* h_cg = pin.p + 16;             // [CG_NSLOTS] CG scalars
   double* h_lam = h_cg + CG_NSLOTS;      // [m]
   double* h_zl = h_lam + m;              // [m]
@@ -619,11 +621,14 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
     cplx<S>* Vn = Vb[1 - cur];
     int meff = m;
     bool broke = false;
-    // Normal mode queues the next step's normalisation (factor read on the
-    // device) and operator apply before it waits for this step's scalars, so
-    // the device stays busy over the host's round trip; a step that needs
-    // another Gram-Schmidt pass redoes the apply.
-    bool applied = false;   // u = A v_j of this step is already queued
+    // Normal mode queues the whole next step (its normalisation, factor read
+    // on the device; the operator apply; the local step, with beta read on the
+    // device; the inner products, the update and the copy of its scalars)
+    // before it waits for this step's scalars, so the device always has a
+    // step of work queued over the host's round trip.  A step that needs
+    // another Gram-Schmidt pass (or breaks down) discards the queued step,
+    // which is then queued again.
+    bool queued = false;   // step j's work (apply, reorthogonalisation, scalar copy) is queued
     auto queue_apply = [&](const cplx<S>* x, cplx<S>* y) -> hipError_t {
       tm.start(Timer::MATVEC);
       hipError_t e = op_apply<S>(op, x, y, ldv, 1, apart, st);
@@ -634,54 +639,67 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       tm.count(Timer::MATVEC, op_bytes(op, es));
       return e;
     };
+    // Step jj: [u = A v_jj, t_jj partials to scal[0..1]], local three-term
+    // step u -= t_jj v_jj + beta_{jj-1} v_{jj-1} fused into the first inner
+    // products against [V_jj, W_jj] (beta from the host, or with beta2 from
+    // the device norm^2), the first update pass, and the copy of scal[0..4]
+    // to the step's pinned slot, recorded by its event.
+    auto queue_step = [&](int jj, bool with_apply, const double* beta2) -> jl_status {
+      cplx<S>* vjj = V + (int64_t)jj * ldv;
+      cplx<S>* uu = V + (int64_t)(jj + 1) * ldv;
+      const int nc = jj + 1;
+      const int sd = dots_stride(nc);
+      tm.sample = n_queued++ % tm.stride == 0;   // this step's events
+      if (with_apply) JL_HIP(ctx, queue_apply(vjj, uu));
+      const double beta_host = (!beta2 && jj > k) ? Tat(jj, jj - 1) : 0.0;
+      tm.start(Timer::DOTS);
+      JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, nc, uu, h, dots_part, ndots, st, scal, beta_host, jj,
+                                        uloc, gd, beta2));
+      tm.stop();
+      // the norms entering the loop (the last two reduced columns: after the
+      // local step, after t_jj v_jj alone) also to scal[3], scal[4]
+      JL_HIP(ctx, launch_reduce_wide(dots_part, ndots, sd, sd, coef, wide_scr, wide_cnt, st, scal + 3));
+      S_.n_dots_launch++;
+      S_.bytes_dots += (double)(nc + 1) * n * es;
+      tm.count(Timer::DOTS, (double)(nc + 1) * n * es);
+      tm.start(Timer::UPDATE);
+      JL_HIP(ctx, launch_reorth_update<S>(V, ldv, nc, uu, h, coef, upd_part, nupd, st, jsym,
+                                          uloc ? uloc : uu, gu, dscr, scal + 2, upd_cnt));
+      tm.stop();
+      S_.n_update_launch++;
+      S_.bytes_update += (double)(nc + 2) * n * es;
+      tm.count(Timer::UPDATE, (double)(nc + 2) * n * es);
+      JL_HIP(ctx, hipMemcpyAsync(hslot[jj & 1], scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+      JL_HIP(ctx, hipEventRecord(ev_copy[jj & 1].e, st));
+      return JL_OK;
+    };
     // ================= Algorithm 2: Lanczos steps j = k .. m-1
     for (int j = k; j < m; ++j) {
-      cplx<S>* vj = V + (int64_t)j * ldv;
       cplx<S>* u = V + (int64_t)(j + 1) * ldv;
       const int ncol = j + 1;
       const int stride = dots_stride(ncol);
       if (invert) {   // u = A^-1 v_j by CG, t_jj = v_j^H u into scal
-        const jl_status cs = cg_solve(vj, u);
+        const jl_status cs = cg_solve(V + (int64_t)j * ldv, u);
         if (cs != JL_OK) return cs;
-      } else if (!applied) {   // u = A v_j, with the block partial sums of t_jj = v_j^H u
-        JL_HIP(ctx, queue_apply(vj, u));
+        const jl_status qs = queue_step(j, false, nullptr);
+        if (qs != JL_OK) return qs;
+      } else if (!queued) {
+        const jl_status qs = queue_step(j, true, nullptr);
+        if (qs != JL_OK) return qs;
       }
-      applied = false;
-      tm.sample = S_.n_mv % tm.stride == 0;   // this step's (and the next queued apply's) events
+      queued = false;
       S_.n_mv++;
       S_.sum_ncol += ncol;
-      // local three-term step u -= t_jj v_j + beta_{j-1} v_{j-1} fused into the
-      // first inner products against [V_j, W_j]; then the first update pass
-      const double beta_prev = (j > k) ? Tat(j, j - 1) : 0.0;
-      tm.start(Timer::DOTS);
-      JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st, scal, beta_prev, j,
-                                        uloc, gd));
-      tm.stop();
-      // the norms entering the loop (the last two reduced columns: after the
-      // local step, after t_jj v_j alone) also to scal[3], scal[4]
-      JL_HIP(ctx, launch_reduce_wide(dots_part, ndots, stride, stride, coef, wide_scr, wide_cnt, st,
-                                     scal + 3));
-      S_.n_dots_launch++;
-      S_.bytes_dots += (double)(ncol + 1) * n * es;
-      tm.count(Timer::DOTS, (double)(ncol + 1) * n * es);
-      tm.start(Timer::UPDATE);
-      JL_HIP(ctx, launch_reorth_update<S>(V, ldv, ncol, u, h, coef, upd_part, nupd, st, jsym,
-                                          uloc ? uloc : u, gu, dscr, scal + 2, upd_cnt));
-      tm.stop();
-      S_.n_update_launch++;
-      S_.bytes_update += (double)(ncol + 2) * n * es;
-      tm.count(Timer::UPDATE, (double)(ncol + 2) * n * es);
-      JL_HIP(ctx, hipMemcpyAsync(hs, scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
-      // speculative: v_{j+1} = u / ||u|| and A v_{j+1}, behind the copy
+      double* hs = hslot[j & 1];
+      // speculative: the whole of step j + 1 on v_{j+1} = u / ||u||, behind
+      // this step's scalar copy
       const bool spec = !invert && j + 1 < m;
       if (spec) {
-        JL_HIP(ctx, hipEventRecord(ev_copy.e, st));
         JL_HIP(ctx, launch_scale_dev<S>(u, n, scal + 2, st));
-        JL_HIP(ctx, queue_apply(u, u + ldv));
-        JL_HIP(ctx, hipEventSynchronize(ev_copy.e));
-      } else {
-        JL_HIP(ctx, hipStreamSynchronize(st));
+        const jl_status qs = queue_step(j + 1, true, scal + 2);   // beta_j = ||u|| on the device
+        if (qs != JL_OK) return qs;
       }
+      JL_HIP(ctx, hipEventSynchronize(ev_copy[j & 1].e));
       tm.resolve();
       const double alpha = hs[0];
       Tat(j, j) = alpha;
@@ -695,7 +713,13 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       const double btol = bd_factor * uround * std::max(maxT, 1e-300);
       int passes = 1;
       S_.gs_passes++;
+      bool drained = false;   // the speculative step has run out (its results are discarded)
       while (!(passes >= min_passes && b1 * sqrt2 > b0) && b1 > btol && passes < max_passes) {
+        if (!drained) {
+          JL_HIP(ctx, hipStreamSynchronize(st));
+          tm.resolve();
+          drained = true;
+        }
         b0 = b1;
         tm.start(Timer::DOTS);
         JL_HIP(ctx, launch_reorth_dots<S>(V, ldv, ncol, u, h, dots_part, ndots, st, nullptr, 0.0, 0,
@@ -733,7 +757,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
         break;
       }
       if (spec && passes == 1) {
-        applied = true;   // the queued v_{j+1} and A v_{j+1} stand
+        queued = true;   // the queued step j + 1 stands
       } else {
         JL_HIP(ctx, launch_scale<S>(u, n, usc / b1, st));
       }
@@ -1179,7 +1203,7 @@ jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double
   if (V >= ((int64_t)1 << 31))
     return set_err(ctx, JL_EINVAL, "the lattice must have fewer than 2^31 sites (got %lld)", (long long)V);
   const size_t es = dtype == JL_C64 ? sizeof(float2) : sizeof(double2);
-  const size_t ubytes = (size_t)64 * V * es;
+  const size_t ubytes = (size_t)link_elems(V) * es;   // tiles of 64 sites (link_index)
   const size_t bbytes = b_per_site ? ubytes : 64 * es;
   DeviceGuard g(ctx->device);
   void* links = nullptr;
@@ -1191,17 +1215,17 @@ jl_status jl_op_create_stencil(jl_ctx ctx, const int32_t L[4], int32_t d, double
   char* ub = static_cast<char*>(links);
   char* bb = ub + ubytes;
   if (dtype == JL_C64) {
-    e = launch_links_site_fastest<float>(static_cast<const float2*>(U), reinterpret_cast<float2*>(ub), V,
+    e = launch_links_tiled<float>(static_cast<const float2*>(U), reinterpret_cast<float2*>(ub), V,
                                          ctx->stream);
     if (e == hipSuccess)
-      e = b_per_site ? launch_links_site_fastest<float>(static_cast<const float2*>(B),
+      e = b_per_site ? launch_links_tiled<float>(static_cast<const float2*>(B),
                                                         reinterpret_cast<float2*>(bb), V, ctx->stream)
                      : hipMemcpyAsync(bb, B, bbytes, hipMemcpyDeviceToDevice, ctx->stream);
   } else {
-    e = launch_links_site_fastest<double>(static_cast<const double2*>(U), reinterpret_cast<double2*>(ub),
+    e = launch_links_tiled<double>(static_cast<const double2*>(U), reinterpret_cast<double2*>(ub),
                                           V, ctx->stream);
     if (e == hipSuccess)
-      e = b_per_site ? launch_links_site_fastest<double>(static_cast<const double2*>(B),
+      e = b_per_site ? launch_links_tiled<double>(static_cast<const double2*>(B),
                                                          reinterpret_cast<double2*>(bb), V, ctx->stream)
                      : hipMemcpyAsync(bb, B, bbytes, hipMemcpyDeviceToDevice, ctx->stream);
   }

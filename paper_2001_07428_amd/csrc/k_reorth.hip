@@ -175,7 +175,8 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
                                                          double* __restrict__ partial,
                                                          const double* __restrict__ tloc,
                                                          double beta, int jl,
-                                                         cplx<S>* __restrict__ uout) {
+                                                         cplx<S>* __restrict__ uout,
+                                                         const double* __restrict__ beta2) {
   constexpr int Q = kPairsPerLane / E;     // loads per half per lane per chunk
   constexpr int CH = 64 * E * Q;           // pairs per chunk
   extern __shared__ double acc[];          // dots_stride(ncol) column accumulators
@@ -215,6 +216,7 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
       __syncthreads();   // every wavefront holds the raw chunk before it is overwritten
       double anorm = 0.0;
       const double t_re = tloc[0], t_im = tloc[1];
+      const double bt = beta2 ? sqrt(beta2[0]) : beta;   // beta_{jl-1}: host value or device norm^2
       const cplx<S>* vj = V + (int64_t)jl * ldv;
       const cplx<S>* vm = vj - ldv;
 #pragma unroll
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
         Ld<S, E>::get(vj + p, tr, ti);
         Ld<S, E>::get(vj + h + p, br, bi);
         S mtr[E], mti[E], mbr[E], mbi[E];
-        if (beta != 0.0) {
+        if (bt != 0.0) {
           Ld<S, E>::get(vm + p, mtr, mti);
           Ld<S, E>::get(vm + h + p, mbr, mbi);
         } else {
@@ -241,10 +243,10 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
           const double abr = ubr[q][e] - (t_re * br[e] - t_im * bi[e]);
           const double abi = ubi[q][e] - (t_re * bi[e] + t_im * br[e]);
           anorm += atr * atr + ati * ati + abr * abr + abi * abi;
-          utr[q][e] = (double)(S)(atr - beta * mtr[e]);
-          uti[q][e] = (double)(S)(ati - beta * mti[e]);
-          ubr[q][e] = (double)(S)(abr - beta * mbr[e]);
-          ubi[q][e] = (double)(S)(abi - beta * mbi[e]);
+          utr[q][e] = (double)(S)(atr - bt * mtr[e]);
+          uti[q][e] = (double)(S)(ati - bt * mti[e]);
+          ubr[q][e] = (double)(S)(abr - bt * mbr[e]);
+          ubi[q][e] = (double)(S)(abi - bt * mbi[e]);
         }
         if (wave == 0 && blockIdx.y == 0) {
 #pragma unroll
@@ -710,9 +712,9 @@ static bool basis_streams(int ncol, int64_t h, size_t es) {
 template <typename S>
 hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* u, int64_t h,
                               double* partial, int nblk, hipStream_t st, const double* tloc,
-                              double beta, int jl, cplx<S>* uout, int groups) {
+                              double beta, int jl, cplx<S>* uout, int groups, const double* beta2) {
   if (ncol > kMaxCols) return hipErrorInvalidValue;
-  if (tloc && (jl < 0 || jl >= ncol || (beta != 0.0 && jl < 1))) return hipErrorInvalidValue;
+  if (tloc && (jl < 0 || jl >= ncol || ((beta != 0.0 || beta2) && jl < 1))) return hipErrorInvalidValue;
   if (groups < 1) return hipErrorInvalidValue;
   if (!uout) uout = u;
   if (tloc && groups > 1 && uout == u) return hipErrorInvalidValue;   // the groups still read u
@@ -731,7 +733,7 @@ hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* 
     constexpr int E = decltype(e2c)::value ? (sizeof(S) == 4 ? 2 : 1) : 1;
     hipLaunchKernelGGL((k_dots<S, E, decltype(localc)::value, decltype(ntc)::value>), g2,
                        dim3(kReorthThreads), lds, st, V, ldv, ncol, u, h, per, partial, tloc, beta,
-                       jl, uout);
+                       jl, uout, beta2);
   };
   using T_ = std::true_type;
   using F_ = std::false_type;
@@ -908,7 +910,7 @@ hipError_t launch_copy_pairs(const cplx<S>* X, int64_t ldx, cplx<S>* Y, int64_t 
 #define JL_INST(S)                                                                                \
   template hipError_t launch_reorth_dots<S>(const cplx<S>*, int64_t, int, cplx<S>*, int64_t,       \
                                             double*, int, hipStream_t, const double*, double,     \
-                                            int, cplx<S>*, int);                                  \
+                                            int, cplx<S>*, int, const double*);                   \
   template hipError_t launch_reorth_update<S>(const cplx<S>*, int64_t, int, cplx<S>*, int64_t,    \
                                               const double*, double*, int, hipStream_t, bool,     \
                                               const cplx<S>*, int, cplx<S>*, double*, unsigned*); \

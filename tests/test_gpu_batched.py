@@ -55,20 +55,22 @@ def test_batched_small_vs_brute(ctx, mixed):
 
 @pytest.mark.parametrize("mixed", [False, True])
 def test_batched_tile_shapes(ctx, mixed):
-    """The autotuner's knobs change the schedule, not the arithmetic: for one
-    workgroup size every apply tile (rows per wavefront, loads in flight) and
+    """The autotuner's knobs change the schedule, not the results.  For one
+    workgroup size and one number of rows per wavefront, the loads in flight and
     the LDS-resident matrices (problems with n <= 90 fit 32 KiB in FP32, n <= 64
-    in FP64) give bit-identical results, and they match brute force."""
+    in FP64) give bit-identical results; two rows per wavefront change which
+    wavefront sums which rows of t_jj = v_j^H A v_j, so the results agree to
+    rounding.  Every shape matches brute force."""
     from paper_2001_07428_amd import jlanczos as J
     say("batched tile shapes", mixed)
     n, probs = inputs.batched_dense(15, count=12, nmin=64, nmax=200)
     dt = cdt(mixed)
     A11s, A12s = [to_dev(a, dt) for a, _ in probs], [to_dev(c, dt) for _, c in probs]
     tol = 1e-4 if mixed else 1e-9
-    ref = None
+    gate = 1e-5 if mixed else 1e-10
     for threads in (256, 512):
-        base = None
-        for rpw, unr, lds in ((1, 4, 0), (2, 4, 0), (1, 8, 0), (2, 8, 0), (1, 4, 32768)):
+        base = {}
+        for rpw, unr, lds in ((1, 4, 0), (1, 8, 0), (1, 4, 32768), (2, 4, 0), (2, 8, 0)):
             shape = dict(threads=threads, blocks=6, rows_per_wave=rpw, unroll=unr,
                          lds_matrix_bytes=lds)
             b = J.Batch(ctx, A11s, A12s, 8, 32, 16, tol, shape=shape)
@@ -76,18 +78,16 @@ def test_batched_tile_shapes(ctx, mixed):
             rc, ev, res, st, stats = b.run()
             assert rc == J.JL_OK and (st == 0).all(), (shape, st)
             X = [to_np(x).copy() for x in b.X]
-            if base is None:
-                base = (ev, res, X)
-                if ref is None:
-                    ref = ev
-                    for i, (A11, A12) in enumerate(probs):
-                        _check_problem(A11, A12, ev[i], X[i], res[i], tol, 1e-5 if mixed else 1e-10, 8)
-            else:
-                assert np.array_equal(ev, base[0]) and np.array_equal(res, base[1]), shape
-                for x, x0 in zip(X, base[2]):
-                    assert np.array_equal(x, x0), shape
             b.close()
-        assert np.abs(base[0] - ref).max() < (1e-5 if mixed else 1e-10) * np.abs(ref).max()
+            if rpw in base:   # same rows per wavefront: the same bits
+                ev0, res0, X0 = base[rpw]
+                assert np.array_equal(ev, ev0) and np.array_equal(res, res0), shape
+                for x, x0 in zip(X, X0):
+                    assert np.array_equal(x, x0), shape
+            else:
+                base[rpw] = (ev, res, X)
+                for i, (A11, A12) in enumerate(probs):
+                    _check_problem(A11, A12, ev[i], X[i], res[i], tol, gate, 8)
 
 
 def test_batched_exhausted_and_largest(ctx):
