@@ -537,7 +537,8 @@ def cpu_baseline(w, host, gpu_stats, budget_s):
 def probe(w, reps=3):
     """Kernel probe for hardware counters: a plain 1 GiB device copy (HBM
     calibration), then `reps` operator applies and J-restricted Gram-Schmidt
-    passes at the workload's shape (mixed precision, basis width 3m/4)."""
+    passes at the workload's shape (mixed precision, basis width 3m/4), and
+    `reps` restart products V_m Z (m basis vectors, k = 3m/5 Ritz vectors)."""
     import torch
     from paper_2001_07428_amd import jlanczos as J
     host = make_host_inputs(w)
@@ -549,14 +550,20 @@ def probe(w, reps=3):
     del x, y
     op = make_op(J, ctx, w, host, torch.complex64)
     ncol = (3 * w["m"]) // 4
+    kz = (3 * w["m"]) // 5
     g = torch.Generator(device="cuda:0").manual_seed(0)
-    V = torch.randn((ncol, op.n), dtype=torch.complex64, device="cuda:0", generator=g) / np.sqrt(op.n)
+    V = torch.randn((w["m"], op.n), dtype=torch.complex64, device="cuda:0", generator=g) / np.sqrt(op.n)
     u = torch.randn(op.n, dtype=torch.complex64, device="cuda:0", generator=g)
     for _ in range(reps):
         J.jl_op_apply(op, V[0], u)
-        J.jl_reorth_pass(ctx, V, u)
+        J.jl_reorth_pass(ctx, V[:ncol], u)
+    Z = torch.randn((w["m"], kz), dtype=torch.float64, device="cuda:0", generator=g)
+    for _ in range(reps):
+        Y = J.jl_basis_update(ctx, V, Z)
+        del Y
     torch.cuda.synchronize()
-    print(json.dumps(dict(probe=w, ncol=ncol, n=op.n, reps=reps, copy_bytes=2 * (1 << 30))), flush=True)
+    print(json.dumps(dict(probe=w, ncol=ncol, gemm_m=w["m"], gemm_k=kz, n=op.n, reps=reps,
+                          copy_bytes=2 * (1 << 30))), flush=True)
 
 
 def main():

@@ -253,9 +253,9 @@ hipError_t launch_norm2(const cplx<S>* x, int64_t n, double* part, hipStream_t s
 // and C of storage type S, B and the MFMA accumulation of type T
 // (instantiated: <float,double>, <double,double>).  With cmap (device, N
 // ints) column c of the product is stored to column cmap[c] of C.
-// Column tile of the GEMM (a launch computing N columns covers
-// ceil(N / kGemmTileN) tiles per row panel).
-constexpr int kGemmTileN = 128;
+// Narrowest column tile of the GEMM: a launch pads its N columns to a
+// multiple of kGemmTileN at most.
+constexpr int kGemmTileN = 32;
 template <typename S, typename T>
 hipError_t launch_gemm_nn(const S* A, int64_t lda, const T* B, int64_t ldb, S* C, int64_t ldc,
                           int64_t M, int N, int K, hipStream_t st, const int* cmap = nullptr);

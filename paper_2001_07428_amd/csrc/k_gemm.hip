@@ -10,12 +10,20 @@
 // Ritz-vector error of about sqrt(m) u_32 that puts the true-residual floor
 // above the mixed-precision tolerance.
 //
-// Block tile 128 x 128, 4 wavefronts in 2 x 2, each 64 x 64 = 4 x 4 MFMA
-// tiles (computed transposed so that stores run down the columns of C); K staged through LDS (as FP64) in steps of 8 with a
-// register prefetch of the next step and two LDS buffers (one barrier per
+// Block tile 128 x BN (BN = 128, 64 or 32), 4 wavefronts in 2 x 2, each
+// 64 x BN/2 = 4 x BN/32 MFMA tiles (computed transposed so that stores run
+// down the columns of C); K staged through LDS (as FP64) in steps of 8 with
+// a register prefetch of the next step and two LDS buffers (one barrier per
 // step).  Consecutive tiles of one row panel are placed on the same XCD so
-// the A panel is shared through that XCD's L2.
+// the A panel is shared through that XCD's L2.  A launch covers its N
+// columns with 128-wide tiles and finishes the remainder with a 64-wide
+// and a 32-wide tile, so at most 31 columns of MFMA work are padding
+// (measured at M = 2^24, K = 500, FP32 A: 58.8 TFLOP/s at N = 256; N = 300
+// in 128-wide tiles alone, 46.4 TFLOP/s).
 #include "common.h"
+
+#include <algorithm>
+#include <type_traits>
 
 namespace jl {
 namespace {
@@ -31,11 +39,11 @@ template <> struct Mfma<double> {
   }
 };
 
-constexpr int BM = 128, BN = kGemmTileN, PAD = 16, LDT = BM + PAD;
+constexpr int BM = 128, PAD = 16, LDT = BM + PAD;
 constexpr int kThreads = 256;
 
 // S: storage type of A and C; T: MFMA (accumulation) type, also the type of B.
-template <typename S, typename T>
+template <typename S, typename T, int BN>
 __global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A, int64_t lda,
                                                       const T* __restrict__ B, int64_t ldb,
                                                       S* __restrict__ C, int64_t ldc, int64_t M,
@@ -43,6 +51,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A
                                                       const int* __restrict__ cmap) {
   using MF = Mfma<T>;
   constexpr int BK = MF::BK;
+  constexpr int WN = BN / 2;                            // columns per wavefront
+  constexpr int NJ = WN / 16;                           // MFMA tiles per wavefront row
   constexpr int AV = 16 / sizeof(S);                    // elements per 16-byte load
   constexpr int A_PER_T = BM * BK / kThreads;           // A elements per thread per step
   constexpr int B_PER_T = BN * BK / kThreads;
@@ -119,11 +129,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A
     for (int e = 0; e < B_PER_T; ++e) Bs[buf][b_k + e][b_c] = rb[e] * (b_in[e] ? (T)1 : (T)0);
   };
 
-  typename MF::acc_t acc[4][4];
+  typename MF::acc_t acc[4][NJ];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
 
   const int nk = (K + BK - 1) / BK;
   load(0);
@@ -138,17 +148,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const int kr = ks * 4 + lane / 16;
-      T a[4], bb[4];
+      T a[4], bb[NJ];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = As[buf][kr][wm * 64 + i * 16 + lane % 16];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = Bs[buf][kr][wn * 64 + j * 16 + lane % 16];
+      for (int j = 0; j < NJ; ++j) bb[j] = Bs[buf][kr][wn * WN + j * 16 + lane % 16];
       // the transposed tile product (B^T A^T): the MFMA output then runs
       // along the rows of C in consecutive lanes
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = MF::op(bb[j], a[i], acc[i][j]);
+        for (int j = 0; j < NJ; ++j) acc[i][j] = MF::op(bb[j], a[i], acc[i][j]);
     }
   }
 
@@ -161,10 +171,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A
     const int64_t row = m0 + wm * 64 + i * 16 + lane % 16;
     if (row >= M) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NJ; ++j) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int col = n0 + wn * 64 + j * 16 + 4 * r + lane / 16;
+        const int col = n0 + wn * WN + j * 16 + 4 * r + lane / 16;
         if (col < N) C[(int64_t)(cmap ? cmap[col] : col) * ldc + row] = (S)acc[i][j][r];
       }
     }
@@ -172,6 +182,19 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm_nn(const S* __restrict__ A
 }
 
 }  // namespace
+
+template <typename S, typename T, int BN>
+hipError_t launch_tiles(const S* A, int64_t lda, const T* B, int64_t ldb, S* C, int64_t ldc, int64_t M,
+                        int N, int K, hipStream_t st, const int* cmap) {
+  const int64_t tm = (M + BM - 1) / BM;
+  const int tn = (N + BN - 1) / BN;
+  int64_t nblk = tm * tn;
+  nblk = (nblk + 7) / 8 * 8;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_gemm_nn<S, T, BN>), dim3((unsigned)nblk), dim3(kThreads), 0, st, A, lda, B, ldb,
+                     C, ldc, M, N, K, tm, tn, cmap);
+  return hipGetLastError();
+}
 
 template <typename S, typename T>
 hipError_t launch_gemm_nn(const S* A, int64_t lda, const T* B, int64_t ldb, S* C, int64_t ldc,
@@ -182,14 +205,23 @@ hipError_t launch_gemm_nn(const S* A, int64_t lda, const T* B, int64_t ldb, S* C
   const int AV = 16 / (int)sizeof(S);
   if ((lda % AV) || (ldc % AV) || (M % AV) || K <= 0 || ((uintptr_t)A % 16) || ((uintptr_t)C % 16))
     return hipErrorInvalidValue;
-  const int64_t tm = (M + BM - 1) / BM;
-  const int tn = (N + BN - 1) / BN;
-  int64_t nblk = tm * tn;
-  nblk = (nblk + 7) / 8 * 8;
-  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gemm_nn<S, T>), dim3((unsigned)nblk), dim3(kThreads), 0, st, A, lda, B, ldb,
-                     C, ldc, M, N, K, tm, tn, cmap);
-  return hipGetLastError();
+  // columns [c0, c0 + w) of the product: B and the output columns move with c0
+  auto part = [&](auto tile, int c0, int w) -> hipError_t {
+    constexpr int TB = decltype(tile)::value;
+    return launch_tiles<S, T, TB>(A, lda, B + (int64_t)c0 * ldb, ldb, cmap ? C : C + (int64_t)c0 * ldc,
+                                  ldc, M, w, K, st, cmap ? cmap + c0 : nullptr);
+  };
+  hipError_t e = hipSuccess;
+  int full = N / 128 * 128;
+  if (N - full > 96) full = N;   // the last 128-wide tile then pads fewer than 32 columns
+  if (full > 0) e = part(std::integral_constant<int, 128>{}, 0, full);
+  int c0 = full;
+  if (e == hipSuccess && N - c0 > 32) {
+    e = part(std::integral_constant<int, 64>{}, c0, std::min(64, N - c0));
+    c0 += 64;
+  }
+  if (e == hipSuccess && N - c0 > 0) e = part(std::integral_constant<int, 32>{}, c0, N - c0);
+  return e;
 }
 
 template hipError_t launch_gemm_nn<float, double>(const float*, int64_t, const double*, int64_t,

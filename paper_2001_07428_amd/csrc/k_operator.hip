@@ -216,6 +216,21 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const X& x
 
 constexpr int kStencilThreads = 256;
 
+// Site block of this workgroup.  Workgroups are dealt to the eight XCDs in
+// turn (workgroup b runs on XCD b mod 8).  When every x0-plane is a whole
+// number of 8 blocks, workgroup b takes the block that gives each XCD one
+// eighth of every plane, planes in increasing order: the operand one plane
+// back or ahead, and the link of the backward hop in x0, were then read a
+// short while before by the same XCD and come from its L2 (measured at 32^4:
+// 1.25 -> 1.05 GB fetched per FP32 apply, 183 -> 175 us).  Otherwise the
+// identity.
+__device__ __forceinline__ int64_t stencil_site_block(const int32_t L[4]) {
+  const int64_t P = (int64_t)L[1] * L[2] * L[3];
+  if (P % (8 * kStencilThreads) != 0) return blockIdx.x;
+  const int64_t bx = P / (8 * kStencilThreads), b = blockIdx.x, k = b >> 3;
+  return (k / bx) * (8 * bx) + (b & 7) * bx + k % bx;
+}
+
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh);
 
@@ -234,7 +249,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply(StencilArgs<S
                                                                    cplx<S>* __restrict__ pnew) {
   if (a.skip && *a.skip != 0.0) return;   // uniform over the grid
   __shared__ double sh[kStencilThreads / 64];
-  const int64_t s = (int64_t)blockIdx.x * kStencilThreads + threadIdx.x;
+  const int64_t s = stencil_site_block(a.L) * kStencilThreads + threadIdx.x;
   const int64_t h = a.V * 4;
   Operand<S, DIR> xo;
   if constexpr (DIR) xo = Operand<S, true>{dr, x, *dbeta};

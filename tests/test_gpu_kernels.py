@@ -195,11 +195,14 @@ def test_ritz(ctx, m, which):
 
 # -------------------------------------------------------------- restart GEMM
 @pytest.mark.parametrize("h,m,k", [(1000, 37, 29), (2048, 160, 130), (50, 3, 3), (3000, 129, 1),
-                                   (6144, 300, 250)])
+                                   (6144, 300, 250), (2048, 160, 80), (2048, 160, 100),
+                                   (1000, 200, 50), (6144, 300, 300), (2048, 256, 208)])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_basis_update(ctx, h, m, k, mixed):
     """V_k = V_m Z[:, :k] (Alg. 1) as a real GEMM on the interleaved basis,
-    FP64 accumulation for both storage types (mixed: one final rounding)."""
+    FP64 accumulation for both storage types (mixed: one final rounding).
+    The k values reach every split of the columns over 128-, 64- and 32-wide
+    tiles."""
     from paper_2001_07428_amd import jlanczos as J
     say("basis_update", h, m, k, mixed)
     rng = np.random.default_rng(7)
