@@ -535,8 +535,8 @@ def cpu_baseline(w, host, gpu_stats, budget_s):
 
 
 def probe(w, reps=3):
-    """Kernel probe for hardware counters: a plain 1 GiB device copy (HBM
-    calibration), then `reps` operator applies and J-restricted Gram-Schmidt
+    """Kernel probe for hardware counters: a plain 1 GiB elementwise pass,
+    y = -x (HBM calibration: 1 GiB read, 1 GiB written), then `reps` operator applies and J-restricted Gram-Schmidt
     passes at the workload's shape (mixed precision, basis width 3m/4), and
     `reps` restart products V_m Z (m basis vectors, k = 3m/5 Ritz vectors)."""
     import torch
@@ -545,8 +545,8 @@ def probe(w, reps=3):
     ctx = J.Context(0)
     x = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").uniform_()
     y = torch.empty_like(x)
-    for _ in range(reps):
-        y.copy_(x)
+    for _ in range(reps):   # y = -x: one elementwise kernel reading and writing 1 GiB
+        torch.neg(x, out=y)
     del x, y
     op = make_op(J, ctx, w, host, torch.complex64)
     ncol = (3 * w["m"]) // 4

@@ -288,7 +288,10 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   L.upd_part = take(sizeof(double) * (size_t)std::max(reorth_update_blocks(h, es), 1));
   L.coef = take(sizeof(double) * (4 * (size_t)(m + 1) + 1));
   const int wcols = dots_stride(m + 1);   // the most inner products one pass reduces
-  L.wide_scr = take(sizeof(double) * reduce_wide_scratch_doubles(reorth_dots_blocks(h, es), wcols));
+  // the slice sums of the wide reductions: the inner products of a pass, and
+  // the true residuals of up to nev candidates (fewer columns than wcols)
+  L.wide_scr = take(sizeof(double) * std::max(reduce_wide_scratch_doubles(reorth_dots_blocks(h, es), wcols),
+                                              reduce_wide_scratch_doubles(op_resid_blocks(op), p->nev)));
   L.wide_cnt = take(sizeof(unsigned) * ((size_t)reduce_wide_tiles(wcols) + 1));   // + update norm
   L.scal = take(sizeof(double) * 64);
   L.Tdev = take(sizeof(double) * (size_t)m * m);
@@ -926,7 +929,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
       JL_HIP(ctx, hipMemcpyAsync(res_lam, h_rlam, sizeof(double) * ncand, hipMemcpyHostToDevice, st));
       int nrb = 0;
       JL_HIP(ctx, op_resid<S>(op, Vn, ldv, res_cols, h_rcols, res_lam, ncand, res_part, &nrb, st));
-      JL_HIP(ctx, launch_reduce_cols(res_part, nrb, ncand, ncand, res_dev, st));
+      JL_HIP(ctx, launch_reduce_wide(res_part, nrb, ncand, ncand, res_dev, wide_scr, wide_cnt, st));
       JL_HIP(ctx, hipMemcpyAsync(h_res, res_dev, sizeof(double) * ncand, hipMemcpyDeviceToHost, st));
       tm.stop();
       JL_HIP(ctx, hipStreamSynchronize(st));

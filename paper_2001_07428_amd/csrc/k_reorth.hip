@@ -527,10 +527,20 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ 
   __shared__ double sh[256];
   const int tx = threadIdx.x % C, ty = threadIdx.x / C;
   const int c = blockIdx.x * C + tx;
-  double s = 0.0;
-  if (c < ncols)
-    for (int b = ty; b < nblk; b += G) s += partial[(int64_t)b * stride + c];
-  sh[threadIdx.x] = s;
+  // four independent running sums per thread (more loads in flight), added
+  // in a fixed order
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (c < ncols) {
+    int b = ty;
+    for (; b + 3 * G < nblk; b += 4 * G) {
+      s0 += partial[(int64_t)b * stride + c];
+      s1 += partial[(int64_t)(b + G) * stride + c];
+      s2 += partial[(int64_t)(b + 2 * G) * stride + c];
+      s3 += partial[(int64_t)(b + 3 * G) * stride + c];
+    }
+    for (; b < nblk; b += G) s0 += partial[(int64_t)b * stride + c];
+  }
+  sh[threadIdx.x] = (s0 + s1) + (s2 + s3);
   __syncthreads();
 #pragma unroll
   for (int g = G / 2; g > 0; g /= 2) {

@@ -532,7 +532,7 @@ class Batch:
                 self.tuned = True
             else:
                 import warnings
-                warnings.warn("no tuned launch shape for this batch and device "
+                warnings.warn(f"no tuned launch shape for this batch and device {tune.device_key()} "
                               "(python -m paper_2001_07428_amd.tune): library defaults")
                 shape = {}
         self._shape = JlBatchShape(**{k: int(v) for k, v in shape.items()})

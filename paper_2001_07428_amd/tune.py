@@ -51,10 +51,12 @@ def signature(n, nev, m, dtype_name):
 
 
 def device_key():
+    """Architecture and compute-unit count (the marketing name is left out: it
+    depends on the driver's device-id table, which some systems lack)."""
     import torch
     p = torch.cuda.get_device_properties(0)
     arch = getattr(p, "gcnArchName", "") or ""
-    return f"{p.name}|{arch.split(':')[0]}|cu={p.multi_processor_count}"
+    return f"{arch.split(':')[0]}|cu={p.multi_processor_count}"
 
 
 def lookup(n, nev, m, dtype_name):
