@@ -254,6 +254,15 @@ def run_batched(J, ctx, w, host, mixed, steps, warmup):
                    (res / np.maximum(np.abs(ev).max(axis=1, keepdims=True), 1.0)).max()),
                matvec_bytes=mv_bytes, resid_apply_bytes=res_bytes, evals=ev, shape=shape,
                tuned_shape=tuned)
+    # workgroup time per phase, summed over the problems (device wall clock)
+    phases = ("apply", "gs", "ritz", "restart", "resid")
+    tot = {ph: float(stats["t_" + ph].sum()) for ph in phases}
+    allt = sum(tot.values())
+    out["phase_seconds"] = {ph: round(v, 6) for ph, v in tot.items()}
+    out["phase_share"] = {ph: round(v / allt, 4) if allt > 0 else None for ph, v in tot.items()}
+    # the problem whose solve ends last sets the launch's critical path
+    per = sum(stats["t_" + ph] for ph in phases)
+    out["longest_problem_seconds"] = float(per.max())
     del b, A11s, A12s
     torch.cuda.empty_cache()
     return out

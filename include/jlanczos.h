@@ -313,6 +313,13 @@ typedef struct {
   int32_t gs_passes;    /* reorthogonalisation passes                           */
   int32_t icnv;         /* converged pairs                                      */
   int32_t n_resid;      /* operator applies spent on true-residual checks       */
+  /* Seconds the problem's workgroup spent in each phase, from the device's
+   * constant-rate wall clock read where the workgroup is in step: the operator
+   * apply of the Lanczos steps; the J-restricted Gram-Schmidt passes with the
+   * normalisation (and the start and restart bookkeeping); the Rayleigh-Ritz
+   * step (in-LDS Jacobi, sort); the restart product V_m Z; the true-residual
+   * checks.  Their sum is the problem's time in the solver. */
+  double t_apply, t_gs, t_ritz, t_restart, t_resid;
 } jl_batch_stats;
 
 jl_status jl_batch_workspace_bytes(int32_t count, const int64_t* n, jl_dtype dtype,

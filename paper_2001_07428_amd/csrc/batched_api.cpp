@@ -20,6 +20,7 @@ struct jl_batch_s {
   hipGraphExec_t exec = nullptr;
   hipEvent_t ready = nullptr;
   double* h_out = nullptr;   // pinned: evals, res, status, stats
+  double tick_s = 0.0;       // seconds per tick of the device wall clock
 };
 
 namespace {
@@ -163,6 +164,12 @@ jl_status jl_batch_create(jl_ctx ctx, int32_t count, const int64_t* n, const voi
     return fail(set_err(ctx, JL_EHIP, "%s failed: %s", #expr, hipGetErrorString(e)));
   BCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   BCHK(hipEventCreateWithFlags(&b->ready, hipEventDisableTiming));
+  {
+    int dev = 0, khz = 0;
+    BCHK(hipGetDevice(&dev));
+    BCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    b->tick_s = khz > 0 ? 1e-3 / khz : 0.0;
+  }
   // doubles: evals, res, then the ints status [count] and stats [count][kBatchStats]
   const size_t nout = 2 * (size_t)count * p->nev + ((size_t)(1 + kBatchStats) * count + 1) / 2;
   BCHK(hipHostMalloc((void**)&b->h_out, sizeof(double) * nout, hipHostMallocDefault));
@@ -237,6 +244,9 @@ jl_status jl_batch_run(jl_batch b, double* evals, double* res, int32_t* status,
       stats[i].gs_passes = h_stats[kBatchStats * i + 2];
       stats[i].icnv = h_stats[kBatchStats * i + 3];
       stats[i].n_resid = h_stats[kBatchStats * i + 4];
+      double* t[kBatchPhases] = {&stats[i].t_apply, &stats[i].t_gs, &stats[i].t_ritz, &stats[i].t_restart,
+                                 &stats[i].t_resid};
+      for (int ph = 0; ph < kBatchPhases; ++ph) *t[ph] = b->tick_s * h_stats[kBatchStats * i + 5 + ph];
     }
   }
   return all ? JL_OK : JL_NOT_CONVERGED;

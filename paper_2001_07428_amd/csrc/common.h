@@ -310,12 +310,16 @@ struct BatchParams {
   int lds_mat;        // LDS bytes per workgroup for a resident [A11 A12] (0: none)
   double tol;
 };
-constexpr int kBatchStats = 5;   // per-problem counters of the batched solve
+// per-problem counters of the batched solve: cycles, n_mv, gs_passes, icnv,
+// n_resid, then the device wall-clock ticks (constant rate) its workgroup spent
+// in each phase (kBatchPhases of them)
+constexpr int kBatchPhases = 5;   // apply, Gram-Schmidt, Rayleigh-Ritz, restart V Z, residuals
+constexpr int kBatchStats = 5 + kBatchPhases;
 struct BatchOut {
   double* evals;      // [count][nev]
   double* res;        // [count][nev]
   int* status;        // [count]
-  int* stats;         // [count][kBatchStats]: cycles, n_mv, gs_passes, icnv, n_resid
+  int* stats;         // [count][kBatchStats]: cycles, n_mv, gs_passes, icnv, n_resid, phase ticks
 };
 size_t batched_lds_bytes(int64_t hmax, int m, int es);   // without the resident-matrix budget
 size_t batched_slot_bytes(int64_t hmax, int m, int es);

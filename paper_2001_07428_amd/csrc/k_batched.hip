@@ -416,6 +416,14 @@ __device__ void solve_one(const BatchProblem& pg, int pid, const BatchParams& P,
   __syncthreads();
   auto Tat = [&](int i, int j) -> double& { return L.T[i + j * (m + 1)]; };
   int k = 0, icnv = 0, status = 1, n_mv = 0, passes_tot = 0, cycles = 0, n_resid = 0;
+  // wall-clock ticks per phase (read at points where the workgroup is in step)
+  long long ph[kBatchPhases] = {};
+  long long t_mark = wall_clock64();
+  auto phase = [&](int i) {
+    const long long t = wall_clock64();
+    ph[i] += t - t_mark;
+    t_mark = t;
+  };
   double maxT = 0.0, tol_scale = 0.0;
   const double sqrt2 = 1.4142135623730951;
   for (int cycle = 0; cycle < P.max_cycles; ++cycle) {
@@ -427,7 +435,9 @@ __device__ void solve_one(const BatchProblem& pg, int pid, const BatchParams& P,
     for (int j = k; j < m; ++j) {
       cplx<S>* u = V + (int64_t)(j + 1) * n;
       double tre, tim;
+      phase(1);   // the previous step's normalisation belongs to Gram-Schmidt
       wg_apply<S, S, NT, RPW, UNR>(pb, V + (int64_t)j * n, u, L, &tre, &tim);
+      phase(0);
       ++n_mv;
       const double beta_prev = (j > k) ? Tat(j, j - 1) : 0.0;
       wg_dots<S, NT>(V, n, j + 1, u, h, L, true, tre, tim, beta_prev, j);
@@ -463,6 +473,7 @@ __device__ void solve_one(const BatchProblem& pg, int pid, const BatchParams& P,
       maxT = fmax(maxT, b1);
       __syncthreads();
     }
+    phase(1);
     if (meff < nev) { status = 2; icnv = 0; break; }
     // ---- Rayleigh-Ritz in LDS
     const int mp = meff + (meff & 1);
@@ -494,6 +505,7 @@ __device__ void solve_one(const BatchProblem& pg, int pid, const BatchParams& P,
       L.svec[r] = beta_m * L.JZ[(meff - 1) + src * mp];
     }
     __syncthreads();
+    phase(2);
     // ---- V_k := V_m Z[:, perm[0:kcols]], FP64 accumulation, four output
     // columns per read of V
     const int kcols = min(kmax, meff);
@@ -528,6 +540,7 @@ __device__ void solve_one(const BatchProblem& pg, int pid, const BatchParams& P,
       }
     }
     __syncthreads();
+    phase(3);
     // ---- true residuals of the candidates
     tol_scale = fmax(tol_scale, fmax(fabs(L.lam[0]), fabs(L.lam[meff - 1])));
     const double tolc = P.tol_relative ? P.tol * tol_scale : P.tol;
@@ -558,6 +571,7 @@ __device__ void solve_one(const BatchProblem& pg, int pid, const BatchParams& P,
       }
       __syncthreads();
     }
+    phase(4);
     icnv = 0;
     for (int i = 0; i < nev; ++i) icnv += L.conv[i];
     if (tid == 0) {
@@ -615,6 +629,8 @@ __device__ void solve_one(const BatchProblem& pg, int pid, const BatchParams& P,
     out.stats[kBatchStats * pid + 2] = passes_tot;
     out.stats[kBatchStats * pid + 3] = icnv;
     out.stats[kBatchStats * pid + 4] = n_resid;
+#pragma unroll
+    for (int i = 0; i < kBatchPhases; ++i) out.stats[kBatchStats * pid + 5 + i] = (int)min(ph[i], 0x7fffffffLL);
   }
   __syncthreads();
 }

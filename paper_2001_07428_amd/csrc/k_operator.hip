@@ -319,12 +319,13 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {   // result 
 // column (row r of U_mu(s), column r of U_mu(s - mu)); the four directions of
 // a row are summed across lanes.  The site-independent B sits in LDS (per-site
 // B is read per use).  FP64 products and accumulation on the stored vectors.
-// The columns are split into groups of kResidCols over gridDim.y (the links
-// are read once per group; a block walks its group's columns in turn).
+// A block walks the columns of its group (cpb of them; gridDim.y groups) in
+// chunks of kResidCols with the links in registers, so the links are read
+// once per group: once in all when the site blocks alone fill the device.
 // partial[blk * ncols + c] = the share of column c of site block blk
 // (stencil_resid_blocks blocks).
 constexpr int kResidSites = kStencilThreads / 16;   // sites per block
-constexpr int kResidCols = 16;                       // columns per block
+constexpr int kResidCols = 16;                       // columns per chunk
 
 template <typename S, bool BSITE>
 __global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S> a,
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S
                                                                    int64_t ldx,
                                                                    const int* __restrict__ cols,
                                                                    const double* __restrict__ lam,
-                                                                   int ncols,
+                                                                   int ncols, int cpb,
                                                                    double* __restrict__ partial) {
   __shared__ cplx<S> Bs[64];
   __shared__ double red[kStencilThreads / 64][kResidCols];   // per-wavefront column sums
@@ -366,68 +367,72 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_resid(StencilArgs<S
   const cplx<S>* Bm = Bs + mu * 16;   // site-independent B
   const double dg = a.diag, sc = a.scale;
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-  const int col0 = (int)blockIdx.y * kResidCols, col1 = min(ncols, col0 + kResidCols);
-  for (int col = col0; col < col1; ++col) {
-    const int cc = col - col0;
-    const cplx<S>* x = X + (int64_t)cols[col] * ldx;
-    double tr = 0.0, ti = 0.0, br = 0.0, bi = 0.0;   // row r, direction mu
-    if (mu == 0) {   // (diag - l) x(s), once per row
-      const double l = lam[col];
-      const cplx<S> xa = x[s * 4 + r], xb = x[h + s * 4 + r];
-      tr = (dg - l) * (double)xa.x; ti = (dg - l) * (double)xa.y;
-      br = (dg - l) * (double)xb.x; bi = (dg - l) * (double)xb.y;
-    }
-    {   // forward: U(s) a(s+mu), conj(U(s)) b(s+mu), B b(s+mu), conj(B) a(s+mu)
-      double ar[4], ai[4], vr[4], vi[4];
-      load_site<S, double>(x + sf * 4, ar, ai);
-      load_site<S, double>(x + h + sf * 4, vr, vi);
-      cx<double> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const cplx<S> wv = BSITE ? a.B[link_index(s, mu, 4 * r + c)] : Bm[4 * r + c];
-        const double ur = uf[c].x, ui = uf[c].y, wr = wv.x, wi = wv.y;
-        mac(t, ur, ui, ar[c], ai[c]);
-        mac_conj_a(q, ur, ui, vr[c], vi[c]);
-        mac(tb, wr, wi, vr[c], vi[c]);
-        mac_conj_a(qb, wr, wi, ar[c], ai[c]);
+  const int colA = (int)blockIdx.y * cpb, colB = min(ncols, colA + cpb);
+  for (int col0 = colA; col0 < colB; col0 += kResidCols) {
+    const int col1 = min(colB, col0 + kResidCols);
+    for (int col = col0; col < col1; ++col) {
+      const int cc = col - col0;
+      const cplx<S>* x = X + (int64_t)cols[col] * ldx;
+      double tr = 0.0, ti = 0.0, br = 0.0, bi = 0.0;   // row r, direction mu
+      if (mu == 0) {   // (diag - l) x(s), once per row
+        const double l = lam[col];
+        const cplx<S> xa = x[s * 4 + r], xb = x[h + s * 4 + r];
+        tr = (dg - l) * (double)xa.x; ti = (dg - l) * (double)xa.y;
+        br = (dg - l) * (double)xb.x; bi = (dg - l) * (double)xb.y;
       }
-      tr += sc * tb.re - t.re; ti += sc * tb.im - t.im;
-      br -= q.re + sc * qb.re; bi -= q.im + sc * qb.im;
-    }
-    {   // backward: U(s-mu)^H a, U(s-mu)^T b, B(s-mu)^T b, B(s-mu)^H a at s - mu
-      double ar[4], ai[4], vr[4], vi[4];
-      load_site<S, double>(x + sb * 4, ar, ai);
-      load_site<S, double>(x + h + sb * 4, vr, vi);
-      cx<double> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
+      {   // forward: U(s) a(s+mu), conj(U(s)) b(s+mu), B b(s+mu), conj(B) a(s+mu)
+        double ar[4], ai[4], vr[4], vi[4];
+        load_site<S, double>(x + sf * 4, ar, ai);
+        load_site<S, double>(x + h + sf * 4, vr, vi);
+        cx<double> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const cplx<S> wv = BSITE ? a.B[link_index(sb, mu, 4 * c + r)] : Bm[4 * c + r];
-        const double ur = ub[c].x, ui = ub[c].y, wr = wv.x, wi = wv.y;
-        mac_conj_a(t, ur, ui, ar[c], ai[c]);
-        mac(q, ur, ui, vr[c], vi[c]);
-        mac(tb, wr, wi, vr[c], vi[c]);
-        mac_conj_a(qb, wr, wi, ar[c], ai[c]);
+        for (int c = 0; c < 4; ++c) {
+          const cplx<S> wv = BSITE ? a.B[link_index(s, mu, 4 * r + c)] : Bm[4 * r + c];
+          const double ur = uf[c].x, ui = uf[c].y, wr = wv.x, wi = wv.y;
+          mac(t, ur, ui, ar[c], ai[c]);
+          mac_conj_a(q, ur, ui, vr[c], vi[c]);
+          mac(tb, wr, wi, vr[c], vi[c]);
+          mac_conj_a(qb, wr, wi, ar[c], ai[c]);
+        }
+        tr += sc * tb.re - t.re; ti += sc * tb.im - t.im;
+        br -= q.re + sc * qb.re; bi -= q.im + sc * qb.im;
       }
-      tr -= t.re + sc * tb.re; ti -= t.im + sc * tb.im;
-      br += sc * qb.re - q.re; bi += sc * qb.im - q.im;
+      {   // backward: U(s-mu)^H a, U(s-mu)^T b, B(s-mu)^T b, B(s-mu)^H a at s - mu
+        double ar[4], ai[4], vr[4], vi[4];
+        load_site<S, double>(x + sb * 4, ar, ai);
+        load_site<S, double>(x + h + sb * 4, vr, vi);
+        cx<double> t = {0, 0}, q = {0, 0}, tb = {0, 0}, qb = {0, 0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const cplx<S> wv = BSITE ? a.B[link_index(sb, mu, 4 * c + r)] : Bm[4 * c + r];
+          const double ur = ub[c].x, ui = ub[c].y, wr = wv.x, wi = wv.y;
+          mac_conj_a(t, ur, ui, ar[c], ai[c]);
+          mac(q, ur, ui, vr[c], vi[c]);
+          mac(tb, wr, wi, vr[c], vi[c]);
+          mac_conj_a(qb, wr, wi, ar[c], ai[c]);
+        }
+        tr -= t.re + sc * tb.re; ti -= t.im + sc * tb.im;
+        br += sc * qb.re - q.re; bi += sc * qb.im - q.im;
+      }
+      // the four directions of row r: lanes that differ in bits 2 and 3
+#pragma unroll
+      for (int o = 4; o <= 8; o <<= 1) {
+        tr += __shfl_xor(tr, o); ti += __shfl_xor(ti, o);
+        br += __shfl_xor(br, o); bi += __shfl_xor(bi, o);
+      }
+      double acc = (ok && mu == 0) ? tr * tr + ti * ti + br * br + bi * bi : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (lane == 0) red[w][cc] = acc;   // only this wavefront writes red[w]: no barrier per column
     }
-    // the four directions of row r: lanes that differ in bits 2 and 3
+    __syncthreads();
+    for (int i = threadIdx.x; col0 + i < col1; i += kStencilThreads) {
+      double tot = 0.0;
 #pragma unroll
-    for (int o = 4; o <= 8; o <<= 1) {
-      tr += __shfl_xor(tr, o); ti += __shfl_xor(ti, o);
-      br += __shfl_xor(br, o); bi += __shfl_xor(bi, o);
+      for (int k = 0; k < kStencilThreads / 64; ++k) tot += red[k][i];
+      partial[(int64_t)blockIdx.x * ncols + col0 + i] = tot;
     }
-    double acc = (ok && mu == 0) ? tr * tr + ti * ti + br * br + bi * bi : 0.0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (lane == 0) red[w][cc] = acc;   // only this wavefront writes red[w]: no barrier per column
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; col0 + i < col1; i += kStencilThreads) {
-    double tot = 0.0;
-#pragma unroll
-    for (int k = 0; k < kStencilThreads / 64; ++k) tot += red[k][i];
-    partial[(int64_t)blockIdx.x * ncols + col0 + i] = tot;
+    __syncthreads();   // red is rewritten by the next chunk
   }
 }
 
@@ -673,13 +678,18 @@ hipError_t launch_stencil_resid(const StencilArgs<S>& a, const cplx<S>* X, int64
   const int nb = stencil_resid_blocks(a.V);
   *nblk = nb;
   if (ncols <= 0) return hipSuccess;
-  const dim3 grid((unsigned)nb, (unsigned)((ncols + kResidCols - 1) / kResidCols));
+  // column groups only as far as the site blocks alone leave the device short
+  // of about 2048 workgroups (the links are read once per group)
+  const int chunks = (ncols + kResidCols - 1) / kResidCols;
+  const int groups = std::max(1, std::min(chunks, (2048 + nb - 1) / nb));
+  const int cpb = (chunks + groups - 1) / groups * kResidCols;
+  const dim3 grid((unsigned)nb, (unsigned)((ncols + cpb - 1) / cpb));
   if (a.b_per_site)
     hipLaunchKernelGGL((k_stencil_resid<S, true>), grid, dim3(kStencilThreads), 0, st, a, X, ldx,
-                       cols, lam, ncols, partial);
+                       cols, lam, ncols, cpb, partial);
   else
     hipLaunchKernelGGL((k_stencil_resid<S, false>), grid, dim3(kStencilThreads), 0, st, a, X, ldx,
-                       cols, lam, ncols, partial);
+                       cols, lam, ncols, cpb, partial);
   return hipGetLastError();
 }
 

@@ -87,7 +87,9 @@ class JlBatchShape(ctypes.Structure):
 class JlBatchStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int32), ("n_mv", ctypes.c_int32),
                 ("gs_passes", ctypes.c_int32), ("icnv", ctypes.c_int32),
-                ("n_resid", ctypes.c_int32)]
+                ("n_resid", ctypes.c_int32), ("t_apply", ctypes.c_double),
+                ("t_gs", ctypes.c_double), ("t_ritz", ctypes.c_double),
+                ("t_restart", ctypes.c_double), ("t_resid", ctypes.c_double)]
 
 
 _lib = None

@@ -45,12 +45,22 @@ def test_batched_small_vs_brute(ctx, mixed):
     dt = cdt(mixed)
     b = J.Batch(ctx, [to_dev(a, dt) for a, _ in probs], [to_dev(c, dt) for _, c in probs],
                 8, 32, 16, 1e-4 if mixed else 1e-9)
+    import time
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     rc, ev, res, st, stats = b.run()
+    wall = time.perf_counter() - t0
     assert rc == J.JL_OK and (st == 0).all(), st
     for i, (A11, A12) in enumerate(probs):
         _check_problem(A11, A12, ev[i], to_np(b.X[i]), res[i], 1e-4 if mixed else 1e-9,
                        1e-5 if mixed else 1e-10, 8)
     assert (stats["n_mv"] > 0).all() and (stats["icnv"] == 8).all()
+    # phase times: every phase ran, and no problem's solve outlasts the replay
+    per = sum(stats[f] for f in ("t_apply", "t_gs", "t_ritz", "t_restart", "t_resid"))
+    for f in ("t_apply", "t_gs", "t_ritz", "t_restart", "t_resid"):
+        assert (stats[f] > 0).all(), f
+    assert (per <= wall).all(), (per.max(), wall)
 
 
 @pytest.mark.parametrize("mixed", [False, True])
