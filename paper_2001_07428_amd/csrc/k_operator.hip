@@ -177,9 +177,9 @@ __device__ __forceinline__ void hop_bwd(const StencilArgs<S>& a, const cplx<S>* 
 // with each entry's sites spread over the whole lattice).  Without
 // BSITE, B holds the 4 direction matrices B_mu (16 entries each), read at
 // wavefront-uniform addresses (scalar loads); with BSITE it has the layout of
-// U.  One direction and one hop are live at a time.  Directions MU0 .. 3;
-// with MU0 > 0 the caller has set (top, bot) and done the directions below.
-template <typename S, typename C, bool BSITE, typename X, int MU0 = 0>
+// U.  One direction and one hop are live at a time.  Directions MU0 .. MU1-1;
+// with MU0 > 0 the caller has set (top, bot) and does the other directions.
+template <typename S, typename C, bool BSITE, typename X, int MU0 = 0, int MU1 = 4>
 __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const X& xo, int64_t h,
                                              int64_t s, cx<C> top[4], cx<C> bot[4]) {
   // site coordinates in 32 bits (the lattice has fewer than 2^31 sites)
@@ -207,7 +207,7 @@ __device__ __forceinline__ void stencil_site(const StencilArgs<S>& a, const X& x
   }
   const int64_t V = a.V;
 #pragma unroll 1
-  for (int mu = MU0; mu < 4; ++mu) {
+  for (int mu = MU0; mu < MU1; ++mu) {
     const int64_t sf = (x[mu] == Ls[mu] - 1) ? s - (int64_t)((Ls[mu] - 1) * st[mu]) : s + st[mu];
     const int64_t sb = (x[mu] == 0) ? s + (int64_t)((Ls[mu] - 1) * st[mu]) : s - st[mu];
     const cplx<S>* Bm = a.B + mu * 16;   // site-independent B
@@ -355,9 +355,11 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_apply(StencilArgs<S
 // gives XCD b mod 8 one eighth of every plane pair, pairs in increasing order.
 // Each thread stages its site's operand, and in the first plane its x0 link,
 // in LDS, so the x0 hops between the two planes of the brick take both from
-// LDS instead of fetching them again (the directions 1..3 as in
-// k_stencil_apply).  Measured at 32^4 in a standalone harness: 166 against
-// 178 us, 0.94 against 1.05 GB fetched; four planes per brick saved no more.
+// LDS instead of fetching them again; in directions 2 and 3 the neighbours
+// inside the brick take their operand from LDS too (links from memory).
+// Measured at 32^4: 168 -> 155 us in the solve for the x0 sharing (in a
+// standalone harness 0.94 against 1.05 GB fetched; four planes per brick
+// saved no more), 153.7 -> 151.0 us for the in-plane operands.
 constexpr int kBrickZ = 2, kBrickS = kStencilThreads / kBrickZ;
 
 template <typename S, bool DIR>
@@ -443,7 +445,50 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_brick(StencilArgs<S
     __builtin_amdgcn_sched_barrier(0);
     hop_bwd<S, S, false>(a, a.B, s, 0, lb, sc, ar, ai, br, bi, top, bot);
   }
-  stencil_site<S, S, false, Operand<S, DIR>, 1>(a, xo, h, s, top, bot);
+  stencil_site<S, S, false, Operand<S, DIR>, 1, 2>(a, xo, h, s, top, bot);
+  // directions 2 and 3: neighbours inside the brick's in-plane sites take the
+  // operand from LDS, the others (and every link) from memory
+  {
+    const unsigned L2 = (unsigned)a.L[2], L3 = (unsigned)a.L[3];
+    const unsigned qi = (unsigned)q, x3 = qi % L3, x2 = (qi / L3) % L2;
+    const int64_t zP = (int64_t)z * P, q0 = c * kBrickS;
+#pragma unroll 1
+    for (int mu = 2; mu < 4; ++mu) {
+      const unsigned xm = mu == 2 ? x2 : x3, Lm = mu == 2 ? L2 : L3, sm = mu == 2 ? L3 : 1u;
+      const int64_t qf = xm == Lm - 1 ? (int64_t)qi - (int64_t)(Lm - 1) * sm : (int64_t)qi + sm;
+      const int64_t qb = xm == 0 ? (int64_t)qi + (int64_t)(Lm - 1) * sm : (int64_t)qi - sm;
+      {
+        S ar[4], ai[4], br[4], bi[4];
+        cplx<S> lf[16];
+        const int64_t i = qf - q0;
+        if (i >= 0 && i < kBrickS) {
+          from_lds(zl * kBrickS + (int)i, ar, ai, br, bi);
+        } else {
+          xo.template site<S>((zP + qf) * 4, ar, ai);
+          xo.template site<S>(h + (zP + qf) * 4, br, bi);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) lf[e] = a.U[link_index(s, mu, e)];
+        __builtin_amdgcn_sched_barrier(0);
+        hop_fwd<S, S, false>(a, a.B + mu * 16, s, mu, lf, sc, ar, ai, br, bi, top, bot);
+      }
+      {
+        S ar[4], ai[4], br[4], bi[4];
+        cplx<S> lb[16];
+        const int64_t i = qb - q0;
+        if (i >= 0 && i < kBrickS) {
+          from_lds(zl * kBrickS + (int)i, ar, ai, br, bi);
+        } else {
+          xo.template site<S>((zP + qb) * 4, ar, ai);
+          xo.template site<S>(h + (zP + qb) * 4, br, bi);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) lb[e] = a.U[link_index(zP + qb, mu, e)];
+        __builtin_amdgcn_sched_barrier(0);
+        hop_bwd<S, S, false>(a, a.B + mu * 16, s, mu, lb, sc, ar, ai, br, bi, top, bot);
+      }
+    }
+  }
   store_site<S, S>(yc + s * 4, top);
   store_site<S, S>(yc + h + s * 4, bot);
   double are = 0.0, aim = 0.0;
