@@ -380,9 +380,11 @@ def cpu_baseline_batched(w, host, budget_s):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return dict(value=dt / done * w["count"], unit="s", cores=os.cpu_count(), kind="oracle",
+    blas_threads, phys, logical = host_cores()
+    return dict(value=dt / done * w["count"], unit="s", cores=blas_threads, kind="oracle",
                 sample=f"{done} of {w['count']} problems solved by the FP64 oracle in {dt:.1f} s, "
-                       f"mean time per problem scaled to {w['count']} (extrapolated)")
+                       f"mean time per problem scaled to {w['count']} (extrapolated); "
+                       f"{blas_threads} BLAS threads on {phys} physical cores / {logical} logical CPUs")
 
 
 def main_cycles(args, J, ctx, w, host):
@@ -485,16 +487,27 @@ def traffic_for(kernel, workload):
         return None
 
 
+def host_cores():
+    """(BLAS threads the oracle's NumPy calls use, physical cores, logical CPUs)."""
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas = None
+    try:
+        import psutil
+        phys = psutil.cpu_count(logical=False)
+    except Exception:
+        phys = None
+    return blas, phys, os.cpu_count()
+
+
 def cpu_baseline(w, host, gpu_stats, budget_s):
     """The FP64 oracle (literal Algorithm 2) on a bounded prefix of the same
     workload: per-step cost fit a + b*j over the first Lanczos steps, then
     extrapolated to the GPU run's N_MV and sum of basis widths."""
     from oracle import cg, jsym, trlan
-    try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        blas_threads = None
+    blas_threads, phys, logical = host_cores()
     if w["kind"] == "stencil":
         U, B, L = host["U"], host["B"], w["L"]
         n = 2 * int(np.prod(L)) * 4
@@ -540,7 +553,8 @@ def cpu_baseline(w, host, gpu_stats, budget_s):
                         f"{', each with a CG solve' if w.get('invert') else ''}) of the same "
                         f"workload in {time.perf_counter() - t_start:.1f} s; per-step time fit "
                         f"{a:.3g} + {b:.3g}*j s extrapolated to the GPU run's N_MV={nmv} and "
-                        f"sum j={sum_j} (extrapolated); os.cpu_count()={os.cpu_count()}"))
+                        f"sum j={sum_j} (extrapolated); {blas_threads} BLAS threads on "
+                        f"{phys} physical cores / {logical} logical CPUs"))
 
 
 def probe(w, reps=3):
