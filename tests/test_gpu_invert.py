@@ -154,7 +154,7 @@ def test_invert_stencil_per_site_B(ctx, mixed):
 
 
 def test_invert_large_fp32_lattice(ctx):
-    """(24, 24, 16, 16): FP32 takes the one-thread-per-site kernel with the
+    """(24, 24, 16, 16): FP32 takes the plane-pair brick kernel with the
     fused CG direction.  The pairs agree with the normal mode on the GPU (its
     parity is tested against the oracle) and their residuals, checked with
     the oracle's operator, are below the tolerance."""

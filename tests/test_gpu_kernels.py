@@ -24,10 +24,14 @@ def _rel(a, b):
 
 
 # ------------------------------------------------------------------ operators
-@pytest.mark.parametrize("L", [(4, 4, 4, 4), (2, 3, 4, 5), (3, 2, 2, 7)])
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (2, 3, 4, 5), (3, 2, 2, 7), (8, 8, 16, 8), (6, 4, 16, 16),
+                               (5, 8, 8, 16)])
 @pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("b_per_site", [False, True])
 def test_stencil_apply(ctx, L, mixed, b_per_site):
+    """Three columns at once, every output.  (8, 8, 16, 8) and (6, 4, 16, 16)
+    have x0-planes of 1024 sites and an even L0, which the FP32 apply takes in
+    plane-pair bricks; (5, 8, 8, 16) has an odd L0."""
     from paper_2001_07428_amd import jlanczos as J
     say("stencil_apply", L, mixed, b_per_site)
     U, B = inputs.stencil_links(4, L, b_per_site=b_per_site)
