@@ -373,7 +373,9 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_brick(StencilArgs<S
                                                                    cplx<S>* __restrict__ pnew) {
   if (a.skip && *a.skip != 0.0) return;   // uniform over the grid
   __shared__ double sh[kStencilThreads / 64];
-  __shared__ cplx<S> xs[kStencilThreads][8];   // the 4 + 4 operand components of each thread's site
+  // the 4 + 4 operand components of each thread's site, component-major so
+  // that consecutive threads touch consecutive words
+  __shared__ cplx<S> xs[8][kStencilThreads];
   __shared__ cplx<S> us[16][kBrickS];          // U_0 of the first plane's sites
   const int64_t P = (int64_t)a.L[1] * a.L[2] * a.L[3];
   const int64_t bx = P / (8 * kBrickS), b = blockIdx.x, k = b >> 3;
@@ -396,8 +398,8 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_brick(StencilArgs<S
     xo.template site<S>(h + s * 4, br, bi);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      xs[t][r].x = ar[r]; xs[t][r].y = ai[r];
-      xs[t][4 + r].x = br[r]; xs[t][4 + r].y = bi[r];
+      xs[r][t].x = ar[r]; xs[r][t].y = ai[r];
+      xs[4 + r][t].x = br[r]; xs[4 + r][t].y = bi[r];
       top[r].re = dg * ar[r]; top[r].im = dg * ai[r];
       bot[r].re = dg * br[r]; bot[r].im = dg * bi[r];
     }
@@ -413,8 +415,8 @@ __global__ __launch_bounds__(kStencilThreads) void k_stencil_brick(StencilArgs<S
   auto from_lds = [&](int i, S ar[4], S ai[4], S br[4], S bi[4]) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      ar[r] = xs[i][r].x; ai[r] = xs[i][r].y;
-      br[r] = xs[i][4 + r].x; bi[r] = xs[i][4 + r].y;
+      ar[r] = xs[r][i].x; ai[r] = xs[r][i].y;
+      br[r] = xs[4 + r][i].x; bi[r] = xs[4 + r][i].y;
     }
   };
   {   // x0 forward: the second plane's operand from LDS
