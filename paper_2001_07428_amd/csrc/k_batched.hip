@@ -140,28 +140,33 @@ __device__ void wg_apply(const BatchProblem& pb, const cplx<S>* __restrict__ x, 
       qq.re += m11r * br + m11i * bi - m12r * ar - m12i * ai;
       qq.im += -m11r * bi + m11i * br + m12r * ai - m12i * ar;
     };
-    int64_t c = lane;
-    for (; c + (UNR - 1) * 64 < h; c += UNR * 64) {   // UNR steps' loads in flight together
+    // UNR column steps' loads in flight together, every step loaded: columns
+    // past the row's end read the last column and multiply as zero, so no
+    // lane leaves the batch for a one-load-at-a-time tail (each lane sums its
+    // columns lane, lane + 64, ... in order, whatever UNR)
+    for (int64_t cb = 0; cb < h; cb += UNR * 64) {
       cplx<S> m11[RPW][UNR], m12[RPW][UNR];
 #pragma unroll
       for (int k = 0; k < RPW; ++k)
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-          m11[k][u] = r11[k][c + 64 * u];
-          m12[k][u] = r12[k][c + 64 * u];
+          const int64_t c = cb + lane + 64 * u;
+          const int64_t cc = c < h ? c : h - 1;
+          m11[k][u] = r11[k][cc];
+          m12[k][u] = r12[k][cc];
         }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const cplx<S> a = L.sv[c + 64 * u], b = L.sv[h + c + 64 * u];
+        const int64_t c = cb + lane + 64 * u;
+        const bool in = c < h;
+        const int64_t cc = in ? c : 0;
+        const cplx<S> a = L.sv[cc], b = L.sv[h + cc];
+        const cplx<S> zero = {(S)0, (S)0};
 #pragma unroll
-        for (int k = 0; k < RPW; ++k) acc(m11[k][u], m12[k][u], a, b, p[k], q[k]);
+        for (int k = 0; k < RPW; ++k)
+          acc(in ? m11[k][u] : zero, in ? m12[k][u] : zero, a, b, p[k], q[k]);
       }
-    }
-    for (; c < h; c += 64) {
-      const cplx<S> a = L.sv[c], b = L.sv[h + c];
-#pragma unroll
-      for (int k = 0; k < RPW; ++k) acc(r11[k][c], r12[k][c], a, b, p[k], q[k]);
     }
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
@@ -202,9 +207,12 @@ __device__ void wg_apply(const BatchProblem& pb, const cplx<S>* __restrict__ x, 
 // one address), FP64 products and accumulation; the column groups are summed
 // by four butterfly steps.  r2[k] (LDS) receives the sums.  Two candidates
 // per pass keep the solver's register count (and so its occupancy) where it
-// was: four cost 50 more registers.
+// was: four cost 50 more registers.  With UR > 1 every lane issues the loads
+// of UR column steps (matrix entries and candidates) before their products,
+// the last batch padded with zero-weight columns; 512-thread workgroups,
+// whose register budget has room, take UR = 4.
 constexpr int kResRhs = 2;
-template <typename S, int NT>
+template <typename S, int NT, int UR = 1>
 __device__ void wg_resid_multi(const BatchProblem& pb, const cplx<S>* __restrict__ X, int64_t n,
                                const int* idx, const double* lamv, int nc, const Lds<S>& L,
                                double* r2) {
@@ -230,7 +238,44 @@ __device__ void wg_resid_multi(const BatchProblem& pb, const cplx<S>* __restrict
     double pr[kResRhs], pi[kResRhs], qr[kResRhs], qi[kResRhs];
 #pragma unroll
     for (int k = 0; k < kResRhs; ++k) pr[k] = pi[k] = qr[k] = qi[k] = 0.0;
-    for (int64_t c = g; c < h; c += 16) {
+    int64_t c0 = g;
+    if constexpr (UR > 1) {
+      // every column step and candidate slot is loaded: columns past the
+      // row's end read the last column and multiply as zero, slots past nc
+      // read candidate 0 and are never summed; no branch closes the batch
+      for (int64_t cb = 0; cb < h; cb += UR * 16) {
+        cplx<S> m11[UR], m12[UR], xa[UR][kResRhs], xb[UR][kResRhs];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+          const int64_t c = cb + g + 16 * u;
+          const int64_t cc = c < h ? c : h - 1;
+          m11[u] = r11[cc];
+          m12[u] = r12[cc];
+#pragma unroll
+          for (int k = 0; k < kResRhs; ++k) {
+            xa[u][k] = xk[k][cc];
+            xb[u][k] = xk[k][h + cc];
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+          const bool in = cb + g + 16 * u < h;
+          const double m11r = in ? (double)m11[u].x : 0.0, m11i = in ? (double)m11[u].y : 0.0;
+          const double m12r = in ? (double)m12[u].x : 0.0, m12i = in ? (double)m12[u].y : 0.0;
+#pragma unroll
+          for (int k = 0; k < kResRhs; ++k) {
+            const double ar = xa[u][k].x, ai = xa[u][k].y, br = xb[u][k].x, bi = xb[u][k].y;
+            pr[k] += m11r * ar - m11i * ai + m12r * br - m12i * bi;
+            pi[k] += m11r * ai + m11i * ar + m12r * bi + m12i * br;
+            qr[k] += m11r * br + m11i * bi - m12r * ar - m12i * ai;
+            qi[k] += -m11r * bi + m11i * br + m12r * ai - m12i * ar;
+          }
+        }
+      }
+      c0 = h;   // nothing left for the single-step loop
+    }
+    for (int64_t c = c0; c < h; c += 16) {
       const cplx<S> m11 = r11[c], m12 = r12[c];
       const double m11r = m11.x, m11i = m11.y, m12r = m12.x, m12i = m12.y;
 #pragma unroll
@@ -562,7 +607,7 @@ __device__ void solve_one(const BatchProblem& pg, int pid, const BatchParams& P,
       double* r2 = L.misc + 16;   // kResRhs scalars
       if (tid < nc) L.misc[1 + tid] = L.lam[L.order[c0 + tid]];   // slots 1..kResRhs
       __syncthreads();
-      wg_resid_multi<S, NT>(pb, Vn, n, L.order + c0, L.misc + 1, nc, L, r2);
+      wg_resid_multi<S, NT, (NT >= 512 ? 4 : 1)>(pb, Vn, n, L.order + c0, L.misc + 1, nc, L, r2);
       if (tid < nc) {
         const int i = L.order[c0 + tid];
         const double r = sqrt(r2[tid]);
