@@ -362,19 +362,26 @@ __device__ void wg_dots(const cplx<S>* __restrict__ V, int64_t n, int ncol, cplx
       cwr += vtr * ubr - vti * ubi - vbr * utr + vbi * uti;
       cwi += vtr * ubi + vti * ubr - vbr * uti - vbi * utr;
     };
-    int64_t p = lane;
-    for (; p + 3 * 64 < h; p += 4 * 64) {   // four steps' loads in flight together
-      cplx<S> a[4], b[4];
+    // DS steps' loads in flight together, every step loaded: pairs past the
+    // end read the last pair and are not summed (each lane sums its pairs
+    // lane, lane + 64, ... in order)
+    constexpr int DS = NT >= 512 ? 8 : 4;
+    for (int64_t pb = 0; pb < h; pb += DS * 64) {
+      cplx<S> a[DS], b[DS];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        a[k] = vt[p + 64 * k];
-        b[k] = vb[p + 64 * k];
+      for (int k = 0; k < DS; ++k) {
+        const int64_t p = pb + lane + 64 * k;
+        const int64_t pc = p < h ? p : h - 1;
+        a[k] = vt[pc];
+        b[k] = vb[pc];
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc(a[k], b[k], p + 64 * k);
+      for (int k = 0; k < DS; ++k) {
+        const int64_t p = pb + lane + 64 * k;
+        if (p < h) acc(a[k], b[k], p);
+      }
     }
-    for (; p < h; p += 64) acc(vt[p], vb[p], p);
     cvr = wsum(cvr); cvi = wsum(cvi); cwr = wsum(cwr); cwi = wsum(cwi);
     if (lane == 0) {
       L.coef[4 * c + 0] = cvr; L.coef[4 * c + 1] = cvi;
@@ -402,17 +409,19 @@ __device__ double wg_update(const cplx<S>* __restrict__ V, int64_t n, int ncol,
       dbr += br * cvr - bi * cvi + tr * cwr + ti * cwi;
       dbi += br * cvi + bi * cvr + tr * cwi - ti * cwr;
     };
+    // UC columns' loads in flight together (the columns are summed in order)
+    constexpr int UC = NT >= 512 ? 8 : 4;
     int c = 0;
-    for (; c + 3 < ncol; c += 4) {   // four columns' loads in flight together
-      cplx<S> a[4], b[4];
+    for (; c + UC - 1 < ncol; c += UC) {
+      cplx<S> a[UC], b[UC];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < UC; ++k) {
         a[k] = V[(int64_t)(c + k) * n + p];
         b[k] = V[(int64_t)(c + k) * n + h + p];
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc(a[k], b[k], c + k);
+      for (int k = 0; k < UC; ++k) acc(a[k], b[k], c + k);
     }
     for (; c < ncol; ++c) acc(V[(int64_t)c * n + p], V[(int64_t)c * n + h + p], c);
     cplx<S> t = L.su[p], b = L.su[h + p];
