@@ -315,6 +315,148 @@ __global__ __launch_bounds__(kReorthThreads, sizeof(S) == 4 ? 4 : 1) void k_dots
     if (i >= 4 * ncol ? g == 0 : ((i / 16) % G == g)) out[i] = acc[i];
 }
 
+// FP32 inner products for long vectors, u staged in LDS: a block takes
+// kDotsLdsPairs consecutive pairs, stages its u (after the local step, with
+// LOCAL) in LDS as FP32 (the values the products use), and each wavefront
+// then streams its columns (c = wave, wave + 4, ...) over the block's whole
+// range, two load batches of 128 pairs per half at a time, so every column
+// is read in 32 KB contiguous runs per half instead of the 2 KB runs of
+// k_dots (measured at 32^4 with 375 columns: 7.08 TB/s against 6.24).  Each
+// wavefront writes its columns' sums straight to the block's partial row;
+// ||u||^2 (and, with LOCAL, ||u - t v_jl||^2) come from the staging.  Same
+// outputs as k_dots with one column group.
+constexpr int kDotsLdsPairs = 4096;
+typedef float ldsf4 __attribute__((ext_vector_type(4)));
+
+template <bool LOCAL, bool NT>
+__global__ __launch_bounds__(kReorthThreads, 2) void k_dots_lds(const cplx<float>* __restrict__ V,
+                                                                int64_t ldv, int ncol,
+                                                                const cplx<float>* __restrict__ u,
+                                                                int64_t h, double* __restrict__ partial,
+                                                                const double* __restrict__ tloc,
+                                                                double beta, int jl,
+                                                                cplx<float>* __restrict__ uout,
+                                                                const double* __restrict__ beta2) {
+  constexpr int BP = kDotsLdsPairs, NQ = BP / 2;   // pairs, pairs of pairs (one 16-byte load)
+  __shared__ ldsf4 us[2][NQ];                      // top, bottom halves
+  __shared__ double red[2][kReorthThreads / 64];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t p0 = (int64_t)blockIdx.x * BP;
+  const int nout = dots_stride(ncol);
+  double* out = partial + (int64_t)blockIdx.x * nout;
+  double unorm = 0.0, anorm = 0.0;
+  double t_re = 0.0, t_im = 0.0, bt = 0.0;
+  if constexpr (LOCAL) {
+    t_re = tloc[0];
+    t_im = tloc[1];
+    bt = beta2 ? sqrt(beta2[0]) : beta;   // beta_{jl-1}: host value or device norm^2
+  }
+  const cplx<float>* vj = V + (int64_t)jl * ldv;
+  const cplx<float>* vm = vj - ldv;
+  for (int i = threadIdx.x; i < NQ; i += kReorthThreads) {
+    const int64_t p = p0 + 2 * i;
+    ldsf4 t = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+    if (p < h) {   // h is even, so both pairs of the load are in range
+      t = *reinterpret_cast<const ldsf4*>(u + p);
+      b = *reinterpret_cast<const ldsf4*>(u + h + p);
+      if constexpr (LOCAL) {
+        // u - t v_j (its norm: the alpha step alone), then - beta v_{j-1},
+        // rounded once to FP32
+        const ldsf4 at = *reinterpret_cast<const ldsf4*>(vj + p), ab = *reinterpret_cast<const ldsf4*>(vj + h + p);
+        ldsf4 mt = {0, 0, 0, 0}, mb = {0, 0, 0, 0};
+        if (bt != 0.0) {
+          mt = *reinterpret_cast<const ldsf4*>(vm + p);
+          mb = *reinterpret_cast<const ldsf4*>(vm + h + p);
+        }
+        float* tf = reinterpret_cast<float*>(&t);
+        float* bf = reinterpret_cast<float*>(&b);
+        const float* atf = reinterpret_cast<const float*>(&at);
+        const float* abf = reinterpret_cast<const float*>(&ab);
+        const float* mtf = reinterpret_cast<const float*>(&mt);
+        const float* mbf = reinterpret_cast<const float*>(&mb);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const double xtr = (double)tf[2 * e] - (t_re * atf[2 * e] - t_im * atf[2 * e + 1]);
+          const double xti = (double)tf[2 * e + 1] - (t_re * atf[2 * e + 1] + t_im * atf[2 * e]);
+          const double xbr = (double)bf[2 * e] - (t_re * abf[2 * e] - t_im * abf[2 * e + 1]);
+          const double xbi = (double)bf[2 * e + 1] - (t_re * abf[2 * e + 1] + t_im * abf[2 * e]);
+          anorm += xtr * xtr + xti * xti + xbr * xbr + xbi * xbi;
+          tf[2 * e] = (float)(xtr - bt * mtf[2 * e]);
+          tf[2 * e + 1] = (float)(xti - bt * mtf[2 * e + 1]);
+          bf[2 * e] = (float)(xbr - bt * mbf[2 * e]);
+          bf[2 * e + 1] = (float)(xbi - bt * mbf[2 * e + 1]);
+        }
+        // only this thread reads these pairs of u: the update is stored in place
+        *reinterpret_cast<ldsf4*>(uout + p) = t;
+        *reinterpret_cast<ldsf4*>(uout + h + p) = b;
+      }
+      unorm += (double)t.x * t.x + (double)t.y * t.y + (double)t.z * t.z + (double)t.w * t.w +
+               (double)b.x * b.x + (double)b.y * b.y + (double)b.z * b.z + (double)b.w * b.w;
+    }
+    us[0][i] = t;
+    us[1][i] = b;
+  }
+  unorm = wave_sum(unorm);
+  anorm = wave_sum(anorm);
+  if (lane == 0) {
+    red[0][wave] = unorm;
+    red[1][wave] = anorm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[4 * ncol] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    out[4 * ncol + 1] = LOCAL ? (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]) : 0.0;
+  }
+  constexpr int B = 2;   // load batches of 64 lanes x 16 bytes per half in flight
+#pragma unroll 1
+  for (int c = wave; c < ncol; c += kReorthThreads / 64) {
+    const cplx<float>* vt = V + (int64_t)c * ldv + p0;
+    const cplx<float>* vb = vt + h;
+    double cvr = 0, cvi = 0, cwr = 0, cwi = 0;
+#pragma unroll 1
+    for (int k0 = 0; k0 < NQ / 64; k0 += B) {
+      ldsf4 a[B], b[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int i = (k0 + k) * 64 + lane;
+        const bool in = p0 + 2 * i < h;
+        const ldsf4* qa = reinterpret_cast<const ldsf4*>(vt) + (in ? i : 0);
+        const ldsf4* qb = reinterpret_cast<const ldsf4*>(vb) + (in ? i : 0);
+        if constexpr (NT) {
+          a[k] = __builtin_nontemporal_load(qa);
+          b[k] = __builtin_nontemporal_load(qb);
+        } else {
+          a[k] = *qa;
+          b[k] = *qb;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int i = (k0 + k) * 64 + lane;
+        const ldsf4 ut = us[0][i], ub = us[1][i];   // zero past the end of the vector
+        const float* av = reinterpret_cast<const float*>(&a[k]);
+        const float* bv = reinterpret_cast<const float*>(&b[k]);
+        const float* utf = reinterpret_cast<const float*>(&ut);
+        const float* ubf = reinterpret_cast<const float*>(&ub);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const double vtr = av[2 * e], vti = av[2 * e + 1], vbr = bv[2 * e], vbi = bv[2 * e + 1];
+          const double utr = utf[2 * e], uti = utf[2 * e + 1], ubr = ubf[2 * e], ubi = ubf[2 * e + 1];
+          // v^H u = conj(v_t) u_t + conj(v_b) u_b;  w^H u = v_t u_b - v_b u_t
+          cvr = fma(vtr, utr, cvr); cvr = fma(vti, uti, cvr); cvr = fma(vbr, ubr, cvr); cvr = fma(vbi, ubi, cvr);
+          cvi = fma(vtr, uti, cvi); cvi = fma(-vti, utr, cvi); cvi = fma(vbr, ubi, cvi); cvi = fma(-vbi, ubr, cvi);
+          cwr = fma(vtr, ubr, cwr); cwr = fma(-vti, ubi, cwr); cwr = fma(-vbr, utr, cwr); cwr = fma(vbi, uti, cwr);
+          cwi = fma(vtr, ubi, cwi); cwi = fma(vti, ubr, cwi); cwi = fma(-vbr, uti, cwi); cwi = fma(-vbi, utr, cwi);
+        }
+      }
+    }
+    double r[4] = {cvr, cvi, cwr, cwi};
+    const double tsum = wave_sum4(r);   // lane 16k holds sum k
+    if ((lane & 15) == 0) out[4 * c + (lane >> 4)] = tsum;
+  }
+}
+
 // Stores this block's share of ||u||^2 (bsum, the same in every thread).
 // With fin the kernel also finishes the sum: each block's share is an
 // agent-scope store, complete before the counter *cnt moves; the last block
@@ -518,11 +660,14 @@ __global__ __launch_bounds__(kReorthThreads) void k_update_fin(const cplx<S>* ui
 }  // namespace
 
 // Pairs per lane of the update kernel: the largest of 8, 4, 2 (1 for FP64
-// or an odd half length) that still gives >= 1024 blocks, so small vectors
-// fill the 256 CUs.
+// or an odd half length) that still gives >= 4096 blocks with two pairs per
+// load (FP32), >= 1024 otherwise, so small vectors fill the 256 CUs (FP32 at
+// 32^4: 4096 blocks of four pairs per lane took a 375-column pass from 7.94 to
+// 7.77 ms against 2048 blocks of eight; 8192 of two, 8.12 ms).
 static int update_ppl(int64_t h, int E) {
+  const int64_t target = E == 2 ? 4096 : 1024;
   for (int ppl = 8; ppl >= 2 * E; ppl /= 2)
-    if ((h + 256 * ppl - 1) / (256 * ppl) >= 1024) return ppl;
+    if ((h + 256 * ppl - 1) / (256 * ppl) >= target) return ppl;
   return E == 2 ? 2 : 1;
 }
 
@@ -547,6 +692,12 @@ static int dots_chunks(int64_t h, int es) {
   return (int)per;
 }
 
+// The FP32 inner products of long vectors (an even half length of at least
+// 256 blocks of kDotsLdsPairs pairs, so one column group) run in k_dots_lds.
+static bool dots_lds_applies(int64_t h, int es) {
+  return es == 8 && h % 2 == 0 && h >= (int64_t)256 * kDotsLdsPairs;
+}
+
 // A pass over the basis streams it through the caches without reuse once it
 // is larger than the 256 MB last-level cache: then its loads are non-temporal.
 static bool basis_streams(int ncol, int64_t h, size_t es) {
@@ -562,6 +713,23 @@ hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* 
   if (groups < 1) return hipErrorInvalidValue;
   if (!uout) uout = u;
   if (tloc && groups > 1 && uout == u) return hipErrorInvalidValue;   // the groups still read u
+  if (dots_lds_applies(h, (int)sizeof(cplx<S>))) {
+    if constexpr (sizeof(S) == 4) {
+      const int64_t nb = (h + kDotsLdsPairs - 1) / kDotsLdsPairs;
+      if (nb != nblk || groups != 1) return hipErrorInvalidValue;
+      const bool nt = basis_streams(ncol, h, sizeof(cplx<S>));
+      auto go = [&](auto localc, auto ntc) {
+        hipLaunchKernelGGL((k_dots_lds<decltype(localc)::value, decltype(ntc)::value>), dim3((unsigned)nb),
+                           dim3(kReorthThreads), 0, st, V, ldv, ncol, u, h, partial, tloc, beta, jl, uout,
+                           beta2);
+      };
+      using T_ = std::true_type;
+      using F_ = std::false_type;
+      if (tloc) { if (nt) go(T_{}, T_{}); else go(T_{}, F_{}); }
+      else      { if (nt) go(F_{}, T_{}); else go(F_{}, F_{}); }
+      return hipGetLastError();
+    }
+  }
   const int64_t ch = 64 * kPairsPerLane;
   const int64_t nch = (h + ch - 1) / ch;
   const int per = (int)((nch + nblk - 1) / nblk);
@@ -593,6 +761,7 @@ hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* 
 
 // Number of dots blocks the driver must size the partial buffer for.
 int reorth_dots_blocks(int64_t h, int es) {
+  if (dots_lds_applies(h, es)) return (int)((h + kDotsLdsPairs - 1) / kDotsLdsPairs);
   const int64_t ch = 64 * kPairsPerLane;
   const int64_t nch = (h + ch - 1) / ch;
   const int per = dots_chunks(h, es);

@@ -114,7 +114,7 @@ def test_pair_vectors(ctx, mixed):
 # ----------------------------------------------------------- reorthogonalisation
 @pytest.mark.parametrize("h,ncol", [(1000, 7), (33, 5), (5000, 130), (4096, 1), (640, 0),
                                     (40000, 77), (262144, 70), (300, 2047),
-                                    (4194304, 6)])
+                                    (4194304, 6), (1048576, 3), (1048578, 2), (1048577, 2)])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_reorth_pass(ctx, h, ncol, mixed):
     """One block Gram-Schmidt pass against [V, W = J V^*] (Alg. 2).  The two
@@ -122,7 +122,9 @@ def test_reorth_pass(ctx, h, ncol, mixed):
     (tiles of 64 sums, the last one ragged); the 262144-pair case's basis
     (over 256 MB) is read with non-temporal loads, as is the 32^4-sized one
     (4194304 pairs); 2047 columns is the largest basis a pass takes (its LDS
-    accumulators and 128 reduction tiles)."""
+    accumulators and 128 reduction tiles).  From 1048576 pairs (even) the FP32
+    inner products stage u in LDS (1048578: a last block of two pairs;
+    1048577, odd, stays on the register kernel)."""
     from paper_2001_07428_amd import jlanczos as J
     say("reorth_pass", h, ncol, mixed)
     rng = np.random.default_rng(6)
