@@ -150,7 +150,9 @@ hipError_t launch_tek_resid(const TekArgs<S>& a, const cplx<S>* X, int64_t ldx, 
 // else zero) ||u - t v_jl||^2 before the beta term and the rounding.
 __host__ __device__ constexpr int dots_stride(int ncol) { return 4 * ncol + 2; }
 int reorth_dots_blocks(int64_t h, int es);   // partial rows written by dots; es: bytes per complex
-int reorth_update_blocks(int64_t h, int es);   // partial entries written by update (es: bytes per complex)
+// partial entries written by update (es: bytes per complex; jsym as for
+// launch_reorth_update, whose long FP32 vectors take other blocks without it)
+int reorth_update_blocks(int64_t h, int es, bool jsym = true);
 constexpr int kReorthMaxCols = 2048;   // largest basis dots supports
 // With tloc != nullptr the kernel first applies the local three-term step
 // u <- u - t v_jl - beta v_{jl-1} (t = tloc[0] + i tloc[1] on the device,

@@ -285,7 +285,7 @@ Layout make_layout(const jl_op_s* op, const jl_params* p) {
   L.V[1] = take((size_t)n * (m + 1) * es);
   L.apart = take(sizeof(double) * 2 * (size_t)op_apply_blocks(op));
   L.dots_part = take(sizeof(double) * (size_t)reorth_dots_blocks(h, es) * (size_t)dots_stride(m + 1));
-  L.upd_part = take(sizeof(double) * (size_t)std::max(reorth_update_blocks(h, es), 1));
+  L.upd_part = take(sizeof(double) * (size_t)std::max(reorth_update_blocks(h, es, p->standard == 0), 1));
   L.coef = take(sizeof(double) * (4 * (size_t)(m + 1) + 1));
   const int wcols = dots_stride(m + 1);   // the most inner products one pass reduces
   // the slice sums of the wide reductions: the inner products of a pass, and
@@ -501,7 +501,7 @@ jl_status solve_impl(jl_op_s* op, const jl_params* prm, const void* v1, void* ws
   unsigned* upd_cnt = wide_cnt + wtiles;
   JL_HIP(ctx, hipMemsetAsync(wide_cnt, 0, sizeof(unsigned) * ((size_t)wtiles + 1), st));
   const int napply = op_apply_blocks(op);
-  const int nupd = reorth_update_blocks(h, es);
+  const int nupd = reorth_update_blocks(h, es, jsym);
   const int64_t ldv = n;
 
   struct Ev {

@@ -114,7 +114,8 @@ def test_pair_vectors(ctx, mixed):
 # ----------------------------------------------------------- reorthogonalisation
 @pytest.mark.parametrize("h,ncol", [(1000, 7), (33, 5), (5000, 130), (4096, 1), (640, 0),
                                     (40000, 77), (262144, 70), (300, 2047),
-                                    (4194304, 6), (1048576, 3), (1048578, 2), (1048577, 2)])
+                                    (4194304, 6), (1048576, 3), (1048578, 2), (1048577, 2),
+                                    (2097152, 3), (2097154, 2)])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_reorth_pass(ctx, h, ncol, mixed):
     """One block Gram-Schmidt pass against [V, W = J V^*] (Alg. 2).  The two
@@ -124,7 +125,9 @@ def test_reorth_pass(ctx, h, ncol, mixed):
     (4194304 pairs); 2047 columns is the largest basis a pass takes (its LDS
     accumulators and 128 reduction tiles).  From 1048576 pairs (even) the FP32
     inner products stage u in LDS (1048578: a last block of two pairs;
-    1048577, odd, stays on the register kernel)."""
+    1048577, odd, stays on the register kernel); from 2097152 pairs (even) the
+    FP32 update keeps its corrections in LDS, one wavefront per 1024 pairs
+    (2097154: a last block of two pairs; 4194304 with non-temporal loads)."""
     from paper_2001_07428_amd import jlanczos as J
     say("reorth_pass", h, ncol, mixed)
     rng = np.random.default_rng(6)

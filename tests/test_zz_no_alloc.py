@@ -1,6 +1,6 @@
 """The allocation-free reorthogonalisation pass (static device scratch)
-against the workspace form of the same pass, through the C ABI: two calls in
-a row on one context, the second with a smaller input, each bit-identical to
+against the workspace form of the same pass, through the C ABI: three calls in
+a row on one context, each later one with a shorter vector, each bit-identical to
 jl_reorth_pass (same kernels, same launch shapes, same summation order)."""
 import numpy as np
 import pytest
@@ -19,8 +19,10 @@ def test_noalloc_pass_matches_workspace_pass(mixed):
     ctx = J.Context(0)
     g = torch.Generator(device="cuda:0").manual_seed(11)
     coef = torch.full((4 * 256 + 2,), np.nan, dtype=torch.float64, device="cuda:0")
-    # a pass at the largest basis width the scratch takes, then a smaller one
-    for n, ncol in ((2 * 262144, 256), (2 * 1531, 37)):
+    # a long vector (the FP32 inner products and update then keep u and the
+    # corrections in LDS; a last block of two pairs), a pass at the largest
+    # basis width the scratch takes, then a smaller one
+    for n, ncol in ((2 * (2097152 + 2), 3), (2 * 262144, 256), (2 * 1531, 37)):
         say("noalloc pass", "mixed" if mixed else "fp64", n, ncol)
         V = torch.randn((ncol, n), dtype=dt, device="cuda:0", generator=g)
         V /= torch.linalg.vector_norm(V, dim=1, keepdim=True)
