@@ -457,6 +457,124 @@ __global__ __launch_bounds__(kReorthThreads, 2) void k_dots_lds(const cplx<float
   }
 }
 
+// The same design for FP64 vectors: a 16-byte load is one complex element, so
+// a block takes kDotsLds64Pairs = 2048 pairs (64 KB of u in LDS, 32 KB runs
+// per half per column, as in FP32); the local step's arithmetic is that of
+// k_dots.
+constexpr int kDotsLds64Pairs = 2048;
+typedef double ldsd2 __attribute__((ext_vector_type(2)));
+
+template <bool LOCAL, bool NT>
+__global__ __launch_bounds__(kReorthThreads, 2) void k_dots_lds64(const cplx<double>* __restrict__ V,
+                                                                  int64_t ldv, int ncol,
+                                                                  const cplx<double>* __restrict__ u,
+                                                                  int64_t h, double* __restrict__ partial,
+                                                                  const double* __restrict__ tloc,
+                                                                  double beta, int jl,
+                                                                  cplx<double>* __restrict__ uout,
+                                                                  const double* __restrict__ beta2) {
+  constexpr int NQ = kDotsLds64Pairs;        // pairs, one 16-byte load per half each
+  __shared__ ldsd2 us[2][NQ];                // top, bottom halves
+  __shared__ double red[2][kReorthThreads / 64];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t p0 = (int64_t)blockIdx.x * NQ;
+  const int nout = dots_stride(ncol);
+  double* out = partial + (int64_t)blockIdx.x * nout;
+  double unorm = 0.0, anorm = 0.0;
+  double t_re = 0.0, t_im = 0.0, bt = 0.0;
+  if constexpr (LOCAL) {
+    t_re = tloc[0];
+    t_im = tloc[1];
+    bt = beta2 ? sqrt(beta2[0]) : beta;   // beta_{jl-1}: host value or device norm^2
+  }
+  const cplx<double>* vj = V + (int64_t)jl * ldv;
+  const cplx<double>* vm = vj - ldv;
+  for (int i = threadIdx.x; i < NQ; i += kReorthThreads) {
+    const int64_t p = p0 + i;
+    ldsd2 t = {0, 0}, b = {0, 0};
+    if (p < h) {
+      t = *reinterpret_cast<const ldsd2*>(u + p);
+      b = *reinterpret_cast<const ldsd2*>(u + h + p);
+      if constexpr (LOCAL) {
+        // u - t v_j (its norm: the alpha step alone), then - beta v_{j-1}
+        const ldsd2 at = *reinterpret_cast<const ldsd2*>(vj + p), ab = *reinterpret_cast<const ldsd2*>(vj + h + p);
+        ldsd2 mt = {0, 0}, mb = {0, 0};
+        if (bt != 0.0) {
+          mt = *reinterpret_cast<const ldsd2*>(vm + p);
+          mb = *reinterpret_cast<const ldsd2*>(vm + h + p);
+        }
+        const double xtr = t.x - (t_re * at.x - t_im * at.y);
+        const double xti = t.y - (t_re * at.y + t_im * at.x);
+        const double xbr = b.x - (t_re * ab.x - t_im * ab.y);
+        const double xbi = b.y - (t_re * ab.y + t_im * ab.x);
+        anorm += xtr * xtr + xti * xti + xbr * xbr + xbi * xbi;
+        t.x = xtr - bt * mt.x;
+        t.y = xti - bt * mt.y;
+        b.x = xbr - bt * mb.x;
+        b.y = xbi - bt * mb.y;
+        // only this thread reads these pairs of u: the update is stored in place
+        *reinterpret_cast<ldsd2*>(uout + p) = t;
+        *reinterpret_cast<ldsd2*>(uout + h + p) = b;
+      }
+      unorm += t.x * t.x + t.y * t.y + b.x * b.x + b.y * b.y;
+    }
+    us[0][i] = t;
+    us[1][i] = b;
+  }
+  unorm = wave_sum(unorm);
+  anorm = wave_sum(anorm);
+  if (lane == 0) {
+    red[0][wave] = unorm;
+    red[1][wave] = anorm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[4 * ncol] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    out[4 * ncol + 1] = LOCAL ? (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]) : 0.0;
+  }
+  constexpr int B = 2;   // load batches of 64 lanes x 16 bytes per half in flight
+#pragma unroll 1
+  for (int c = wave; c < ncol; c += kReorthThreads / 64) {
+    const cplx<double>* vt = V + (int64_t)c * ldv + p0;
+    const cplx<double>* vb = vt + h;
+    double cvr = 0, cvi = 0, cwr = 0, cwi = 0;
+#pragma unroll 1
+    for (int k0 = 0; k0 < NQ / 64; k0 += B) {
+      ldsd2 a[B], b[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int i = (k0 + k) * 64 + lane;
+        const int j = p0 + i < h ? i : 0;
+        const ldsd2* qa = reinterpret_cast<const ldsd2*>(vt) + j;
+        const ldsd2* qb = reinterpret_cast<const ldsd2*>(vb) + j;
+        if constexpr (NT) {
+          a[k] = __builtin_nontemporal_load(qa);
+          b[k] = __builtin_nontemporal_load(qb);
+        } else {
+          a[k] = *qa;
+          b[k] = *qb;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int i = (k0 + k) * 64 + lane;
+        const ldsd2 ut = us[0][i], ub = us[1][i];   // zero past the end of the vector
+        const double vtr = a[k].x, vti = a[k].y, vbr = b[k].x, vbi = b[k].y;
+        const double utr = ut.x, uti = ut.y, ubr = ub.x, ubi = ub.y;
+        // v^H u = conj(v_t) u_t + conj(v_b) u_b;  w^H u = v_t u_b - v_b u_t
+        cvr = fma(vtr, utr, cvr); cvr = fma(vti, uti, cvr); cvr = fma(vbr, ubr, cvr); cvr = fma(vbi, ubi, cvr);
+        cvi = fma(vtr, uti, cvi); cvi = fma(-vti, utr, cvi); cvi = fma(vbr, ubi, cvi); cvi = fma(-vbi, ubr, cvi);
+        cwr = fma(vtr, ubr, cwr); cwr = fma(-vti, ubi, cwr); cwr = fma(-vbr, utr, cwr); cwr = fma(vbi, uti, cwr);
+        cwi = fma(vtr, ubi, cwi); cwi = fma(vti, ubr, cwi); cwi = fma(-vbr, uti, cwi); cwi = fma(-vbi, utr, cwi);
+      }
+    }
+    double r[4] = {cvr, cvi, cwr, cwi};
+    const double tsum = wave_sum4(r);   // lane 16k holds sum k
+    if ((lane & 15) == 0) out[4 * c + (lane >> 4)] = tsum;
+  }
+}
+
 // Stores this block's share of ||u||^2 (bsum, the same in every thread).
 // With fin the kernel also finishes the sum: each block's share is an
 // agent-scope store, complete before the counter *cnt moves; the last block
@@ -827,6 +945,11 @@ static int dots_chunks(int64_t h, int es) {
 static bool dots_lds_applies(int64_t h, int es) {
   return es == 8 && h % 2 == 0 && h >= (int64_t)256 * kDotsLdsPairs;
 }
+// The FP64 inner products of vectors of at least 256 blocks of
+// kDotsLds64Pairs pairs run in k_dots_lds64.
+static bool dots_lds64_applies(int64_t h, int es) {
+  return es == 16 && h >= (int64_t)256 * kDotsLds64Pairs;
+}
 
 // A pass over the basis streams it through the caches without reuse once it
 // is larger than the 256 MB last-level cache: then its loads are non-temporal.
@@ -843,6 +966,23 @@ hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* 
   if (groups < 1) return hipErrorInvalidValue;
   if (!uout) uout = u;
   if (tloc && groups > 1 && uout == u) return hipErrorInvalidValue;   // the groups still read u
+  if (dots_lds64_applies(h, (int)sizeof(cplx<S>))) {
+    if constexpr (sizeof(S) == 8) {
+      const int64_t nb = (h + kDotsLds64Pairs - 1) / kDotsLds64Pairs;
+      if (nb != nblk || groups != 1) return hipErrorInvalidValue;
+      const bool nt = basis_streams(ncol, h, sizeof(cplx<S>));
+      auto go = [&](auto localc, auto ntc) {
+        hipLaunchKernelGGL((k_dots_lds64<decltype(localc)::value, decltype(ntc)::value>), dim3((unsigned)nb),
+                           dim3(kReorthThreads), 0, st, V, ldv, ncol, u, h, partial, tloc, beta, jl, uout,
+                           beta2);
+      };
+      using T_ = std::true_type;
+      using F_ = std::false_type;
+      if (tloc) { if (nt) go(T_{}, T_{}); else go(T_{}, F_{}); }
+      else      { if (nt) go(F_{}, T_{}); else go(F_{}, F_{}); }
+      return hipGetLastError();
+    }
+  }
   if (dots_lds_applies(h, (int)sizeof(cplx<S>))) {
     if constexpr (sizeof(S) == 4) {
       const int64_t nb = (h + kDotsLdsPairs - 1) / kDotsLdsPairs;
@@ -892,6 +1032,7 @@ hipError_t launch_reorth_dots(const cplx<S>* V, int64_t ldv, int ncol, cplx<S>* 
 // Number of dots blocks the driver must size the partial buffer for.
 int reorth_dots_blocks(int64_t h, int es) {
   if (dots_lds_applies(h, es)) return (int)((h + kDotsLdsPairs - 1) / kDotsLdsPairs);
+  if (dots_lds64_applies(h, es)) return (int)((h + kDotsLds64Pairs - 1) / kDotsLds64Pairs);
   const int64_t ch = 64 * kPairsPerLane;
   const int64_t nch = (h + ch - 1) / ch;
   const int per = dots_chunks(h, es);

@@ -167,3 +167,26 @@ def test_basis_decomposition_16_4(ctx, mixed, b0_rule):
         assert kry < 64 * us * anorm + 16 * otol * anorm
         if b0_rule == 1:
             assert out.stats["gs_passes"] > out.stats["n_mv"]
+
+
+@pytest.mark.parametrize("b0_rule", [0, 1])
+def test_basis_decomposition_fp64_long(ctx, b0_rule):
+    """As test_basis_decomposition_16_4 in FP64 on a 16^3 x 32 lattice (2^19
+    pairs, where the FP64 inner products stage u in LDS and fuse the local
+    three-term step), 20 pairs, m = 60, mwin = 30."""
+    from paper_2001_07428_amd import jlanczos as J
+    L = (16, 16, 16, 32)
+    say("basis decomposition fp64", L, "b0_rule", b0_rule)
+    U, B = inputs.stencil_links(4, L)
+    nev, m, mwin = 20, 60, 30
+    anorm = _abs_rowsum_bound(U, B)
+    op = J.jl_op_create_stencil(ctx, L, to_dev(U, cdt(False)), to_dev(B, cdt(False)))
+    for cyc in (1, 2):
+        out = J.jl_solve(op, nev, m, mwin, 1e-10, max_cycles=cyc, basis_cycle=cyc, b0_rule=b0_rule)
+        assert out.status == J.JL_NOT_CONVERGED and out.stats["cycles"] == cyc
+        orth, jorth, kry = _decomposition_errors(U, B, L, out.basis, out.T, m, [0, 1, 30, 31, 59])
+        out.basis = None
+        print(f"  iteration {cyc}: ||V^H V - I|| {orth:.2e}  ||V^T J^T V|| {jorth:.2e}  "
+              f"Krylov relation {kry:.2e}", flush=True)
+        assert orth < 1e-12 and jorth < 1e-12
+        assert kry < 64 * U64 * anorm + 16 * 1e-12 * anorm
