@@ -36,9 +36,10 @@ jl_status jl_reorth_pass(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t ncol, co
  * shares it, so calls that overlap on one GPU (other streams, other
  * contexts, other threads) race and must be ordered by the caller.  Same
  * arguments and results as jl_reorth_pass.  Errors: JL_EINVAL as
- * jl_reorth_pass, and for ncol > 256 or n beyond the scratch (more than
- * 65536 update blocks: n above about 2.7e8 in FP32); JL_EHIP if the scratch
- * could not be located on the context's device. */
+ * jl_reorth_pass, and for ncol > 256 or n beyond the scratch (FP32 with an
+ * even n / 2 and n above 16777216, or FP64 with n above 8388608, where the
+ * inner products would write more than 2048 blocks of partial sums); JL_EHIP
+ * if the scratch could not be located on the context's device. */
 jl_status jl_reorth_pass_noalloc(jl_ctx ctx, jl_dtype dtype, int64_t n, int32_t ncol,
                                  const void* V, int64_t ldv, void* u, double* coef);
 

@@ -62,8 +62,11 @@ hipError_t reorth_pass(int64_t n, int ncol, const cplx<S>* V, int64_t ldv, cplx<
 // The scratch of jl_reorth_pass_noalloc lives in a static device array (one
 // copy per GPU, held until the process ends), sized for at most
 // kNaMaxCols basis columns and kNaMaxUpdBlocks update blocks: the dots
-// partials of at most 2048 blocks (reorth_dots_blocks never exceeds it), the
-// update partials, the wide-reduction slices (at most 16) and the counters.
+// partials of at most kNaMaxDotsBlocks blocks (short vectors take at most
+// 2048 in any case; the LDS inner products of long ones take one block per
+// 4096 FP32 or 2048 FP64 pairs, so n up to 16777216 in FP32, when n / 2 is
+// even, and 8388608 in FP64), the update partials, the wide-reduction slices
+// (at most 16) and the counters.
 constexpr int kNaMaxCols = 256;
 constexpr int kNaMaxDotsBlocks = 2048;
 constexpr int kNaMaxUpdBlocks = 65536;

@@ -42,3 +42,18 @@ def test_noalloc_pass_matches_workspace_pass(mixed):
         J.jl_reorth_pass_noalloc(ctx, Vb, torch.zeros(64, dtype=dt, device="cuda:0"),
                                  torch.zeros(4 * 257 + 2, dtype=torch.float64, device="cuda:0"))
     assert e.value.status == J.JL_EINVAL
+    # the longest vector the scratch takes (norm only), then the next longer
+    # one that the long-vector inner products take: a clear error (FP32 with
+    # an even half length up to 16777216 elements, FP64 up to 8388608)
+    nmax = 16777216 if mixed else 8388608
+    u0 = torch.randn(nmax, dtype=dt, device="cuda:0", generator=g)
+    c_ws = J.jl_reorth_pass(ctx, None, u0.clone())
+    coef.fill_(np.nan)
+    J.jl_reorth_pass_noalloc(ctx, None, u0.clone(), coef)
+    torch.cuda.synchronize()
+    assert torch.equal(coef[:2], c_ws)
+    del u0
+    with pytest.raises(J.JLError) as e:
+        J.jl_reorth_pass_noalloc(ctx, None, torch.zeros(nmax + (4 if mixed else 2), dtype=dt,
+                                                         device="cuda:0"), coef)
+    assert e.value.status == J.JL_EINVAL
