@@ -127,7 +127,9 @@ def test_reorth_pass(ctx, h, ncol, mixed):
     inner products stage u in LDS (1048578: a last block of two pairs;
     1048577, odd, stays on the register kernel); from 2097152 pairs (even) the
     FP32 update keeps its corrections in LDS, one wavefront per 1024 pairs
-    (2097154: a last block of two pairs; 4194304 with non-temporal loads)."""
+    (2097154: a last block of two pairs; 4194304 with non-temporal loads).
+    From 524288 pairs the FP64 inner products stage u in LDS, 2048 pairs per
+    block (1048577: a last block of one pair)."""
     from paper_2001_07428_amd import jlanczos as J
     say("reorth_pass", h, ncol, mixed)
     rng = np.random.default_rng(6)
